@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Benchmark: batched beamforming R = W x S on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--config 2] [--prec fp32]
+
+A step is one bf_apply over the whole batch (descriptor packing and upload,
+one kernel launch), with S already resident in HBM.  The default workload
+is the full-width batch: 16384 products of 64x36 by 36x60 complex64, W from
+a pool of 64 unit-norm precoders, S normalised 256-QAM.  Three disjoint
+S/R buffer sets (2.4 GB) rotate so that the 256 MB last-level cache cannot
+serve repeated reads.
+
+Prints one JSON line: whole-job complex GFLOP/s (8 real flops per complex
+multiply-add, 8*64*60*f per product), the roofline of the apply kernel
+(kernel time from HIP events on the launch stream, algorithmic flops or
+bytes per launch), and the FP64 oracle timed on the host on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+from pathlib import Path
+
+import numpy as np
+
+ROOT = Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+from paper_1810_11451_amd import bf  # noqa: E402
+from paper_1810_11451_amd import workloads as wl  # noqa: E402
+
+METRIC = "complex GFLOP/s + %roofline for batched 64×f·f×60 beamforming; p50/p99 latency"
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3
+PEAK_LP_TFLOPS = 2500.0
+PRECS = {"fp32": bf.BF_FP32, "fp16": bf.BF_FP16, "bf16": bf.BF_BF16,
+         "fp16x2": bf.BF_FP16X2, "bf16x2": bf.BF_BF16X2}
+CONFIGS = {1: wl.config1, 2: wl.config2, 3: wl.config3, 4: wl.config4}
+KERNEL_SOURCES = ["paper_1810_11451_amd/csrc/bf_kernels.hip",
+                  "paper_1810_11451_amd/csrc/bf_internal.h"]
+
+
+def kernel_sha() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update((ROOT / p).read_bytes())
+    return h.hexdigest()[:16]
+
+
+def host_threads() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        n = os.cpu_count() or 1
+    cap = os.environ.get("OMP_NUM_THREADS")
+    if cap and cap.isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return max(1, n)
+
+
+def cpu_baseline(batch, target_s: float) -> dict:
+    """The FP64 oracle (as it stands) on a bounded sample of the workload."""
+    from oracle import oracle as orc
+    threads = host_threads()
+    rng = np.random.default_rng(12345)
+    probe = rng.choice(batch.n, size=min(batch.n, 8 * threads), replace=False)
+    t0 = time.perf_counter()
+    orc.apply(batch, items=probe, threads=threads)
+    dt = max(time.perf_counter() - t0, 1e-6)
+    n = int(min(batch.n, max(len(probe), len(probe) * target_s / dt)))
+    items = rng.choice(batch.n, size=n, replace=False)
+    t0 = time.perf_counter()
+    orc.apply(batch, items=items, threads=threads)
+    dt = time.perf_counter() - t0
+    flops = 8 * wl.M * wl.B * int(np.sum(batch.f[items].astype(np.int64)))
+    return {"value": round(flops / dt / 1e9, 3), "unit": "complex GFLOP/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{n} of the {batch.n} products of the same workload (seeded choice), "
+                      f"C FP64 triple loop, {dt:.1f} s"}
+
+
+def load_traffic(workload_key: str):
+    """HBM traffic per launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel source; else None."""
+    path = ROOT / "profiles" / "traffic.json"
+    if not path.exists():
+        return None
+    try:
+        data = json.loads(path.read_text())
+    except ValueError:
+        return None
+    entry = data.get(workload_key)
+    if not entry or entry.get("kernel_sha") != kernel_sha():
+        return None
+    return entry.get("traffic_bytes_per_launch")
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--config", type=int, default=2, choices=sorted(CONFIGS))
+    ap.add_argument("--prec", default="fp32", choices=sorted(PRECS))
+    ap.add_argument("--copies", type=int, default=3, help="disjoint S/R buffer sets rotated")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", action="store_true", help="tune the variant before timing")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the products are "
+              "independent and this library has no multi-GPU path (sharding is by item, see the "
+              "design notes).", file=sys.stderr)
+        return 2
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        return 1
+    from paper_1810_11451_amd.device import DeviceBatch
+
+    torch.cuda.set_device(0)
+    prec = PRECS[args.prec]
+    batch = CONFIGS[args.config]()
+    print(f"[bench] config {args.config}: {batch.name}, prec {args.prec}", file=sys.stderr, flush=True)
+    plan = bf.bf_plan_create(batch.W, bf.BF_PREC_BIT(prec))
+    db = DeviceBatch(batch, copies=args.copies, fill_r=None)
+    stream = torch.cuda.current_stream()
+    tuned = None
+    if args.autotune:
+        tuned = bf.bf_autotune(plan, batch.w_ids, batch.f, db.s_ptrs[0], db.r_ptrs[0], prec, reps=5)
+    variant = bf.bf_get_variant(plan, prec, bf.bf_f_bucket(int(batch.f.max())))
+
+    for i in range(args.warmup):
+        db.apply(plan, prec, copy=i % args.copies)
+    torch.cuda.synchronize()
+
+    K = args.steps
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    if torch.distributed.is_available() and torch.distributed.is_initialized():
+        torch.distributed.barrier()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(K):
+        ev[i][0].record(stream)
+        db.apply(plan, prec, copy=i % args.copies)
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    if torch.distributed.is_available() and torch.distributed.is_initialized():
+        torch.distributed.barrier()
+    wall = t1 - t0
+    kern_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    kern_s = float(np.mean(kern_ms)) / 1e3
+
+    flops = batch.flops()
+    nbytes = batch.bytes_moved()
+    value = flops * K / wall / 1e9
+    ai = flops / nbytes
+    lp = prec != bf.BF_FP32
+    peak_flops = (PEAK_LP_TFLOPS if lp else PEAK_FP32_TFLOPS) * 1e12
+    ridge = peak_flops / (PEAK_HBM_GBS * 1e9)
+    key = f"config{args.config}-{args.prec}"
+    traffic = load_traffic(key)
+    if ai >= ridge:
+        ach = flops / kern_s / 1e12
+        roof = {"bound": "mfma", "achieved": round(ach, 2), "peak": peak_flops / 1e12,
+                "unit": "TFLOP/s", "frac": round(ach / (peak_flops / 1e12), 4)}
+    else:
+        ach = nbytes / kern_s / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(ach / PEAK_HBM_GBS, 4)}
+    roof["traffic"] = traffic
+    roof["kernel"] = "apply_fp32_kernel" if not lp else "apply_lp_kernel"
+    roof["kernel_us_mean"] = round(kern_s * 1e6, 2)
+    roof["algorithmic"] = {"flops_per_launch": flops, "bytes_per_launch": nbytes,
+                           "ai_flop_per_byte": round(ai, 2)}
+    roof["hbm_gbs_equiv"] = round(nbytes / kern_s / 1e9, 1)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "complex GFLOP/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / K * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp16": "f16", "bf16": "bf16", "fp16x2": "f16x2",
+                  "bf16x2": "bf16x2"}[args.prec],
+        "data": "synthetic",
+        "config": {"workload": batch.name, "n_products": batch.n, "n_w": batch.n_w,
+                   "f": int(batch.f.max()) if batch.f.min() == batch.f.max() else "U{1..36}",
+                   "prec": args.prec, "variant": {"schedule": variant[0], "wg_per_cu": variant[1],
+                                                  "order": variant[2]},
+                   "buffer_sets": args.copies},
+        "latency_us": {"p50": round(float(np.percentile(kern_ms, 50)) * 1e3, 2),
+                       "p99": round(float(np.percentile(kern_ms, 99)) * 1e3, 2)},
+        "roofline": roof,
+    }
+    if tuned is not None:
+        out["config"]["autotuned_us"] = round(tuned[1], 2)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(batch, args.cpu_seconds)
+    plan.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,328 @@
+"""Python binding of libbf (the C ABI in include/bf.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libbf.so.  Function names match the C entry points.  Device
+buffers may be given as torch tensors (anything with ``data_ptr()``) or as
+integer addresses; streams as ``torch.cuda.Stream``, a raw ``hipStream_t``
+integer, or None (torch's current stream when torch has a GPU, else the
+default stream).
+
+There is no fallback: if libbf.so is missing or fails to load, every call
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+from pathlib import Path
+
+import numpy as np
+
+LIB_PATH = Path(__file__).resolve().with_name("libbf.so")
+
+BF_M, BF_B, BF_FMAX = 64, 60, 36
+BF_OK, BF_ERR_INVALID, BF_ERR_OOM, BF_ERR_DEVICE = 0, -1, -2, -3
+BF_ERR_BUSY, BF_ERR_TIMEOUT, BF_ERR_UNSUPPORTED = -4, -5, -6
+BF_FP32, BF_FP16, BF_BF16, BF_FP16X2, BF_BF16X2 = 0, 1, 2, 3, 4
+PREC_NAMES = {BF_FP32: "fp32", BF_FP16: "fp16", BF_BF16: "bf16",
+              BF_FP16X2: "fp16x2", BF_BF16X2: "bf16x2"}
+PREC_ALL = 0x1F
+
+
+def BF_PREC_BIT(p: int) -> int:
+    return 1 << int(p)
+
+
+class BfError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: {status_name(status)} ({detail})")
+        self.status = status
+        self.detail = detail
+
+
+class bf_variant(ctypes.Structure):
+    _fields_ = [("schedule", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.schedule, self.wg_per_cu, self.order)
+
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_u32 = ctypes.c_uint32
+_SIGS = {
+    "bf_plan_create": (_i32, [ctypes.POINTER(_vp), _vp, _i32, _i32, _u32, _vp]),
+    "bf_plan_destroy": (_i32, [_vp]),
+    "bf_plan_info": (_i32, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_u32)]),
+    "bf_apply": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _i32, _vp]),
+    "bf_apply_packed": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _i32, _vp]),
+    "bf_check_batch": (_i32, [_i32, _i32, _i32, _vp, _vp, _vp, _vp]),
+    "bf_graph_create": (_i32, [ctypes.POINTER(_vp), _vp, _i32, _vp, _vp, _vp, _vp, _i32, _vp]),
+    "bf_graph_launch": (_i32, [_vp, _vp]),
+    "bf_graph_destroy": (_i32, [_vp]),
+    "bf_set_variant": (_i32, [_vp, _i32, _i32, ctypes.POINTER(bf_variant)]),
+    "bf_get_variant": (_i32, [_vp, _i32, _i32, ctypes.POINTER(bf_variant)]),
+    "bf_f_bucket": (_i32, [_i32]),
+    "bf_autotune": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _i32, _i32, _vp,
+                           ctypes.POINTER(bf_variant), ctypes.POINTER(ctypes.c_float)]),
+    "bf_tune_save": (_i32, [_vp, ctypes.c_char_p]),
+    "bf_tune_load": (_i32, [_vp, ctypes.c_char_p]),
+    "bf_status_str": (ctypes.c_char_p, [_i32]),
+    "bf_last_error": (ctypes.c_char_p, []),
+    "bf_build_info": (ctypes.c_char_p, []),
+    "bf_device_cu_count": (_i32, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libbf.so (once).  Raises if it is not built."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1810_11451_amd.build`. "
+                               "The beamforming path has no CPU fallback.")
+        L = ctypes.CDLL(str(LIB_PATH))
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_name(s: int) -> str:
+    try:
+        return lib().bf_status_str(int(s)).decode()
+    except Exception:  # pragma: no cover - library not loadable
+        return str(s)
+
+
+def bf_last_error() -> str:
+    return lib().bf_last_error().decode()
+
+
+def bf_status_str(s: int) -> str:
+    return lib().bf_status_str(int(s)).decode()
+
+
+def bf_build_info() -> str:
+    return lib().bf_build_info().decode()
+
+
+def _check(rc: int, where: str) -> int:
+    if rc < 0:
+        raise BfError(rc, where, bf_last_error())
+    return rc
+
+
+def _ptr(x) -> int:
+    if x is None:
+        return 0
+    if isinstance(x, (int, np.integer)):
+        return int(x)
+    if hasattr(x, "data_ptr"):
+        return int(x.data_ptr())
+    if isinstance(x, np.ndarray):
+        return int(x.ctypes.data)
+    raise TypeError(f"cannot take a device address of {type(x)}")
+
+
+def _stream(s) -> int:
+    if s is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return int(torch.cuda.current_stream().cuda_stream)
+        except Exception:  # pragma: no cover
+            pass
+        return 0
+    if isinstance(s, (int, np.integer)):
+        return int(s)
+    if hasattr(s, "cuda_stream"):
+        return int(s.cuda_stream)
+    raise TypeError(f"not a stream: {type(s)}")
+
+
+def _i32_array(a, n=None) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(a), dtype=np.int32)
+    if n is not None and a.shape != (n,):
+        raise ValueError(f"expected {n} entries, got shape {a.shape}")
+    return a
+
+
+def _ptr_array(ptrs, n) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray([_ptr(p) for p in ptrs] if not isinstance(ptrs, np.ndarray)
+                                        else ptrs, dtype=np.uint64))
+    if a.shape != (n,):
+        raise ValueError(f"expected {n} pointers, got shape {a.shape}")
+    return a
+
+
+class Plan:
+    """Owns a bf_plan handle; destroyed with bf_plan_destroy on close()."""
+
+    def __init__(self, handle: int, n_w: int, f_max: int, mask: int):
+        self.handle = handle
+        self.n_w = n_w
+        self.f_max = f_max
+        self.mask = mask
+
+    def close(self):
+        if self.handle:
+            _check(lib().bf_plan_destroy(self.handle), "bf_plan_destroy")
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):  # pragma: no cover - best effort
+        try:
+            if self.handle:
+                lib().bf_plan_destroy(self.handle)
+        except Exception:
+            pass
+
+
+def bf_plan_create(w_pool: np.ndarray, prec_mask: int = 0, stream=None) -> Plan:
+    w = np.ascontiguousarray(w_pool, dtype=np.complex64)
+    if w.ndim != 3 or w.shape[1] != BF_M:
+        raise ValueError(f"w_pool must be [n_w, 64, f_max], got {w.shape}")
+    h = _vp()
+    _check(lib().bf_plan_create(ctypes.byref(h), w.ctypes.data, w.shape[0], w.shape[2],
+                                int(prec_mask), _stream(stream)), "bf_plan_create")
+    return Plan(h.value, w.shape[0], w.shape[2], int(prec_mask) or 1)
+
+
+def bf_plan_destroy(plan: Plan) -> None:
+    plan.close()
+
+
+def bf_plan_info(plan: Plan):
+    n_w, f_max, mask = _i32(), _i32(), _u32()
+    _check(lib().bf_plan_info(plan.handle, ctypes.byref(n_w), ctypes.byref(f_max),
+                              ctypes.byref(mask)), "bf_plan_info")
+    return n_w.value, f_max.value, mask.value
+
+
+def bf_apply(plan: Plan, w_ids, f, S_ptrs, R_ptrs, prec: int = BF_FP32, stream=None) -> None:
+    w_ids = _i32_array(w_ids)
+    n = w_ids.shape[0]
+    f = _i32_array(f, n)
+    S = _ptr_array(S_ptrs, n)
+    R = _ptr_array(R_ptrs, n)
+    _check(lib().bf_apply(plan.handle, n, w_ids.ctypes.data, f.ctypes.data, S.ctypes.data,
+                          R.ctypes.data, int(prec), _stream(stream)), "bf_apply")
+
+
+def bf_apply_packed(plan: Plan, w_ids, f, S_base, s_off, R_base, prec: int = BF_FP32,
+                    stream=None) -> None:
+    w_ids = _i32_array(w_ids)
+    n = w_ids.shape[0]
+    f = _i32_array(f, n)
+    s_off = np.ascontiguousarray(np.asarray(s_off), dtype=np.int64)
+    if s_off.shape != (n,):
+        raise ValueError("s_off must have one entry per item")
+    _check(lib().bf_apply_packed(plan.handle, n, w_ids.ctypes.data, f.ctypes.data, _ptr(S_base),
+                                 s_off.ctypes.data, _ptr(R_base), int(prec), _stream(stream)),
+           "bf_apply_packed")
+
+
+def bf_check_batch(n_w: int, f_max: int, w_ids, f, S_ptrs, R_ptrs) -> int:
+    """Host-only check; returns the bf_status (does not raise)."""
+    w_ids = _i32_array(w_ids)
+    n = w_ids.shape[0]
+    f = _i32_array(f, n)
+    S = _ptr_array(S_ptrs, n)
+    R = _ptr_array(R_ptrs, n)
+    return int(lib().bf_check_batch(n_w, f_max, n, w_ids.ctypes.data, f.ctypes.data,
+                                    S.ctypes.data, R.ctypes.data))
+
+
+class Graph:
+    def __init__(self, handle: int):
+        self.handle = handle
+
+    def close(self):
+        if self.handle:
+            _check(lib().bf_graph_destroy(self.handle), "bf_graph_destroy")
+            self.handle = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            if self.handle:
+                lib().bf_graph_destroy(self.handle)
+        except Exception:
+            pass
+
+
+def bf_graph_create(plan: Plan, w_ids, f, S_ptrs, R_ptrs, prec: int = BF_FP32,
+                    stream=None) -> Graph:
+    w_ids = _i32_array(w_ids)
+    n = w_ids.shape[0]
+    f = _i32_array(f, n)
+    S = _ptr_array(S_ptrs, n)
+    R = _ptr_array(R_ptrs, n)
+    h = _vp()
+    _check(lib().bf_graph_create(ctypes.byref(h), plan.handle, n, w_ids.ctypes.data, f.ctypes.data,
+                                 S.ctypes.data, R.ctypes.data, int(prec), _stream(stream)),
+           "bf_graph_create")
+    return Graph(h.value)
+
+
+def bf_graph_launch(graph: Graph, stream=None) -> None:
+    _check(lib().bf_graph_launch(graph.handle, _stream(stream)), "bf_graph_launch")
+
+
+def bf_graph_destroy(graph: Graph) -> None:
+    graph.close()
+
+
+def bf_f_bucket(f: int) -> int:
+    return int(lib().bf_f_bucket(int(f)))
+
+
+def bf_set_variant(plan: Plan, prec: int, bucket: int, schedule: int, wg_per_cu: int = 0,
+                   order: int = 1) -> None:
+    v = bf_variant(schedule, wg_per_cu, order, 0)
+    _check(lib().bf_set_variant(plan.handle, int(prec), int(bucket), ctypes.byref(v)),
+           "bf_set_variant")
+
+
+def bf_get_variant(plan: Plan, prec: int, bucket: int):
+    v = bf_variant()
+    _check(lib().bf_get_variant(plan.handle, int(prec), int(bucket), ctypes.byref(v)),
+           "bf_get_variant")
+    return v.as_tuple()
+
+
+def bf_autotune(plan: Plan, w_ids, f, S_ptrs, R_ptrs, prec: int = BF_FP32, reps: int = 5,
+                stream=None):
+    w_ids = _i32_array(w_ids)
+    n = w_ids.shape[0]
+    f = _i32_array(f, n)
+    S = _ptr_array(S_ptrs, n)
+    R = _ptr_array(R_ptrs, n)
+    best = bf_variant()
+    us = ctypes.c_float()
+    _check(lib().bf_autotune(plan.handle, n, w_ids.ctypes.data, f.ctypes.data, S.ctypes.data,
+                             R.ctypes.data, int(prec), int(reps), _stream(stream),
+                             ctypes.byref(best), ctypes.byref(us)), "bf_autotune")
+    return best.as_tuple(), float(us.value)
+
+
+def bf_tune_save(plan: Plan, path: str) -> None:
+    _check(lib().bf_tune_save(plan.handle, str(path).encode()), "bf_tune_save")
+
+
+def bf_tune_load(plan: Plan, path: str) -> None:
+    _check(lib().bf_tune_load(plan.handle, str(path).encode()), "bf_tune_load")
+
+
+def bf_device_cu_count() -> int:
+    return _check(lib().bf_device_cu_count(), "bf_device_cu_count")

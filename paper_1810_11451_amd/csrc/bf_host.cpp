@@ -1,0 +1,778 @@
+// Host side of libbf: the C ABI declared in include/bf.h.
+//
+// plan   : W pool upload and plan-time operand layouts (W is constant).
+// apply  : all-or-nothing argument check, descriptor packing into a pinned
+//          staging ring, one H2D copy and one kernel launch per batch.
+// graph  : descriptors uploaded once, persistent kernel captured in a
+//          hipGraph for replay.
+// tuning : variant table per (precision, f bucket), autotuner, text cache.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "bf_internal.h"
+#include "bf_host.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+}  // namespace
+
+bf_status bf_fail(bf_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// Argument checks (host only).
+
+static inline bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+static inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+extern "C" bf_status bf_check_batch(int32_t n_w, int32_t f_max, int32_t batch,
+                                    const int32_t *w_ids, const int32_t *f, const void *const *S,
+                                    void *const *R)
+{
+    if (batch < 0)
+        return bf_fail(BF_ERR_INVALID, "batch %d < 0", batch);
+    if (batch == 0)
+        return BF_OK;
+    if (!w_ids || !f || !S || !R)
+        return bf_fail(BF_ERR_INVALID, "null array argument");
+    for (int32_t t = 0; t < batch; ++t) {
+        if (w_ids[t] < 0 || w_ids[t] >= n_w)
+            return bf_fail(BF_ERR_INVALID, "item %d: w_id %d outside [0, %d)", t, w_ids[t], n_w);
+        if (f[t] < 0 || f[t] > f_max)
+            return bf_fail(BF_ERR_INVALID, "item %d: f %d outside [0, %d]", t, f[t], f_max);
+        if (!R[t] || !aligned8(R[t]))
+            return bf_fail(BF_ERR_INVALID, "item %d: R pointer null or not 8-byte aligned", t);
+        if (f[t] > 0 && (!S[t] || !aligned8(S[t])))
+            return bf_fail(BF_ERR_INVALID, "item %d: S pointer null or not 8-byte aligned", t);
+    }
+    return BF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Plan.
+
+static void release_slot(StagingSlot &s)
+{
+    if (s.ev)
+        (void)hipEventSynchronize(s.ev);
+    if (s.host)
+        (void)hipHostFree(s.host);
+    if (s.dev)
+        (void)hipFree(s.dev);
+    if (s.ev)
+        (void)hipEventDestroy(s.ev);
+    if (s.copied)
+        (void)hipEventDestroy(s.copied);
+    s = StagingSlot{};
+}
+
+static bf_status default_variants(bf_plan p)
+{
+    for (int pr = 0; pr < kPrecCount; ++pr)
+        for (int b = 0; b < kBucketCount; ++b) {
+            bf_variant v{};
+            v.schedule = 1;
+            v.wg_per_cu = 0;   // 0: the kernel's occupancy
+            v.order = 1;
+            p->table[pr][b] = v;
+        }
+    return BF_OK;
+}
+
+extern "C" bf_status bf_plan_create(bf_plan *out, const void *w_pool, int32_t n_w, int32_t f_max,
+                                    uint32_t prec_mask, void *hip_stream)
+{
+    if (!out)
+        return bf_fail(BF_ERR_INVALID, "out is null");
+    *out = nullptr;
+    if (!w_pool)
+        return bf_fail(BF_ERR_INVALID, "w_pool is null");
+    if (n_w < 1)
+        return bf_fail(BF_ERR_INVALID, "n_w %d < 1", n_w);
+    if (f_max < 0 || f_max > BF_FMAX)
+        return bf_fail(BF_ERR_INVALID, "f_max %d outside [0, %d]", f_max, BF_FMAX);
+    if (prec_mask == 0)
+        prec_mask = BF_PREC_BIT(BF_FP32);
+    if (prec_mask & ~BF_PREC_ALL)
+        return bf_fail(BF_ERR_INVALID, "unknown precision bits 0x%x", prec_mask);
+    if (prec_mask & ~kSupportedMask)
+        return bf_fail(BF_ERR_UNSUPPORTED, "precision form not built in this library (mask 0x%x)",
+                       prec_mask);
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+
+    bf_plan p = new (std::nothrow) bf_plan_s();
+    if (!p)
+        return bf_fail(BF_ERR_OOM, "plan allocation");
+    p->n_w = n_w;
+    p->f_max = f_max;
+    p->mask = prec_mask;
+    p->pairs = (f_max + 1) / 2;
+    default_variants(p);
+
+    auto fail_dev = [&](const char *what, hipError_t e) {
+        bf_status s = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? BF_ERR_OOM
+                                                                                   : BF_ERR_DEVICE;
+        bf_plan_destroy(p);
+        return bf_fail(s, "%s: %s", what, hipGetErrorString(e));
+    };
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess)
+        return fail_dev("hipGetDevice", e);
+    int cus = 0;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
+    if (e != hipSuccess)
+        return fail_dev("hipDeviceGetAttribute", e);
+    p->n_cu = cus > 0 ? cus : 1;
+    e = hipStreamCreateWithFlags(&p->copy_stream, hipStreamNonBlocking);
+    if (e != hipSuccess)
+        return fail_dev("hipStreamCreate(copy)", e);
+
+    const size_t w_bytes = (size_t)n_w * BF_M * f_max * sizeof(float2);
+    float2 *w_dev = nullptr;
+    if (w_bytes) {
+        e = hipMalloc(&w_dev, w_bytes);
+        if (e != hipSuccess)
+            return fail_dev("hipMalloc(W staging)", e);
+        e = hipMemcpyAsync(w_dev, w_pool, w_bytes, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) {
+            (void)hipFree(w_dev);
+            return fail_dev("hipMemcpyAsync(W)", e);
+        }
+    }
+    if (prec_mask & BF_PREC_BIT(BF_FP32)) {
+        p->a_fp32_stride = bfk::fp32_w_stride(p->pairs);
+        const size_t bytes = std::max<size_t>(1, (size_t)n_w * p->a_fp32_stride * sizeof(float2));
+        e = hipMalloc(&p->a_fp32, bytes);
+        if (e == hipSuccess && p->pairs > 0)
+            e = bfk::launch_w_transform_fp32(w_dev, n_w, f_max, p->a_fp32, p->pairs, st);
+        if (e != hipSuccess) {
+            if (w_dev)
+                (void)hipFree(w_dev);
+            return fail_dev("FP32 W layout", e);
+        }
+    }
+    e = hipStreamSynchronize(st);
+    if (w_dev)
+        (void)hipFree(w_dev);
+    if (e != hipSuccess)
+        return fail_dev("hipStreamSynchronize(plan)", e);
+    *out = p;
+    return BF_OK;
+}
+
+extern "C" bf_status bf_plan_destroy(bf_plan p)
+{
+    if (!p)
+        return bf_fail(BF_ERR_INVALID, "plan is null");
+    {
+        std::lock_guard<std::mutex> lk(p->mu);
+        for (auto &s : p->ring)
+            release_slot(s);
+    }
+    if (p->a_fp32)
+        (void)hipFree(p->a_fp32);
+    if (p->copy_stream)
+        (void)hipStreamDestroy(p->copy_stream);
+    delete p;
+    return BF_OK;
+}
+
+extern "C" bf_status bf_plan_info(bf_plan p, int32_t *n_w, int32_t *f_max, uint32_t *mask)
+{
+    if (!p)
+        return bf_fail(BF_ERR_INVALID, "plan is null");
+    if (n_w)
+        *n_w = p->n_w;
+    if (f_max)
+        *f_max = p->f_max;
+    if (mask)
+        *mask = p->mask;
+    return BF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Descriptor packing.
+
+extern "C" int32_t bf_f_bucket(int32_t f)
+{
+    if (f <= 0)
+        return 0;
+    const int32_t b = f / 9;
+    return b < kBucketCount ? b : kBucketCount - 1;
+}
+
+// Orders items longest f first and, for equal f, by W id (so that a
+// persistent workgroup keeps its W operands across consecutive items).
+// Two stable counting sorts: by W id, then by f descending.
+void order_items(const BfItem *in, BfItem *out, int n, int n_w, std::vector<int> &scratch)
+{
+    std::vector<BfItem> tmp(in, in + n);
+    scratch.assign((size_t)std::max(n_w, BF_FMAX + 1) + 1, 0);
+    for (int t = 0; t < n; ++t)
+        scratch[(size_t)tmp[t].w_id + 1]++;
+    for (int k = 0; k < n_w; ++k)
+        scratch[(size_t)k + 1] += scratch[(size_t)k];
+    std::vector<BfItem> by_w((size_t)n);
+    for (int t = 0; t < n; ++t)
+        by_w[(size_t)scratch[(size_t)tmp[t].w_id]++] = tmp[t];
+    int cnt[BF_FMAX + 2] = {0};
+    for (int t = 0; t < n; ++t)
+        cnt[BF_FMAX - by_w[(size_t)t].f + 1]++;
+    for (int k = 0; k <= BF_FMAX; ++k)
+        cnt[k + 1] += cnt[k];
+    for (int t = 0; t < n; ++t)
+        out[cnt[BF_FMAX - by_w[(size_t)t].f]++] = by_w[(size_t)t];
+}
+
+bfk::LaunchCfg choose_launch(bf_plan p, bf_prec prec, int n, int max_f, bool vec16,
+                             const bf_variant *force)
+{
+    const bf_variant v = force ? *force : p->table[prec][bf_f_bucket(max_f)];
+    bfk::LaunchCfg cfg{};
+    cfg.prec = prec;
+    cfg.schedule = v.schedule;
+    cfg.vec16 = vec16;
+    if (v.schedule == 0) {
+        cfg.grid = n;
+    } else {
+        const int occ = bfk::apply_occupancy(prec, 1, vec16);
+        const int per_cu = v.wg_per_cu > 0 ? v.wg_per_cu : occ;
+        const long g = (long)per_cu * p->n_cu;
+        cfg.grid = (int)std::min<long>(g, n);
+    }
+    return cfg;
+}
+
+static bf_status ensure_slot(StagingSlot &s, size_t bytes)
+{
+    if (s.ev) {
+        hipError_t e = hipEventSynchronize(s.ev);
+        if (e != hipSuccess)
+            return bf_fail(BF_ERR_DEVICE, "hipEventSynchronize(staging): %s", hipGetErrorString(e));
+    } else {
+        hipError_t e = hipEventCreateWithFlags(&s.ev, hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&s.copied, hipEventDisableTiming);
+        if (e != hipSuccess)
+            return bf_fail(BF_ERR_DEVICE, "hipEventCreate: %s", hipGetErrorString(e));
+    }
+    if (s.cap >= bytes)
+        return BF_OK;
+    size_t cap = std::max<size_t>(bytes, 64 * 1024);
+    cap = std::max(cap, s.cap * 2);
+    if (s.host)
+        (void)hipHostFree(s.host);
+    if (s.dev)
+        (void)hipFree(s.dev);
+    s.host = nullptr;
+    s.dev = nullptr;
+    s.cap = 0;
+    if (hipHostMalloc(&s.host, cap, hipHostMallocDefault) != hipSuccess)
+        return bf_fail(BF_ERR_OOM, "pinned staging of %zu bytes", cap);
+    if (hipMalloc(&s.dev, cap) != hipSuccess) {
+        (void)hipHostFree(s.host);
+        s.host = nullptr;
+        return bf_fail(BF_ERR_OOM, "device staging of %zu bytes", cap);
+    }
+    s.cap = cap;
+    return BF_OK;
+}
+
+// Common tail of bf_apply / bf_apply_packed / the serving batcher: items
+// are already validated and written by `fill` into host memory.
+bf_status enqueue_items(bf_plan p, bf_prec prec, int n, const FillFn &fill, hipStream_t st,
+                        const bf_variant *force, int *grid_out)
+{
+    if (n == 0)
+        return BF_OK;
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (p->ring.empty())
+        p->ring.resize(kRingSlots);
+    StagingSlot &slot = p->ring[p->ring_next];
+    p->ring_next = (p->ring_next + 1) % p->ring.size();
+    const size_t bytes = sizeof(BfHeader) + (size_t)n * sizeof(BfItem);
+    bf_status s = ensure_slot(slot, bytes);
+    if (s != BF_OK)
+        return s;
+
+    BfHeader *hdr = static_cast<BfHeader *>(slot.host);
+    std::memset(hdr, 0, sizeof *hdr);
+    hdr->n_items = (uint32_t)n;
+    BfItem *items = reinterpret_cast<BfItem *>(hdr + 1);
+    const FillStats fs = fill(items);
+    const int max_f = fs.max_f;
+    const bool vec16 = fs.vec16;
+    bf_variant chosen = force ? *force : p->table[prec][bf_f_bucket(max_f)];
+    if (chosen.order == 1 && n > 1) {
+        p->sort_tmp.resize((size_t)n);
+        order_items(items, p->sort_tmp.data(), n, p->n_w, p->sort_scratch);
+        std::memcpy(items, p->sort_tmp.data(), (size_t)n * sizeof(BfItem));
+    }
+    bfk::LaunchCfg cfg = choose_launch(p, prec, n, max_f, vec16, &chosen);
+    if (grid_out)
+        *grid_out = cfg.grid;
+
+    // The slot's previous launch has finished (ensure_slot waited for it), so
+    // the upload may run on the copy stream while the caller's stream is
+    // still busy with earlier work; the launch waits only for the upload.
+    hipError_t e = hipMemcpyAsync(slot.dev, slot.host, bytes, hipMemcpyHostToDevice,
+                                  p->copy_stream);
+    if (e != hipSuccess)
+        return bf_fail(BF_ERR_DEVICE, "hipMemcpyAsync(descriptors): %s", hipGetErrorString(e));
+    e = hipEventRecord(slot.copied, p->copy_stream);
+    if (e == hipSuccess)
+        e = hipStreamWaitEvent(st, slot.copied, 0);
+    if (e != hipSuccess)
+        return bf_fail(BF_ERR_DEVICE, "descriptor upload ordering: %s", hipGetErrorString(e));
+    e = launch_for_plan(p, cfg, static_cast<BfHeader *>(slot.dev), n, st);
+    if (e != hipSuccess)
+        return bf_fail(BF_ERR_DEVICE, "kernel launch: %s", hipGetErrorString(e));
+    e = hipEventRecord(slot.ev, st);
+    if (e != hipSuccess)
+        return bf_fail(BF_ERR_DEVICE, "hipEventRecord: %s", hipGetErrorString(e));
+    return BF_OK;
+}
+
+hipError_t launch_for_plan(bf_plan p, const bfk::LaunchCfg &cfg, BfHeader *blk, int n,
+                           hipStream_t st)
+{
+    const void *a = nullptr;
+    size_t stride = 0;
+    const float *scale = nullptr;
+    switch (cfg.prec) {
+    case BF_FP32:
+        a = p->a_fp32;
+        stride = p->a_fp32_stride;
+        break;
+    default:
+        return hipErrorNotSupported;
+    }
+    return bfk::launch_apply(cfg, blk, n, a, stride, p->pairs, scale, st);
+}
+
+static bf_status check_plan_prec(bf_plan p, bf_prec prec)
+{
+    if (!p)
+        return bf_fail(BF_ERR_INVALID, "plan is null");
+    if ((int)prec < 0 || (int)prec >= kPrecCount)
+        return bf_fail(BF_ERR_INVALID, "unknown precision %d", (int)prec);
+    if (!(p->mask & BF_PREC_BIT(prec)))
+        return bf_fail(BF_ERR_UNSUPPORTED, "precision %d not prepared by this plan", (int)prec);
+    return BF_OK;
+}
+
+extern "C" bf_status bf_apply(bf_plan p, int32_t batch, const int32_t *w_ids, const int32_t *f,
+                              const void *const *S, void *const *R, bf_prec prec, void *hip_stream)
+{
+    bf_status s = check_plan_prec(p, prec);
+    if (s != BF_OK)
+        return s;
+    s = bf_check_batch(p->n_w, p->f_max, batch, w_ids, f, S, R);
+    if (s != BF_OK || batch == 0)
+        return s;
+    FillFn fill = [&](BfItem *items) {
+        FillStats fs{0, true};
+        for (int32_t t = 0; t < batch; ++t) {
+            BfItem &it = items[t];
+            it.S = static_cast<const float2 *>(S[t]);
+            it.R = static_cast<float2 *>(R[t]);
+            it.w_id = w_ids[t];
+            it.f = f[t];
+            it.pad0 = it.pad1 = 0;
+            fs.max_f = std::max(fs.max_f, (int)f[t]);
+            if (f[t] > 0 && !aligned16(S[t]))
+                fs.vec16 = false;
+        }
+        return fs;
+    };
+    return enqueue_items(p, prec, batch, fill, static_cast<hipStream_t>(hip_stream), nullptr,
+                         nullptr);
+}
+
+extern "C" bf_status bf_apply_packed(bf_plan p, int32_t batch, const int32_t *w_ids,
+                                     const int32_t *f, const void *S_base, const int64_t *s_off,
+                                     void *R_base, bf_prec prec, void *hip_stream)
+{
+    bf_status s = check_plan_prec(p, prec);
+    if (s != BF_OK)
+        return s;
+    if (batch < 0)
+        return bf_fail(BF_ERR_INVALID, "batch %d < 0", batch);
+    if (batch == 0)
+        return BF_OK;
+    if (!w_ids || !f || !s_off || !R_base)
+        return bf_fail(BF_ERR_INVALID, "null argument");
+    if (!aligned8(R_base) || (S_base && !aligned8(S_base)))
+        return bf_fail(BF_ERR_INVALID, "S_base or R_base not 8-byte aligned");
+    for (int32_t t = 0; t < batch; ++t) {
+        if (w_ids[t] < 0 || w_ids[t] >= p->n_w)
+            return bf_fail(BF_ERR_INVALID, "item %d: w_id %d outside [0, %d)", t, w_ids[t], p->n_w);
+        if (f[t] < 0 || f[t] > p->f_max)
+            return bf_fail(BF_ERR_INVALID, "item %d: f %d outside [0, %d]", t, f[t], p->f_max);
+        if (f[t] > 0 && (!S_base || s_off[t] < 0))
+            return bf_fail(BF_ERR_INVALID, "item %d: S_base null or negative offset", t);
+    }
+    const float2 *sb = static_cast<const float2 *>(S_base);
+    float2 *rb = static_cast<float2 *>(R_base);
+    FillFn fill = [&](BfItem *items) {
+        FillStats fs{0, aligned16(S_base) || !S_base};
+        for (int32_t t = 0; t < batch; ++t) {
+            BfItem &it = items[t];
+            it.S = f[t] > 0 ? sb + s_off[t] : nullptr;
+            it.R = rb + (size_t)t * BF_M * BF_B;
+            it.w_id = w_ids[t];
+            it.f = f[t];
+            it.pad0 = it.pad1 = 0;
+            fs.max_f = std::max(fs.max_f, (int)f[t]);
+            if (f[t] > 0 && (s_off[t] & 1))
+                fs.vec16 = false;
+        }
+        return fs;
+    };
+    return enqueue_items(p, prec, batch, fill, static_cast<hipStream_t>(hip_stream), nullptr,
+                         nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// Graphs.
+
+struct bf_graph_s {
+    bf_plan plan = nullptr;
+    void *blk = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int n = 0;
+};
+
+extern "C" bf_status bf_graph_create(bf_graph *out, bf_plan p, int32_t batch, const int32_t *w_ids,
+                                     const int32_t *f, const void *const *S, void *const *R,
+                                     bf_prec prec, void *hip_stream)
+{
+    if (!out)
+        return bf_fail(BF_ERR_INVALID, "out is null");
+    *out = nullptr;
+    bf_status s = check_plan_prec(p, prec);
+    if (s != BF_OK)
+        return s;
+    s = bf_check_batch(p->n_w, p->f_max, batch, w_ids, f, S, R);
+    if (s != BF_OK)
+        return s;
+    if (batch == 0)
+        return bf_fail(BF_ERR_INVALID, "a graph needs at least one item");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+
+    std::vector<BfItem> raw((size_t)batch), items((size_t)batch);
+    int max_f = 0;
+    bool vec16 = true;
+    for (int32_t t = 0; t < batch; ++t) {
+        raw[(size_t)t] = BfItem{static_cast<const float2 *>(S[t]), static_cast<float2 *>(R[t]),
+                                w_ids[t], f[t], 0, 0};
+        max_f = std::max(max_f, (int)f[t]);
+        if (f[t] > 0 && !aligned16(S[t]))
+            vec16 = false;
+    }
+    std::vector<int> scratch;
+    bf_variant v = p->table[prec][bf_f_bucket(max_f)];
+    v.schedule = 1;   // replays rely on the self-resetting claim counter
+    if (v.order == 1)
+        order_items(raw.data(), items.data(), batch, p->n_w, scratch);
+    else
+        items = raw;
+    bfk::LaunchCfg cfg = choose_launch(p, prec, batch, max_f, vec16, &v);
+
+    bf_graph g = new (std::nothrow) bf_graph_s();
+    if (!g)
+        return bf_fail(BF_ERR_OOM, "graph allocation");
+    g->plan = p;
+    g->n = batch;
+    const size_t bytes = sizeof(BfHeader) + (size_t)batch * sizeof(BfItem);
+    std::vector<unsigned char> host(bytes, 0);
+    reinterpret_cast<BfHeader *>(host.data())->n_items = (uint32_t)batch;
+    std::memcpy(host.data() + sizeof(BfHeader), items.data(), (size_t)batch * sizeof(BfItem));
+    hipStream_t cap = nullptr;
+    hipError_t e = hipMalloc(&g->blk, bytes);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g->blk, host.data(), bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    if (e == hipSuccess)
+        e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = launch_for_plan(p, cfg, static_cast<BfHeader *>(g->blk), batch, cap);
+        e = hipStreamEndCapture(cap, &g->graph);
+        if (le != hipSuccess)
+            e = le;
+    }
+    if (e == hipSuccess)
+        e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (cap)
+        (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+        bf_graph_destroy(g);
+        return bf_fail(BF_ERR_DEVICE, "graph capture: %s", hipGetErrorString(e));
+    }
+    *out = g;
+    return BF_OK;
+}
+
+extern "C" bf_status bf_graph_launch(bf_graph g, void *hip_stream)
+{
+    if (!g || !g->exec)
+        return bf_fail(BF_ERR_INVALID, "graph is null");
+    hipError_t e = hipGraphLaunch(g->exec, static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess)
+        return bf_fail(BF_ERR_DEVICE, "hipGraphLaunch: %s", hipGetErrorString(e));
+    return BF_OK;
+}
+
+extern "C" bf_status bf_graph_destroy(bf_graph g)
+{
+    if (!g)
+        return bf_fail(BF_ERR_INVALID, "graph is null");
+    (void)hipDeviceSynchronize();
+    if (g->exec)
+        (void)hipGraphExecDestroy(g->exec);
+    if (g->graph)
+        (void)hipGraphDestroy(g->graph);
+    if (g->blk)
+        (void)hipFree(g->blk);
+    delete g;
+    return BF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Variants and tuning.
+
+static bool valid_variant(const bf_variant &v)
+{
+    return (v.schedule == 0 || v.schedule == 1) && v.wg_per_cu >= 0 && v.wg_per_cu <= 64 &&
+           (v.order == 0 || v.order == 1);
+}
+
+extern "C" bf_status bf_set_variant(bf_plan p, bf_prec prec, int32_t bucket, const bf_variant *v)
+{
+    if (!p || !v)
+        return bf_fail(BF_ERR_INVALID, "null argument");
+    if ((int)prec < 0 || (int)prec >= kPrecCount || bucket < 0 || bucket >= kBucketCount)
+        return bf_fail(BF_ERR_INVALID, "precision %d or bucket %d out of range", (int)prec, bucket);
+    if (!valid_variant(*v))
+        return bf_fail(BF_ERR_INVALID, "invalid variant");
+    std::lock_guard<std::mutex> lk(p->mu);
+    p->table[prec][bucket] = *v;
+    return BF_OK;
+}
+
+extern "C" bf_status bf_get_variant(bf_plan p, bf_prec prec, int32_t bucket, bf_variant *v)
+{
+    if (!p || !v)
+        return bf_fail(BF_ERR_INVALID, "null argument");
+    if ((int)prec < 0 || (int)prec >= kPrecCount || bucket < 0 || bucket >= kBucketCount)
+        return bf_fail(BF_ERR_INVALID, "precision %d or bucket %d out of range", (int)prec, bucket);
+    std::lock_guard<std::mutex> lk(p->mu);
+    *v = p->table[prec][bucket];
+    return BF_OK;
+}
+
+extern "C" bf_status bf_autotune(bf_plan p, int32_t batch, const int32_t *w_ids, const int32_t *f,
+                                 const void *const *S, void *const *R, bf_prec prec, int32_t reps,
+                                 void *hip_stream, bf_variant *best, float *best_us)
+{
+    bf_status s = check_plan_prec(p, prec);
+    if (s != BF_OK)
+        return s;
+    s = bf_check_batch(p->n_w, p->f_max, batch, w_ids, f, S, R);
+    if (s != BF_OK)
+        return s;
+    if (batch == 0)
+        return bf_fail(BF_ERR_INVALID, "cannot tune an empty batch");
+    if (reps < 1)
+        reps = 1;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    int max_f = 0;
+    for (int32_t t = 0; t < batch; ++t)
+        max_f = std::max(max_f, (int)f[t]);
+
+    std::vector<bf_variant> cands;
+    cands.push_back(bf_variant{0, 0, 0, 0});
+    cands.push_back(bf_variant{0, 0, 1, 0});
+    const int per_cu[] = {1, 2, 3, 4, 6, 8};
+    for (int w : per_cu)
+        for (int o = 0; o < 2; ++o)
+            cands.push_back(bf_variant{1, w, o, 0});
+
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return bf_fail(BF_ERR_DEVICE, "hipEventCreate");
+    float best_t = 1e30f;
+    bf_variant best_v = cands[0];
+    for (const bf_variant &v : cands) {
+        FillFn fill = [&](BfItem *items) {
+            FillStats fs{0, true};
+            for (int32_t t = 0; t < batch; ++t) {
+                items[t] = BfItem{static_cast<const float2 *>(S[t]), static_cast<float2 *>(R[t]),
+                                  w_ids[t], f[t], 0, 0};
+                fs.max_f = std::max(fs.max_f, (int)f[t]);
+                if (f[t] > 0 && !aligned16(S[t]))
+                    fs.vec16 = false;
+            }
+            return fs;
+        };
+        for (int w = 0; w < 2; ++w) {
+            s = enqueue_items(p, prec, batch, fill, st, &v, nullptr);
+            if (s != BF_OK)
+                break;
+        }
+        if (s != BF_OK)
+            break;
+        (void)hipEventRecord(e0, st);
+        for (int r = 0; r < reps && s == BF_OK; ++r)
+            s = enqueue_items(p, prec, batch, fill, st, &v, nullptr);
+        (void)hipEventRecord(e1, st);
+        if (s != BF_OK)
+            break;
+        if (hipEventSynchronize(e1) != hipSuccess) {
+            s = bf_fail(BF_ERR_DEVICE, "hipEventSynchronize(autotune)");
+            break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        const float us = ms * 1000.f / (float)reps;
+        if (us < best_t) {
+            best_t = us;
+            best_v = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s != BF_OK)
+        return s;
+    {
+        std::lock_guard<std::mutex> lk(p->mu);
+        p->table[prec][bf_f_bucket(max_f)] = best_v;
+    }
+    if (best)
+        *best = best_v;
+    if (best_us)
+        *best_us = best_t;
+    return BF_OK;
+}
+
+static std::string arch_name()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return "unknown";
+    return prop.gcnArchName;
+}
+
+extern "C" bf_status bf_tune_save(bf_plan p, const char *path)
+{
+    if (!p || !path)
+        return bf_fail(BF_ERR_INVALID, "null argument");
+    FILE *fp = fopen(path, "w");
+    if (!fp)
+        return bf_fail(BF_ERR_INVALID, "cannot open %s for writing", path);
+    std::lock_guard<std::mutex> lk(p->mu);
+    fprintf(fp, "# bf tune v1 arch=%s\n", arch_name().c_str());
+    fprintf(fp, "# prec bucket schedule wg_per_cu order\n");
+    for (int pr = 0; pr < kPrecCount; ++pr)
+        for (int b = 0; b < kBucketCount; ++b) {
+            const bf_variant &v = p->table[pr][b];
+            fprintf(fp, "%d %d %d %d %d\n", pr, b, v.schedule, v.wg_per_cu, v.order);
+        }
+    fclose(fp);
+    return BF_OK;
+}
+
+extern "C" bf_status bf_tune_load(bf_plan p, const char *path)
+{
+    if (!p || !path)
+        return bf_fail(BF_ERR_INVALID, "null argument");
+    FILE *fp = fopen(path, "r");
+    if (!fp)
+        return bf_fail(BF_ERR_INVALID, "cannot open %s", path);
+    char line[256];
+    std::vector<std::pair<std::pair<int, int>, bf_variant>> rows;
+    bool ok = true;
+    while (fgets(line, sizeof line, fp)) {
+        if (line[0] == '#' || line[0] == '\n')
+            continue;
+        int pr, b, sc, w, o;
+        if (sscanf(line, "%d %d %d %d %d", &pr, &b, &sc, &w, &o) != 5 || pr < 0 ||
+            pr >= kPrecCount || b < 0 || b >= kBucketCount) {
+            ok = false;
+            break;
+        }
+        bf_variant v{sc, w, o, 0};
+        if (!valid_variant(v)) {
+            ok = false;
+            break;
+        }
+        rows.push_back({{pr, b}, v});
+    }
+    fclose(fp);
+    if (!ok)
+        return bf_fail(BF_ERR_INVALID, "malformed tune file %s", path);
+    std::lock_guard<std::mutex> lk(p->mu);
+    for (auto &r : rows)
+        p->table[r.first.first][r.first.second] = r.second;
+    return BF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics.
+
+extern "C" const char *bf_status_str(bf_status s)
+{
+    switch (s) {
+    case BF_OK: return "BF_OK";
+    case BF_ERR_INVALID: return "BF_ERR_INVALID";
+    case BF_ERR_OOM: return "BF_ERR_OOM";
+    case BF_ERR_DEVICE: return "BF_ERR_DEVICE";
+    case BF_ERR_BUSY: return "BF_ERR_BUSY";
+    case BF_ERR_TIMEOUT: return "BF_ERR_TIMEOUT";
+    case BF_ERR_UNSUPPORTED: return "BF_ERR_UNSUPPORTED";
+    }
+    return "BF_ERR_UNKNOWN";
+}
+
+extern "C" const char *bf_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" const char *bf_build_info(void)
+{
+    return "libbf gfx950 hip-" BF_STRINGIFY(HIP_VERSION_MAJOR) "." BF_STRINGIFY(HIP_VERSION_MINOR)
+           " fp32-mfma";
+}
+
+extern "C" int32_t bf_device_cu_count(void)
+{
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess)
+        return bf_fail(BF_ERR_DEVICE, "device query: %s", hipGetErrorString(e));
+    return cus;
+}

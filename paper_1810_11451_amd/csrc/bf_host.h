@@ -1,0 +1,64 @@
+// Host-side internals of libbf (plan object, staging ring, helpers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <functional>
+#include <mutex>
+#include <vector>
+
+#include "bf_internal.h"
+
+#define BF_STRINGIFY2(x) #x
+#define BF_STRINGIFY(x) BF_STRINGIFY2(x)
+
+constexpr int kPrecCount = 5;
+constexpr int kBucketCount = 5;
+constexpr int kRingSlots = 8;
+constexpr uint32_t kSupportedMask = BF_PREC_BIT(BF_FP32);
+
+// One slot of the descriptor staging ring: a pinned host block, its device
+// copy, an event recorded on the plan's copy stream after the upload, and
+// an event recorded on the caller's stream after the launch that reads it.
+struct StagingSlot {
+    void *host = nullptr;
+    void *dev = nullptr;
+    size_t cap = 0;
+    hipEvent_t copied = nullptr;
+    hipEvent_t ev = nullptr;
+};
+
+struct bf_plan_s {
+    int device = 0;
+    int n_cu = 1;
+    int n_w = 0;
+    int f_max = 0;
+    int pairs = 0;
+    uint32_t mask = 0;
+
+    float2 *a_fp32 = nullptr;   // FP32 operand layout, a_fp32_stride float2 per W
+    size_t a_fp32_stride = 0;
+
+    hipStream_t copy_stream = nullptr;   // descriptor uploads (overlap the previous launch)
+    std::mutex mu;              // guards the ring, the tables and the sort buffers
+    std::vector<StagingSlot> ring;
+    size_t ring_next = 0;
+    bf_variant table[kPrecCount][kBucketCount];
+    std::vector<BfItem> sort_tmp;
+    std::vector<int> sort_scratch;
+};
+
+struct FillStats {
+    int max_f;
+    bool vec16;
+};
+using FillFn = std::function<FillStats(BfItem *)>;
+
+bf_status bf_fail(bf_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+void order_items(const BfItem *in, BfItem *out, int n, int n_w, std::vector<int> &scratch);
+bfk::LaunchCfg choose_launch(bf_plan p, bf_prec prec, int n, int max_f, bool vec16,
+                             const bf_variant *force);
+bf_status enqueue_items(bf_plan p, bf_prec prec, int n, const FillFn &fill, hipStream_t st,
+                        const bf_variant *force, int *grid_out);
+hipError_t launch_for_plan(bf_plan p, const bfk::LaunchCfg &cfg, BfHeader *blk, int n,
+                           hipStream_t st);

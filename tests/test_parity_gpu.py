@@ -1,0 +1,231 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bar (FP32 path): relative Frobenius error <= 2e-6 per product; exact
+(bitwise) where the arithmetic is exact (identity W, f = 0, Gaussian
+integers).  Sizes span several workgroups and ragged f; the full-size
+workloads are checked on every item (uneven batch) or on a seeded sample
+(full-width batch) in the launch configuration the benchmark uses.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import FP32_TOL, announce, rel_errors, require_gpu, run_batch
+from oracle import oracle as orc
+from paper_1810_11451_amd import bf
+from paper_1810_11451_amd import workloads as wl
+from paper_1810_11451_amd.device import DeviceBatch
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = {
+    "one-per-wg": (0, 0, 0),
+    "persistent-occ-sorted": (1, 0, 1),
+    "persistent-1-asgiven": (1, 1, 0),
+    "persistent-3-sorted": (1, 3, 1),
+}
+
+
+@pytest.mark.parametrize("vname", sorted(VARIANTS))
+def test_config1_fp32(vname):
+    b = wl.config1()
+    announce(f"config1 fp32 variant={vname} n={b.n}")
+    R = run_batch(b, variant=VARIANTS[vname])
+    err, _ = rel_errors(b, R)
+    assert np.max(err) <= FP32_TOL, f"max rel err {np.max(err):.3g}"
+
+
+@pytest.mark.parametrize("vname", sorted(VARIANTS))
+@pytest.mark.parametrize("seed", [101, 102])
+def test_ragged_all_f(vname, seed):
+    """Every f in 0..36, several pool entries, items in random order."""
+    rng = np.random.default_rng(seed)
+    f_values = np.repeat(np.arange(0, 37), 3)
+    b = wl.random_batch(rng, len(f_values), 7, f_values=f_values)
+    announce(f"ragged seed={seed} variant={vname} n={b.n}")
+    R = run_batch(b, variant=VARIANTS[vname])
+    err, ref = rel_errors(b, R)
+    nz = b.f > 0
+    assert np.max(err[nz]) <= FP32_TOL, f"max rel err {np.max(err[nz]):.3g}"
+    assert np.all(R[~nz] == 0), "f = 0 items must be all zeros"
+
+
+@pytest.mark.parametrize("f_max", [1, 2, 7, 36])
+def test_small_pools(f_max):
+    """Pools narrower than 36 (odd and even f_max)."""
+    rng = np.random.default_rng(200 + f_max)
+    b = wl.random_batch(rng, 50, 3, f_max=f_max)
+    announce(f"pool f_max={f_max} n={b.n}")
+    R = run_batch(b)
+    err, _ = rel_errors(b, R)
+    nz = b.f > 0
+    assert np.max(err[nz], initial=0) <= FP32_TOL
+    assert np.all(R[~nz] == 0)
+
+
+def test_packed_entry_point_and_unaligned_s():
+    """bf_apply_packed, and S blocks that are only 8-byte aligned."""
+    rng = np.random.default_rng(301)
+    f = np.array([3, 1, 36, 5, 0, 2, 35], np.int32)
+    b = wl.random_batch(rng, len(f), 2, f_values=[0])
+    blocks = [wl.cn01(rng, (int(x), wl.B)) for x in f]
+    b = wl._pack("unaligned", b.W, b.w_ids, f, blocks)
+    # shift every block by one complex element: S offsets become odd
+    S2 = np.zeros(b.S.size + len(f), np.complex64)
+    off2 = b.s_off + np.arange(len(f)) + 1
+    for t in range(len(f)):
+        S2[off2[t]: off2[t] + f[t] * wl.B] = b.s_block(t).reshape(-1)
+    b2 = wl.Batch("unaligned", b.W, b.w_ids, f, S2, off2)
+    announce("packed + 8-byte aligned S")
+    for packed in (False, True):
+        R = run_batch(b2, packed=packed)
+        err, _ = rel_errors(b2, R)
+        nz = f > 0
+        assert np.max(err[nz]) <= FP32_TOL
+        assert np.all(R[~nz] == 0)
+
+
+def test_identity_is_exact():
+    rng = np.random.default_rng(401)
+    W = np.stack([wl.identity_w(f, 36) for f in (1, 2, 17, 36)])
+    f = np.array([1, 2, 17, 36, 36, 17], np.int32)
+    w_ids = np.array([0, 1, 2, 3, 3, 2], np.int32)
+    blocks = [wl.cn01(rng, (int(x), wl.B)) for x in f]
+    b = wl._pack("identity", W, w_ids, f, blocks)
+    announce("identity W")
+    R = run_batch(b)
+    for t in range(b.n):
+        S = b.s_block(t)
+        assert np.array_equal(R[t, : f[t]], S), f"item {t}: identity rows differ"
+        assert np.all(R[t, f[t]:] == 0)
+
+
+def test_exact_integers_bitwise():
+    rng = np.random.default_rng(402)
+    b = wl.exact_integer_batch(rng, 200, 5)
+    announce(f"exact integers n={b.n}")
+    R = run_batch(b)
+    ref = orc.apply(b)
+    assert np.array_equal(R.astype(np.complex128), ref)
+
+
+def test_dft_closed_form():
+    rng = np.random.default_rng(403)
+    W = wl.dft_w(36)[None]
+    f = np.array([1, 8, 36], np.int32)
+    blocks = [wl.qam256(rng, (int(x), wl.B)) for x in f]
+    b = wl._pack("dft", W, np.zeros(3, np.int32), f, blocks)
+    announce("DFT W")
+    R = run_batch(b)
+    for t in range(3):
+        pad = np.zeros((wl.M, wl.B), np.complex128)
+        pad[: f[t]] = b.s_block(t)
+        ref = np.fft.fft(pad, axis=0) / 8.0
+        e = np.linalg.norm(R[t] - ref) / np.linalg.norm(ref)
+        assert e <= FP32_TOL, f"f={f[t]}: {e:.3g}"
+
+
+def test_nothing_written_on_invalid_batch():
+    torch = require_gpu()
+    b = wl.config1(n=10)
+    plan = bf.bf_plan_create(b.W)
+    db = DeviceBatch(b)
+    w_ids = b.w_ids.copy()
+    w_ids[7] = 1   # pool has one entry
+    announce("invalid batch leaves R untouched")
+    with pytest.raises(bf.BfError) as ei:
+        bf.bf_apply(plan, w_ids, b.f, db.s_ptrs[0], db.r_ptrs[0])
+    assert ei.value.status == bf.BF_ERR_INVALID and "item 7" in ei.value.detail
+    torch.cuda.synchronize()
+    assert np.all(np.isnan(db.result().view(np.float32)))
+    with pytest.raises(bf.BfError) as ei:
+        bf.bf_apply(plan, b.w_ids, b.f, db.s_ptrs[0], db.r_ptrs[0], prec=bf.BF_BF16X2)
+    assert ei.value.status == bf.BF_ERR_UNSUPPORTED
+    bf.bf_apply(plan, b.w_ids[:0], b.f[:0], db.s_ptrs[0][:0], db.r_ptrs[0][:0])   # no-op
+    plan.close()
+
+
+def test_two_streams_and_plan_reuse():
+    torch = require_gpu()
+    rng = np.random.default_rng(501)
+    b = wl.random_batch(rng, 300, 4, dist="qam")
+    plan = bf.bf_plan_create(b.W)
+    db = DeviceBatch(b, copies=2)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    announce("two streams")
+    for _ in range(3):
+        db.apply(plan, copy=0, stream=s1)
+        db.apply(plan, copy=1, stream=s2)
+    torch.cuda.synchronize()
+    ref = orc.apply(b)
+    for c in range(2):
+        err = orc.rel_frobenius(db.result(c), ref)
+        nz = b.f > 0
+        assert np.max(err[nz]) <= FP32_TOL
+    plan.close()
+
+
+def test_graph_replay_matches_direct():
+    torch = require_gpu()
+    b = wl.config3(n=700)
+    plan = bf.bf_plan_create(b.W)
+    direct = DeviceBatch(b)
+    direct.apply(plan)
+    Rd = direct.result()
+    db = DeviceBatch(b)
+    announce("graph replay x4")
+    g = bf.bf_graph_create(plan, b.w_ids, b.f, db.s_ptrs[0], db.r_ptrs[0])
+    for rep in range(4):
+        db.R[0].view(torch.float32).fill_(float("nan"))
+        bf.bf_graph_launch(g)
+        torch.cuda.synchronize()
+        Rg = db.result()
+        assert np.array_equal(Rg.view(np.uint32), Rd.view(np.uint32)), f"replay {rep} differs"
+        direct.apply(plan)          # eager work between replays
+        torch.cuda.synchronize()
+    g.close()
+    err, _ = rel_errors(b, Rd)
+    assert np.max(err) <= FP32_TOL
+    plan.close()
+
+
+def test_autotune_and_cache(tmp_path):
+    require_gpu()
+    b = wl.config3(n=2000)
+    plan = bf.bf_plan_create(b.W)
+    db = DeviceBatch(b)
+    announce("autotune")
+    best, us = bf.bf_autotune(plan, b.w_ids, b.f, db.s_ptrs[0], db.r_ptrs[0], reps=2)
+    assert us > 0
+    assert bf.bf_get_variant(plan, bf.BF_FP32, bf.bf_f_bucket(36)) == best
+    path = tmp_path / "tune.txt"
+    bf.bf_tune_save(plan, path)
+    plan2 = bf.bf_plan_create(b.W)
+    bf.bf_tune_load(plan2, path)
+    assert bf.bf_get_variant(plan2, bf.BF_FP32, bf.bf_f_bucket(36)) == best
+    db.R[0].fill_(float("nan"))
+    db.apply(plan2)
+    err, _ = rel_errors(b, db.result())
+    assert np.max(err) <= FP32_TOL
+    plan.close()
+    plan2.close()
+
+
+def test_full_width_workload_sampled():
+    """16384 products, f = 36, pool of 64: the benchmark's workload and launch."""
+    b = wl.config2()
+    announce(f"full-width n={b.n}")
+    R = run_batch(b)
+    assert not np.any(np.isnan(R.view(np.float32))), "some R not written"
+    items = np.random.default_rng(7).choice(b.n, size=1024, replace=False)
+    items = np.concatenate([items, [0, b.n - 1]])
+    err, _ = rel_errors(b, R, items=items)
+    assert np.max(err) <= FP32_TOL, f"max rel err {np.max(err):.3g}"
+
+
+def test_uneven_workload_all_items():
+    """8192 products with f ~ U{1..36} from a pool of 256: every item checked."""
+    b = wl.config3()
+    announce(f"uneven n={b.n}")
+    R = run_batch(b)
+    err, _ = rel_errors(b, R)
+    assert np.max(err) <= FP32_TOL, f"max rel err {np.max(err):.3g}"
