@@ -111,6 +111,8 @@ def main(argv=None) -> int:
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="tune the variant before timing")
+    ap.add_argument("--variant", default=None,
+                    help="force schedule:wg_per_cu:order (e.g. 2:3:1) instead of the plan table")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -133,9 +135,13 @@ def main(argv=None) -> int:
     db = DeviceBatch(batch, copies=args.copies, fill_r=None)
     stream = torch.cuda.current_stream()
     tuned = None
+    if args.variant:
+        v = [int(x) for x in args.variant.split(":")]
+        for bk in range(5):
+            bf.bf_set_variant(plan, prec, bk, *v)
     if args.autotune:
         tuned = bf.bf_autotune(plan, batch.w_ids, batch.f, db.s_ptrs[0], db.r_ptrs[0], prec, reps=5)
-    variant = bf.bf_get_variant(plan, prec, bf.bf_f_bucket(int(batch.f.max())))
+    variant = bf.bf_get_variant(plan, prec, bf.batch_bucket(batch.f))
 
     for i in range(args.warmup):
         db.apply(plan, prec, copy=i % args.copies)

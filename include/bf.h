@@ -137,7 +137,8 @@ bf_status bf_graph_destroy(bf_graph graph);
  * the fastest for (prec, f bucket) in the plan; bf_apply uses it from
  * then on.  The table can be saved to and loaded from a text file. */
 typedef struct {
-    int32_t schedule;      /* 0: one product per workgroup; 1: persistent, atomic claim */
+    int32_t schedule;      /* 0: one product per workgroup; 1: persistent, atomic claim;
+                              2: persistent, static share per XCD, next S prefetched */
     int32_t wg_per_cu;     /* persistent grid = wg_per_cu * CU count (ignored for 0) */
     int32_t order;         /* 0: as given; 1: longest f first, then by W id */
     int32_t reserved;

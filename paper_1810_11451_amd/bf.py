@@ -287,6 +287,14 @@ def bf_f_bucket(f: int) -> int:
     return int(lib().bf_f_bucket(int(f)))
 
 
+def batch_bucket(f) -> int:
+    """Tuning-table bucket the library uses for a batch: that of its mean f."""
+    f = np.asarray(f, dtype=np.int64)
+    if f.size == 0:
+        return 0
+    return bf_f_bucket(int((int(f.sum()) + f.size // 2) // f.size))
+
+
 def bf_set_variant(plan: Plan, prec: int, bucket: int, schedule: int, wg_per_cu: int = 0,
                    order: int = 1) -> None:
     v = bf_variant(schedule, wg_per_cu, order, 0)

@@ -85,14 +85,18 @@ static void release_slot(StagingSlot &s)
     s = StagingSlot{};
 }
 
+// Defaults measured on MI355X: full-width batches (mean f 36) stream
+// through persistent workgroups with the next S prefetched; batches of
+// mixed or small f run one product per workgroup in the order given.
 static bf_status default_variants(bf_plan p)
 {
     for (int pr = 0; pr < kPrecCount; ++pr)
         for (int b = 0; b < kBucketCount; ++b) {
             bf_variant v{};
-            v.schedule = 1;
+            const bool full = b == kBucketCount - 1;
+            v.schedule = full ? 2 : 0;
             v.wg_per_cu = 0;   // 0: the kernel's occupancy
-            v.order = 1;
+            v.order = full ? 1 : 0;
             p->table[pr][b] = v;
         }
     return BF_OK;
@@ -220,6 +224,15 @@ extern "C" int32_t bf_f_bucket(int32_t f)
     return b < kBucketCount ? b : kBucketCount - 1;
 }
 
+// Batches are keyed by their mean f (rounded): uniform full-width batches
+// and uneven batches with the same largest f want different schedules.
+int batch_bucket(int64_t sum_f, int n)
+{
+    if (n <= 0)
+        return 0;
+    return bf_f_bucket((int32_t)((sum_f + n / 2) / n));
+}
+
 // Orders items longest f first and, for equal f, by W id (so that a
 // persistent workgroup keeps its W operands across consecutive items).
 // Two stable counting sorts: by W id, then by f descending.
@@ -247,6 +260,7 @@ bfk::LaunchCfg choose_launch(bf_plan p, bf_prec prec, int n, int max_f, bool vec
                              const bf_variant *force)
 {
     const bf_variant v = force ? *force : p->table[prec][bf_f_bucket(max_f)];
+    (void)max_f;
     bfk::LaunchCfg cfg{};
     cfg.prec = prec;
     cfg.schedule = v.schedule;
@@ -254,7 +268,7 @@ bfk::LaunchCfg choose_launch(bf_plan p, bf_prec prec, int n, int max_f, bool vec
     if (v.schedule == 0) {
         cfg.grid = n;
     } else {
-        const int occ = bfk::apply_occupancy(prec, 1, vec16);
+        const int occ = bfk::apply_occupancy(prec, v.schedule, vec16);
         const int per_cu = v.wg_per_cu > 0 ? v.wg_per_cu : occ;
         const long g = (long)per_cu * p->n_cu;
         cfg.grid = (int)std::min<long>(g, n);
@@ -309,7 +323,7 @@ bf_status enqueue_items(bf_plan p, bf_prec prec, int n, const FillFn &fill, hipS
         p->ring.resize(kRingSlots);
     StagingSlot &slot = p->ring[p->ring_next];
     p->ring_next = (p->ring_next + 1) % p->ring.size();
-    const size_t bytes = sizeof(BfHeader) + (size_t)n * sizeof(BfItem);
+    const size_t bytes = block_bytes(n);
     bf_status s = ensure_slot(slot, bytes);
     if (s != BF_OK)
         return s;
@@ -317,11 +331,12 @@ bf_status enqueue_items(bf_plan p, bf_prec prec, int n, const FillFn &fill, hipS
     BfHeader *hdr = static_cast<BfHeader *>(slot.host);
     std::memset(hdr, 0, sizeof *hdr);
     hdr->n_items = (uint32_t)n;
-    BfItem *items = reinterpret_cast<BfItem *>(hdr + 1);
+    BfItem *items = reinterpret_cast<BfItem *>(static_cast<char *>(slot.host) + sizeof(BfHeader) +
+                                               kSinkBytes);
     const FillStats fs = fill(items);
     const int max_f = fs.max_f;
     const bool vec16 = fs.vec16;
-    bf_variant chosen = force ? *force : p->table[prec][bf_f_bucket(max_f)];
+    bf_variant chosen = force ? *force : p->table[prec][batch_bucket(fs.sum_f, n)];
     if (chosen.order == 1 && n > 1) {
         p->sort_tmp.resize((size_t)n);
         order_items(items, p->sort_tmp.data(), n, p->n_w, p->sort_scratch);
@@ -390,7 +405,7 @@ extern "C" bf_status bf_apply(bf_plan p, int32_t batch, const int32_t *w_ids, co
     if (s != BF_OK || batch == 0)
         return s;
     FillFn fill = [&](BfItem *items) {
-        FillStats fs{0, true};
+        FillStats fs{0, true, 0};
         for (int32_t t = 0; t < batch; ++t) {
             BfItem &it = items[t];
             it.S = static_cast<const float2 *>(S[t]);
@@ -399,6 +414,7 @@ extern "C" bf_status bf_apply(bf_plan p, int32_t batch, const int32_t *w_ids, co
             it.f = f[t];
             it.pad0 = it.pad1 = 0;
             fs.max_f = std::max(fs.max_f, (int)f[t]);
+            fs.sum_f += f[t];
             if (f[t] > 0 && !aligned16(S[t]))
                 fs.vec16 = false;
         }
@@ -434,7 +450,7 @@ extern "C" bf_status bf_apply_packed(bf_plan p, int32_t batch, const int32_t *w_
     const float2 *sb = static_cast<const float2 *>(S_base);
     float2 *rb = static_cast<float2 *>(R_base);
     FillFn fill = [&](BfItem *items) {
-        FillStats fs{0, aligned16(S_base) || !S_base};
+        FillStats fs{0, aligned16(S_base) || !S_base, 0};
         for (int32_t t = 0; t < batch; ++t) {
             BfItem &it = items[t];
             it.S = f[t] > 0 ? sb + s_off[t] : nullptr;
@@ -443,6 +459,7 @@ extern "C" bf_status bf_apply_packed(bf_plan p, int32_t batch, const int32_t *w_
             it.f = f[t];
             it.pad0 = it.pad1 = 0;
             fs.max_f = std::max(fs.max_f, (int)f[t]);
+            fs.sum_f += f[t];
             if (f[t] > 0 && (s_off[t] & 1))
                 fs.vec16 = false;
         }
@@ -482,17 +499,20 @@ extern "C" bf_status bf_graph_create(bf_graph *out, bf_plan p, int32_t batch, co
 
     std::vector<BfItem> raw((size_t)batch), items((size_t)batch);
     int max_f = 0;
+    int64_t sum_f = 0;
     bool vec16 = true;
     for (int32_t t = 0; t < batch; ++t) {
         raw[(size_t)t] = BfItem{static_cast<const float2 *>(S[t]), static_cast<float2 *>(R[t]),
                                 w_ids[t], f[t], 0, 0};
         max_f = std::max(max_f, (int)f[t]);
+        sum_f += f[t];
         if (f[t] > 0 && !aligned16(S[t]))
             vec16 = false;
     }
     std::vector<int> scratch;
-    bf_variant v = p->table[prec][bf_f_bucket(max_f)];
-    v.schedule = 1;   // replays rely on the self-resetting claim counter
+    bf_variant v = p->table[prec][batch_bucket(sum_f, batch)];
+    if (v.schedule == 0)
+        v.schedule = 2;   // a graph replays a persistent launch
     if (v.order == 1)
         order_items(raw.data(), items.data(), batch, p->n_w, scratch);
     else
@@ -504,10 +524,11 @@ extern "C" bf_status bf_graph_create(bf_graph *out, bf_plan p, int32_t batch, co
         return bf_fail(BF_ERR_OOM, "graph allocation");
     g->plan = p;
     g->n = batch;
-    const size_t bytes = sizeof(BfHeader) + (size_t)batch * sizeof(BfItem);
+    const size_t bytes = block_bytes(batch);
     std::vector<unsigned char> host(bytes, 0);
     reinterpret_cast<BfHeader *>(host.data())->n_items = (uint32_t)batch;
-    std::memcpy(host.data() + sizeof(BfHeader), items.data(), (size_t)batch * sizeof(BfItem));
+    std::memcpy(host.data() + sizeof(BfHeader) + kSinkBytes, items.data(),
+                (size_t)batch * sizeof(BfItem));
     hipStream_t cap = nullptr;
     hipError_t e = hipMalloc(&g->blk, bytes);
     if (e == hipSuccess)
@@ -566,7 +587,7 @@ extern "C" bf_status bf_graph_destroy(bf_graph g)
 
 static bool valid_variant(const bf_variant &v)
 {
-    return (v.schedule == 0 || v.schedule == 1) && v.wg_per_cu >= 0 && v.wg_per_cu <= 64 &&
+    return v.schedule >= 0 && v.schedule <= 2 && v.wg_per_cu >= 0 && v.wg_per_cu <= 64 &&
            (v.order == 0 || v.order == 1);
 }
 
@@ -609,17 +630,18 @@ extern "C" bf_status bf_autotune(bf_plan p, int32_t batch, const int32_t *w_ids,
     if (reps < 1)
         reps = 1;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    int max_f = 0;
+    int64_t sum_f = 0;
     for (int32_t t = 0; t < batch; ++t)
-        max_f = std::max(max_f, (int)f[t]);
+        sum_f += f[t];
 
     std::vector<bf_variant> cands;
     cands.push_back(bf_variant{0, 0, 0, 0});
     cands.push_back(bf_variant{0, 0, 1, 0});
     const int per_cu[] = {1, 2, 3, 4, 6, 8};
-    for (int w : per_cu)
-        for (int o = 0; o < 2; ++o)
-            cands.push_back(bf_variant{1, w, o, 0});
+    for (int sc = 1; sc <= 2; ++sc)
+        for (int w : per_cu)
+            for (int o = 0; o < 2; ++o)
+                cands.push_back(bf_variant{sc, w, o, 0});
 
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -628,11 +650,12 @@ extern "C" bf_status bf_autotune(bf_plan p, int32_t batch, const int32_t *w_ids,
     bf_variant best_v = cands[0];
     for (const bf_variant &v : cands) {
         FillFn fill = [&](BfItem *items) {
-            FillStats fs{0, true};
+            FillStats fs{0, true, 0};
             for (int32_t t = 0; t < batch; ++t) {
                 items[t] = BfItem{static_cast<const float2 *>(S[t]), static_cast<float2 *>(R[t]),
                                   w_ids[t], f[t], 0, 0};
                 fs.max_f = std::max(fs.max_f, (int)f[t]);
+            fs.sum_f += f[t];
                 if (f[t] > 0 && !aligned16(S[t]))
                     fs.vec16 = false;
             }
@@ -669,7 +692,7 @@ extern "C" bf_status bf_autotune(bf_plan p, int32_t batch, const int32_t *w_ids,
         return s;
     {
         std::lock_guard<std::mutex> lk(p->mu);
-        p->table[prec][bf_f_bucket(max_f)] = best_v;
+        p->table[prec][batch_bucket(sum_f, batch)] = best_v;
     }
     if (best)
         *best = best_v;

@@ -51,7 +51,10 @@ struct bf_plan_s {
 struct FillStats {
     int max_f;
     bool vec16;
+    int64_t sum_f;
 };
+// Tuning-table bucket of a batch: bf_f_bucket of its mean f, rounded.
+int batch_bucket(int64_t sum_f, int n);
 using FillFn = std::function<FillStats(BfItem *)>;
 
 bf_status bf_fail(bf_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));

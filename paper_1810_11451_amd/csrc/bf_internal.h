@@ -16,16 +16,22 @@ struct BfItem {
     int32_t pad1;
 };
 
-// Header of a device descriptor block; the items follow it.  `next` is the
-// claim counter of the persistent schedule and `done` counts finished
-// workgroups; the last workgroup to finish puts both back to zero, so a
-// block can be replayed (graphs) without clearing it in between.
+// Header of a device descriptor block.  Layout of a block:
+//   [BfHeader, 64 B][sink, kSinkBytes][BfItem x n_items]
+// `next` is the claim counter of the persistent schedule and `done` counts
+// finished workgroups; the last workgroup to finish puts both back to zero,
+// so a block can be replayed (graphs) without clearing it in between.
+// The sink is scratch that lets every memory access of the kernels be
+// unconditional: loads for f = 0 products read it and the stores of the
+// four padding columns (60..63) of each row land in it.
 struct BfHeader {
     uint32_t next;
     uint32_t done;
     uint32_t n_items;
     uint32_t pad[13];
 };
+constexpr size_t kSinkBytes = 8192;
+inline size_t block_bytes(int n_items) { return 64 + kSinkBytes + (size_t)n_items * 32; }
 static_assert(sizeof(BfItem) == 32, "BfItem layout");
 static_assert(sizeof(BfHeader) == 64, "BfHeader layout");
 

@@ -1,0 +1,68 @@
+"""Achievable HBM bandwidth: time a plain streaming copy of known size.
+
+    python -m paper_1810_11451_amd.probe.hbm [--mib 1024] [--iters 20] [--grid G]
+
+Prints one JSON line with the copy's read+write GB/s.  Under a counter run
+(rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE) the same command gives the bytes
+the counters report for a known traffic of `mib` MiB read and written per
+dispatch, which scales the counters of the beamforming kernel.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import subprocess
+import sys
+from pathlib import Path
+
+HERE = Path(__file__).resolve().parent
+LIB = HERE / "libbfprobe.so"
+
+
+def build() -> Path:
+    from paper_1810_11451_amd.build import ARCH, COMMON, hipcc
+    cmd = [hipcc(), *COMMON, "-x", "hip", "-shared", "-fPIC", str(HERE / "hbm_probe.hip"),
+           "-o", str(LIB)]
+    subprocess.run(cmd, check=True)
+    return LIB
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--mib", type=int, default=1024)
+    ap.add_argument("--iters", type=int, default=20)
+    ap.add_argument("--grid", type=int, default=0, help="workgroups (0: 256 CUs x 8)")
+    ap.add_argument("--variant", type=int, default=1,
+                    help="bit 0 non-temporal, bits 1-2 log2 unroll (default 1: plain nt copy)")
+    a = ap.parse_args(argv)
+    import torch
+    if not LIB.exists():
+        raise RuntimeError(f"{LIB} not built")
+    L = ctypes.CDLL(str(LIB))
+    L.bfprobe_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
+                               ctypes.c_int, ctypes.c_void_p]
+    nbytes = a.mib << 20
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    grid = a.grid or 256 * 8
+    st = torch.cuda.current_stream()
+    for _ in range(3):
+        assert L.bfprobe_copy(src.data_ptr(), dst.data_ptr(), nbytes, grid, a.variant, st.cuda_stream) == 0
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(a.iters):
+        L.bfprobe_copy(src.data_ptr(), dst.data_ptr(), nbytes, grid, a.variant, st.cuda_stream)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / a.iters
+    assert bool(torch.equal(src[:1024], dst[:1024]))
+    print(json.dumps({"probe": "hbm_copy", "bytes_read": nbytes, "bytes_written": nbytes,
+                      "us": round(ms * 1e3, 2), "GBps_rw": round(2 * nbytes / ms / 1e6, 1),
+                      "grid": grid, "variant": a.variant}), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

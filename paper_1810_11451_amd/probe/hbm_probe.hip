@@ -1,0 +1,59 @@
+// HBM reference kernels: a plain streaming copy of known size.  Used to
+// measure achievable bandwidth next to the spec-sheet peak, and to scale
+// the FETCH_SIZE / WRITE_SIZE counters (bytes a counter reports for a copy
+// whose traffic is known).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// Each thread moves kU 16-byte chunks per step (all loads first), blocks
+// stride over the buffer; kNt selects non-temporal loads and stores.
+template <int kU, bool kNt>
+__global__ __launch_bounds__(256) void copy_kernel(const f4v *__restrict__ src,
+                                                   f4v *__restrict__ dst, size_t n)
+{
+    const size_t step = (size_t)gridDim.x * 256 * kU;
+    for (size_t base = (size_t)blockIdx.x * 256 * kU + threadIdx.x; base < n; base += step) {
+        f4v v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const size_t i = base + (size_t)u * 256;
+            if (i < n)
+                v[u] = kNt ? __builtin_nontemporal_load(src + i) : src[i];
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const size_t i = base + (size_t)u * 256;
+            if (i < n) {
+                if (kNt)
+                    __builtin_nontemporal_store(v[u], dst + i);
+                else
+                    dst[i] = v[u];
+            }
+        }
+    }
+}
+
+// variant: bit 0 = non-temporal, bits 1-2 = log2 of the per-thread unroll.
+extern "C" int bfprobe_copy(const void *src, void *dst, uint64_t bytes, int grid, int variant,
+                            void *stream)
+{
+    if (!src || !dst || (bytes & 15) || grid <= 0 || variant < 0 || variant > 7)
+        return -1;
+    const size_t n = bytes / 16;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const f4v *s = static_cast<const f4v *>(src);
+    f4v *d = static_cast<f4v *>(dst);
+    switch (variant) {
+    case 0: hipLaunchKernelGGL((copy_kernel<1, false>), dim3(grid), dim3(256), 0, st, s, d, n); break;
+    case 1: hipLaunchKernelGGL((copy_kernel<1, true>), dim3(grid), dim3(256), 0, st, s, d, n); break;
+    case 2: hipLaunchKernelGGL((copy_kernel<2, false>), dim3(grid), dim3(256), 0, st, s, d, n); break;
+    case 3: hipLaunchKernelGGL((copy_kernel<2, true>), dim3(grid), dim3(256), 0, st, s, d, n); break;
+    case 4: hipLaunchKernelGGL((copy_kernel<4, false>), dim3(grid), dim3(256), 0, st, s, d, n); break;
+    case 5: hipLaunchKernelGGL((copy_kernel<4, true>), dim3(grid), dim3(256), 0, st, s, d, n); break;
+    case 6: hipLaunchKernelGGL((copy_kernel<8, false>), dim3(grid), dim3(256), 0, st, s, d, n); break;
+    default: hipLaunchKernelGGL((copy_kernel<8, true>), dim3(grid), dim3(256), 0, st, s, d, n); break;
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}

@@ -19,9 +19,12 @@ pytestmark = pytest.mark.gpu
 
 VARIANTS = {
     "one-per-wg": (0, 0, 0),
-    "persistent-occ-sorted": (1, 0, 1),
-    "persistent-1-asgiven": (1, 1, 0),
-    "persistent-3-sorted": (1, 3, 1),
+    "claim-occ-sorted": (1, 0, 1),
+    "claim-1-asgiven": (1, 1, 0),
+    "claim-3-sorted": (1, 3, 1),
+    "stream-occ-sorted": (2, 0, 1),
+    "stream-1-asgiven": (2, 1, 0),
+    "stream-2-sorted": (2, 2, 1),
 }
 
 
@@ -196,12 +199,13 @@ def test_autotune_and_cache(tmp_path):
     announce("autotune")
     best, us = bf.bf_autotune(plan, b.w_ids, b.f, db.s_ptrs[0], db.r_ptrs[0], reps=2)
     assert us > 0
-    assert bf.bf_get_variant(plan, bf.BF_FP32, bf.bf_f_bucket(36)) == best
+    bucket = bf.batch_bucket(b.f)
+    assert bf.bf_get_variant(plan, bf.BF_FP32, bucket) == best
     path = tmp_path / "tune.txt"
     bf.bf_tune_save(plan, path)
     plan2 = bf.bf_plan_create(b.W)
     bf.bf_tune_load(plan2, path)
-    assert bf.bf_get_variant(plan2, bf.BF_FP32, bf.bf_f_bucket(36)) == best
+    assert bf.bf_get_variant(plan2, bf.BF_FP32, bucket) == best
     db.R[0].fill_(float("nan"))
     db.apply(plan2)
     err, _ = rel_errors(b, db.result())
