@@ -174,6 +174,29 @@ extern "C" bf_status bf_plan_create(bf_plan *out, const void *w_pool, int32_t n_
             return fail_dev("FP32 W layout", e);
         }
     }
+    p->lp_stride = bfk::lp_w_units(f_max);
+    for (int ty = 0; ty < 2; ++ty) {
+        const bf_prec plain = ty == 0 ? BF_FP16 : BF_BF16;
+        const bf_prec split = ty == 0 ? BF_FP16X2 : BF_BF16X2;
+        const bool want = prec_mask & (BF_PREC_BIT(plain) | BF_PREC_BIT(split));
+        if (!want)
+            continue;
+        const bool want_lo = prec_mask & BF_PREC_BIT(split);
+        const size_t bytes = std::max<size_t>(16, (size_t)n_w * p->lp_stride * 16);
+        e = hipMalloc(&p->lp_hi[ty], bytes);
+        if (e == hipSuccess && want_lo)
+            e = hipMalloc(&p->lp_lo[ty], bytes);
+        if (e == hipSuccess)
+            e = hipMalloc(&p->lp_exp[ty], sizeof(int) * (size_t)n_w);
+        if (e == hipSuccess && w_dev)
+            e = bfk::launch_w_transform_lp(w_dev, n_w, f_max, ty == 1, p->lp_hi[ty], p->lp_lo[ty],
+                                           p->lp_exp[ty], st);
+        if (e != hipSuccess) {
+            if (w_dev)
+                (void)hipFree(w_dev);
+            return fail_dev("16-bit W layout", e);
+        }
+    }
     e = hipStreamSynchronize(st);
     if (w_dev)
         (void)hipFree(w_dev);
@@ -194,6 +217,14 @@ extern "C" bf_status bf_plan_destroy(bf_plan p)
     }
     if (p->a_fp32)
         (void)hipFree(p->a_fp32);
+    for (int ty = 0; ty < 2; ++ty) {
+        if (p->lp_hi[ty])
+            (void)hipFree(p->lp_hi[ty]);
+        if (p->lp_lo[ty])
+            (void)hipFree(p->lp_lo[ty]);
+        if (p->lp_exp[ty])
+            (void)hipFree(p->lp_exp[ty]);
+    }
     if (p->copy_stream)
         (void)hipStreamDestroy(p->copy_stream);
     delete p;
@@ -264,11 +295,13 @@ bfk::LaunchCfg choose_launch(bf_plan p, bf_prec prec, int n, int max_f, bool vec
     bfk::LaunchCfg cfg{};
     cfg.prec = prec;
     cfg.schedule = v.schedule;
+    if (prec != BF_FP32 && cfg.schedule == 1)
+        cfg.schedule = 2;   // the 16-bit forms have no claim schedule
     cfg.vec16 = vec16;
     if (v.schedule == 0) {
         cfg.grid = n;
     } else {
-        const int occ = bfk::apply_occupancy(prec, v.schedule, vec16);
+        const int occ = bfk::apply_occupancy(prec, cfg.schedule, vec16);
         const int per_cu = v.wg_per_cu > 0 ? v.wg_per_cu : occ;
         const long g = (long)per_cu * p->n_cu;
         cfg.grid = (int)std::min<long>(g, n);
@@ -370,18 +403,17 @@ bf_status enqueue_items(bf_plan p, bf_prec prec, int n, const FillFn &fill, hipS
 hipError_t launch_for_plan(bf_plan p, const bfk::LaunchCfg &cfg, BfHeader *blk, int n,
                            hipStream_t st)
 {
-    const void *a = nullptr;
-    size_t stride = 0;
-    const float *scale = nullptr;
-    switch (cfg.prec) {
-    case BF_FP32:
-        a = p->a_fp32;
-        stride = p->a_fp32_stride;
-        break;
-    default:
-        return hipErrorNotSupported;
-    }
-    return bfk::launch_apply(cfg, blk, n, a, stride, p->pairs, scale, st);
+    bfk::PlanDev pd{};
+    pd.a_fp32 = p->a_fp32;
+    pd.a_fp32_stride = (int)p->a_fp32_stride;
+    pd.pairs = p->pairs;
+    const int ty = (cfg.prec == BF_BF16 || cfg.prec == BF_BF16X2) ? 1 : 0;
+    pd.lp_hi = p->lp_hi[ty];
+    pd.lp_lo = p->lp_lo[ty];
+    pd.lp_exp = p->lp_exp[ty];
+    pd.lp_stride = (int)p->lp_stride;
+    pd.lp_chunks = bfk::lp_chunks(p->f_max);
+    return bfk::launch_apply(cfg, blk, n, pd, st);
 }
 
 static bf_status check_plan_prec(bf_plan p, bf_prec prec)
@@ -786,7 +818,7 @@ extern "C" const char *bf_last_error(void) { return g_last_error.c_str(); }
 extern "C" const char *bf_build_info(void)
 {
     return "libbf gfx950 hip-" BF_STRINGIFY(HIP_VERSION_MAJOR) "." BF_STRINGIFY(HIP_VERSION_MINOR)
-           " fp32-mfma";
+           " fp32-mfma fp16/bf16-mfma split";
 }
 
 extern "C" int32_t bf_device_cu_count(void)

@@ -15,7 +15,7 @@
 constexpr int kPrecCount = 5;
 constexpr int kBucketCount = 5;
 constexpr int kRingSlots = 8;
-constexpr uint32_t kSupportedMask = BF_PREC_BIT(BF_FP32);
+constexpr uint32_t kSupportedMask = BF_PREC_ALL;
 
 // One slot of the descriptor staging ring: a pinned host block, its device
 // copy, an event recorded on the plan's copy stream after the upload, and
@@ -38,6 +38,11 @@ struct bf_plan_s {
 
     float2 *a_fp32 = nullptr;   // FP32 operand layout, a_fp32_stride float2 per W
     size_t a_fp32_stride = 0;
+    // 16-bit operand layouts, index 0 = FP16, 1 = BF16 (lo only for split forms)
+    void *lp_hi[2] = {nullptr, nullptr};
+    void *lp_lo[2] = {nullptr, nullptr};
+    int *lp_exp[2] = {nullptr, nullptr};
+    size_t lp_stride = 0;       // 16-byte units per W
 
     hipStream_t copy_stream = nullptr;   // descriptor uploads (overlap the previous launch)
     std::mutex mu;              // guards the ring, the tables and the sort buffers

@@ -48,24 +48,38 @@ constexpr int kThreads = 64 * kWaves;
 // [kWaves][pairs][64 lanes]; see bf_kernels.hip.
 inline size_t fp32_w_stride(int pairs) { return (size_t)kWaves * pairs * 64; }
 
-// Split-form operand layouts (16-bit types): per W, per form; see
-// bf_kernels.hip.  Sizes are in bytes.
-size_t lp_w_bytes(int f_max);
+// Device-side view of a plan, as the apply kernels need it.
+struct PlanDev {
+    const float2 *a_fp32;     // FP32 form: kWaves x pairs x 64 float2 per W
+    int a_fp32_stride;        // float2 per W
+    int pairs;                // ceil(f_max / 2)
+    const void *lp_hi;        // 16-bit forms: kWaves x chunks x 64 x 16 bytes per W
+    const void *lp_lo;        // (lo part, split forms only)
+    const int *lp_exp;        // per-W power-of-two exponent of the 16-bit operands
+    int lp_stride;            // 16-byte units per W
+    int lp_chunks;            // ceil(f_max / 8)
+};
+
+constexpr int kLpFlows = 8;   // flows per 16-bit matrix-core step (K = 16 real)
+inline int lp_chunks(int f_max) { return (f_max + kLpFlows - 1) / kLpFlows; }
+inline size_t lp_w_units(int f_max) { return (size_t)kWaves * lp_chunks(f_max) * 64; }
 
 hipError_t launch_w_transform_fp32(const float2 *w_dev, int n_w, int f_max, float2 *a_out,
                                    int pairs, hipStream_t st);
-hipError_t launch_w_transform_lp(const float2 *w_dev, int n_w, int f_max, int prec,
-                                 void *a_out, float *w_scale_out, hipStream_t st);
+// bf16 selects BF16 (else FP16); lo may be null (plain forms only).
+hipError_t launch_w_transform_lp(const float2 *w_dev, int n_w, int f_max, bool bf16, void *hi,
+                                 void *lo, int *w_exp, hipStream_t st);
 
 struct LaunchCfg {
     int prec;        // bf_prec
-    int schedule;    // 0 one product per workgroup, 1 persistent with atomic claim
+    int schedule;    // 0 one product per workgroup, 1 persistent with atomic claim,
+                     // 2 persistent static share with prefetch
     int grid;        // workgroups
     bool vec16;      // all S 16-byte aligned
 };
 
-hipError_t launch_apply(const LaunchCfg &cfg, BfHeader *blk, int n_items, const void *a_pool,
-                        size_t a_w_stride, int pairs, const float *w_scale, hipStream_t st);
+hipError_t launch_apply(const LaunchCfg &cfg, BfHeader *blk, int n_items, const PlanDev &pd,
+                        hipStream_t st);
 
 // Workgroups of the apply kernel that fit on one CU at once.
 int apply_occupancy(int prec, int schedule, bool vec16);

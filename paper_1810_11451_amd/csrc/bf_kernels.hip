@@ -442,46 +442,485 @@ __global__ __launch_bounds__(kThreads) void apply_fp32_stream(BfHeader *__restri
     }
 }
 
-size_t lp_w_bytes(int) { return 0; }
+// ---------------------------------------------------------------------------
+// 16-bit forms: FP16 / BF16, plain and 2-term split.
+//
+// The same real GEMM as the FP32 form, on v_mfma_f32_32x32x16_{f16,bf16}:
+// one instruction covers K = 16 real indices, i.e. 8 flows x (re, im).  In
+// step t, operand slot s of lane l (row or column l % 32, half h = l / 32)
+// holds K index (flow 8t + 4h + s / 2, part s % 2).  A and B use the same
+// assignment, so the instruction sums over exactly these K indices.
+//
+// Scaling (exact, powers of two): W is stored times 2^-eW (plan time, eW
+// from the largest |Re|, |Im| of that W) and each S times 2^-eS (eS from
+// the largest |Re|, |Im| of that S, found in the kernel), so operands are
+// near 1 and far from FP16's range limits.  Split forms store
+//   hi = RN(x),  lo = RN((x - hi) * 2^sh),  sh = 11 (FP16) or 8 (BF16),
+// which keeps lo out of FP16's subnormal range; hi*hi and the cross terms
+// hi*lo + lo*hi use separate FP32 accumulators, lo*lo is dropped, and
+//   R = 2^(eW + eS) * (C_hh + 2^-sh * C_cross).
 
-hipError_t launch_w_transform_lp(const float2 *, int, int, int, void *, float *, hipStream_t)
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+typedef __bf16 b8v __attribute__((ext_vector_type(8)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const u4v g_cu4v;
+
+constexpr int kLpFlowsMax = ((kFMax + kLpFlows - 1) / kLpFlows) * kLpFlows;   // 40
+constexpr int kLpChunksMax = kLpFlowsMax / kLpFlows;                            // 5
+constexpr int kLpPitch = kLpFlowsMax + 4;   // dwords per LDS column: 8 lanes cover all banks
+
+template <bool kBf16>
+struct Lp;
+template <>
+struct Lp<false> {
+    typedef _Float16 T;
+    static constexpr int kShift = 11;
+    __device__ static floatx16 mfma(u4v a, u4v b, floatx16 c)
+    {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(h8v, a),
+                                                      __builtin_bit_cast(h8v, b), c, 0, 0, 0);
+    }
+};
+template <>
+struct Lp<true> {
+    typedef __bf16 T;
+    static constexpr int kShift = 8;
+    __device__ static floatx16 mfma(u4v a, u4v b, floatx16 c)
+    {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(b8v, a),
+                                                       __builtin_bit_cast(b8v, b), c, 0, 0, 0);
+    }
+};
+
+template <bool kBf16>
+__device__ __forceinline__ unsigned short to16(float x)
 {
-    return hipErrorNotSupported;
+    return __builtin_bit_cast(unsigned short, (typename Lp<kBf16>::T)x);
+}
+template <bool kBf16>
+__device__ __forceinline__ float from16(unsigned short b)
+{
+    return (float)__builtin_bit_cast(typename Lp<kBf16>::T, b);
+}
+// hi and lo (scaled by 2^kShift) 16-bit codes of x.
+template <bool kBf16>
+__device__ __forceinline__ void split16(float x, unsigned short &hi, unsigned short &lo)
+{
+    hi = to16<kBf16>(x);
+    lo = to16<kBf16>((x - from16<kBf16>(hi)) * (float)(1 << Lp<kBf16>::kShift));
+}
+
+// Exponent e with 2^e <= m < 2^(e+1) for the bit pattern m of a positive
+// float (0 for m == 0), clamped so that 2^-e is a normal float.
+__device__ __forceinline__ int exp_of_bits(uint32_t m)
+{
+    if (m == 0)
+        return 0;
+    const int e = (int)(m >> 23) - 127;
+    return e < -126 ? -126 : (e > 126 ? 126 : e);
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+}
+
+// Plan time: one block per W.  Layout per W and part (hi, lo):
+// [kWaves][chunks][64 lanes][8 x 16-bit], slot s of lane l in step t being
+// real row m = l % 32 of the wave (antenna 16 wave + m / 2, c = m % 2) and
+// K index (flow 8t + 4(l / 32) + s / 2, part q = s % 2):
+//   (c, q) = (0, 0): Wr   (0, 1): -Wi   (1, 0): Wi   (1, 1): Wr.
+template <bool kBf16>
+__global__ __launch_bounds__(256) void w_transform_lp_kernel(const float2 *__restrict__ w, int f_max,
+                                                             int chunks,
+                                                             unsigned short *__restrict__ hi,
+                                                             unsigned short *__restrict__ lo,
+                                                             int *__restrict__ w_exp)
+{
+    __shared__ uint32_t wmax[kThreads / 64];
+    const size_t wi = blockIdx.x;
+    const float2 *W = w + wi * kM * (size_t)f_max;
+    uint32_t m = 0;
+    for (int e = threadIdx.x; e < kM * f_max; e += blockDim.x) {
+        const float2 v = W[e];
+        m = max(m, max(__float_as_uint(v.x) & 0x7fffffffu, __float_as_uint(v.y) & 0x7fffffffu));
+    }
+    m = wave_max_u32(m);
+    if ((threadIdx.x & 63) == 0)
+        wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    m = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
+    const int ew = exp_of_bits(m);
+    const float scale = __builtin_amdgcn_ldexpf(1.0f, -ew);
+    if (threadIdx.x == 0)
+        w_exp[wi] = ew;
+    const size_t per_w = (size_t)kWaves * chunks * 64 * 8;
+    for (size_t idx = threadIdx.x; idx < per_w; idx += blockDim.x) {
+        const int s = (int)(idx % 8);
+        const int lane = (int)((idx / 8) % 64);
+        const int t = (int)((idx / 512) % chunks);
+        const int wave = (int)(idx / (512 * (size_t)chunks));
+        const int mrow = lane & 31;
+        const int i = 16 * wave + mrow / 2;
+        const int c = mrow & 1;
+        const int q = s & 1;
+        const int k = kLpFlows * t + 4 * (lane >> 5) + (s >> 1);
+        float x = 0.f;
+        if (k < f_max) {
+            const float2 v = W[(size_t)i * f_max + k];
+            x = c == 0 ? (q == 0 ? v.x : -v.y) : (q == 0 ? v.y : v.x);
+        }
+        unsigned short h, l;
+        split16<kBf16>(x * scale, h, l);
+        hi[wi * per_w + idx] = h;
+        if (lo)
+            lo[wi * per_w + idx] = l;
+    }
+}
+
+hipError_t launch_w_transform_lp(const float2 *w_dev, int n_w, int f_max, bool bf16, void *hi,
+                                 void *lo, int *w_exp, hipStream_t st)
+{
+    const int chunks = lp_chunks(f_max);
+    if (n_w <= 0 || chunks == 0)
+        return hipSuccess;
+    if (bf16)
+        hipLaunchKernelGGL(w_transform_lp_kernel<true>, dim3(n_w), dim3(256), 0, st, w_dev, f_max,
+                           chunks, static_cast<unsigned short *>(hi),
+                           static_cast<unsigned short *>(lo), w_exp);
+    else
+        hipLaunchKernelGGL(w_transform_lp_kernel<false>, dim3(n_w), dim3(256), 0, st, w_dev, f_max,
+                           chunks, static_cast<unsigned short *>(hi),
+                           static_cast<unsigned short *>(lo), w_exp);
+    return hipGetLastError();
+}
+
+// Largest |Re|, |Im| (as float bits) over the valid part of staged S registers.
+template <bool kVec16>
+__device__ __forceinline__ uint32_t absmax_bits(const SRegs<kVec16> &r, int f)
+{
+    const int tid = threadIdx.x;
+    uint32_t m = 0;
+    if constexpr (kVec16) {
+        const int chunks = f * (kB / 2);
+#pragma unroll
+        for (int u = 0; u < kChunks16; ++u) {
+            if (tid + u * kThreads < chunks) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    m = max(m, __float_as_uint(r.v[u][e]) & 0x7fffffffu);
+            }
+        }
+    } else {
+        const int elems = f * kB;
+#pragma unroll
+        for (int u = 0; u < kChunks8; ++u) {
+            if (tid + u * kThreads < elems) {
+                m = max(m, __float_as_uint(r.v[u][0]) & 0x7fffffffu);
+                m = max(m, __float_as_uint(r.v[u][1]) & 0x7fffffffu);
+            }
+        }
+    }
+    return m;
+}
+
+// Writes one complex value (scaled) as packed 16-bit (re, im) codes.
+template <bool kBf16, bool kSplit>
+__device__ __forceinline__ void put_c16(uint32_t *__restrict__ bhi, uint32_t *__restrict__ blo,
+                                        int col, int k, float re, float im)
+{
+    unsigned short rh, rl, ih, il;
+    split16<kBf16>(re, rh, rl);
+    split16<kBf16>(im, ih, il);
+    bhi[col * kLpPitch + k] = (uint32_t)rh | ((uint32_t)ih << 16);
+    if (kSplit)
+        blo[col * kLpPitch + k] = (uint32_t)rl | ((uint32_t)il << 16);
+}
+
+// Stages S (already in registers) into the transposed 16-bit LDS tile:
+// column j holds flows 0..39 of column j as packed (re, im).  Flows
+// [f, 8 ceil(f / 8)) are cleared.
+template <bool kBf16, bool kSplit, bool kVec16>
+__device__ __forceinline__ void put_s_lp(uint32_t *__restrict__ bhi, uint32_t *__restrict__ blo,
+                                         const SRegs<kVec16> &r, int f, float scale)
+{
+    const int tid = threadIdx.x;
+    if constexpr (kVec16) {
+        const int chunks = f * (kB / 2);
+#pragma unroll
+        for (int u = 0; u < kChunks16; ++u) {
+            const int c = tid + u * kThreads;
+            if (c < chunks) {
+                const int row = c / (kB / 2);
+                const int col = 2 * (c - row * (kB / 2));
+                put_c16<kBf16, kSplit>(bhi, blo, col, row, r.v[u][0] * scale, r.v[u][1] * scale);
+                put_c16<kBf16, kSplit>(bhi, blo, col + 1, row, r.v[u][2] * scale, r.v[u][3] * scale);
+            }
+        }
+    } else {
+        const int elems = f * kB;
+#pragma unroll
+        for (int u = 0; u < kChunks8; ++u) {
+            const int c = tid + u * kThreads;
+            if (c < elems) {
+                const int row = c / kB;
+                const int col = c - row * kB;
+                put_c16<kBf16, kSplit>(bhi, blo, col, row, r.v[u][0] * scale, r.v[u][1] * scale);
+            }
+        }
+    }
+    const int fpad = (f + kLpFlows - 1) & ~(kLpFlows - 1);
+    const int gap = fpad - f;
+    if (gap > 0) {
+        for (int e = tid; e < kB * gap; e += kThreads) {
+            const int col = e / gap;
+            const int k = f + (e - col * gap);
+            bhi[col * kLpPitch + k] = 0u;
+            if (kSplit)
+                blo[col * kLpPitch + k] = 0u;
+        }
+    }
+}
+
+template <bool kSplit>
+struct LpA {
+    u4v hi[kLpChunksMax];
+    u4v lo[kSplit ? kLpChunksMax : 1];
+};
+
+template <bool kSplit>
+__device__ __forceinline__ void load_a_lp(LpA<kSplit> &a, const PlanDev &pd, int w, int wave, int lane)
+{
+    const size_t base = (size_t)w * pd.lp_stride + (size_t)wave * pd.lp_chunks * 64 + lane;
+    const g_cu4v *h = (const g_cu4v *)pd.lp_hi + base;
+#pragma unroll
+    for (int t = 0; t < kLpChunksMax; ++t)
+        a.hi[t] = h[min(t, pd.lp_chunks - 1) * 64];
+    if constexpr (kSplit) {
+        const g_cu4v *l = (const g_cu4v *)pd.lp_lo + base;
+#pragma unroll
+        for (int t = 0; t < kLpChunksMax; ++t)
+            a.lo[t] = l[min(t, pd.lp_chunks - 1) * 64];
+    }
+}
+
+// Matrix-core steps of one product from the staged 16-bit tile, then the
+// rescaled result to R.
+template <bool kBf16, bool kSplit>
+__device__ __forceinline__ void contract_store_lp(const uint32_t *__restrict__ bhi,
+                                                  const uint32_t *__restrict__ blo,
+                                                  const LpA<kSplit> &a, int f, int eo,
+                                                  float2 *__restrict__ R, float2 *__restrict__ sink,
+                                                  int wave, int lane)
+{
+    const int h = lane >> 5;
+    const int n = lane & 31;
+    const int tc = (f + kLpFlows - 1) / kLpFlows;
+    floatx16 hh0 = {}, hh1 = {}, cr0 = {}, cr1 = {};
+#pragma unroll
+    for (int t = 0; t < kLpChunksMax; ++t) {
+        if (t < tc) {
+            const int k0 = kLpFlows * t + 4 * h;
+            const u4v b0 = *reinterpret_cast<const u4v *>(bhi + n * kLpPitch + k0);
+            const u4v b1 = *reinterpret_cast<const u4v *>(bhi + (32 + n) * kLpPitch + k0);
+            hh0 = Lp<kBf16>::mfma(a.hi[t], b0, hh0);
+            hh1 = Lp<kBf16>::mfma(a.hi[t], b1, hh1);
+            if constexpr (kSplit) {
+                const u4v l0 = *reinterpret_cast<const u4v *>(blo + n * kLpPitch + k0);
+                const u4v l1 = *reinterpret_cast<const u4v *>(blo + (32 + n) * kLpPitch + k0);
+                cr0 = Lp<kBf16>::mfma(a.hi[t], l0, cr0);
+                cr1 = Lp<kBf16>::mfma(a.hi[t], l1, cr1);
+                cr0 = Lp<kBf16>::mfma(a.lo[t], b0, cr0);
+                cr1 = Lp<kBf16>::mfma(a.lo[t], b1, cr1);
+            }
+        }
+    }
+    floatx16 o0, o1;
+    const float back = __builtin_amdgcn_ldexpf(1.0f, -Lp<kBf16>::kShift);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        float v0 = hh0[r], v1 = hh1[r];
+        if constexpr (kSplit) {
+            v0 = __builtin_fmaf(cr0[r], back, v0);
+            v1 = __builtin_fmaf(cr1[r], back, v1);
+        }
+        o0[r] = __builtin_amdgcn_ldexpf(v0, eo);
+        o1[r] = __builtin_amdgcn_ldexpf(v1, eo);
+    }
+    store_r(R, sink, wave, lane, o0, o1);
+}
+
+constexpr int kLpTile = 64 * kLpPitch;   // dwords per staged 16-bit tile
+
+// kSched 0 for the 16-bit forms: one product per workgroup.
+template <bool kBf16, bool kSplit, bool kVec16>
+__global__ __launch_bounds__(kThreads) void apply_lp_single(BfHeader *__restrict__ blk,
+                                                            const BfItem *__restrict__ items,
+                                                            int n_items, PlanDev pd)
+{
+    __shared__ uint32_t lds_hi[kLpTile];
+    __shared__ uint32_t lds_lo[kSplit ? kLpTile : 1];
+    __shared__ uint32_t smax[kWaves];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    float2 *sink = sink_of(blk);
+    const int it = xcd_contiguous(blockIdx.x, n_items);
+    const BfItem d = items[it];
+    SRegs<kVec16> sr;
+    load_s<kVec16>(sr, d.f > 0 ? d.S : sink, d.f);
+    LpA<kSplit> a;
+    int ew = 0;
+    if (pd.lp_chunks > 0) {
+        load_a_lp<kSplit>(a, pd, d.w_id, wave, lane);
+        ew = pd.lp_exp[d.w_id];
+    }
+    const uint32_t m = wave_max_u32(absmax_bits<kVec16>(sr, d.f));
+    if (lane == 0)
+        smax[wave] = m;
+    __syncthreads();
+    const int es = exp_of_bits(max(max(smax[0], smax[1]), max(smax[2], smax[3])));
+    put_s_lp<kBf16, kSplit, kVec16>(lds_hi, lds_lo, sr, d.f, __builtin_amdgcn_ldexpf(1.0f, -es));
+    __syncthreads();
+    contract_store_lp<kBf16, kSplit>(lds_hi, lds_lo, a, d.f, ew + es, d.R, sink, wave, lane);
+}
+
+// kSched 2 for the 16-bit forms: persistent, static share, next S
+// prefetched during the current product's matrix-core steps (as
+// apply_fp32_stream, with an extra barrier for the per-product scale).
+template <bool kBf16, bool kSplit, bool kVec16>
+__global__ __launch_bounds__(kThreads) void apply_lp_stream(BfHeader *__restrict__ blk,
+                                                            const BfItem *__restrict__ items,
+                                                            int n_items, PlanDev pd)
+{
+    __shared__ uint32_t lds_hi[2][kLpTile];
+    __shared__ uint32_t lds_lo[2][kSplit ? kLpTile : 1];
+    __shared__ uint32_t smax[2][kWaves];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    float2 *sink = sink_of(blk);
+
+    const int G = gridDim.x;
+    const int X = G < 8 ? G : 8;
+    const int x = blockIdx.x % X;
+    const int j = blockIdx.x / X;
+    const int nb = G / X + (x < G % X ? 1 : 0);
+    const int q = n_items / X, r = n_items % X;
+    const int lo = x * q + (x < r ? x : r);
+    const int hi = lo + q + (x < r ? 1 : 0);
+
+    int it = lo + j;
+    if (it >= hi)
+        return;
+    const int last = hi - 1;
+    DescV d = uniform(load_desc_v(items, it));
+    int nxt = it + nb;
+    DescV dn = load_desc_v(items, min(nxt, last));
+    SRegs<kVec16> sr;
+    load_s<kVec16>(sr, d.f > 0 ? d.S : sink, d.f);
+    prime_store_count(sink, lane);
+    LpA<kSplit> a;
+    int cur_w = -1;
+    int ew = 0;
+    int buf = 0;
+    while (true) {
+        const uint32_t m = wave_max_u32(absmax_bits<kVec16>(sr, d.f));
+        if (lane == 0)
+            smax[buf][wave] = m;
+        if (d.w_id != cur_w && pd.lp_chunks > 0) {
+            cur_w = d.w_id;
+            load_a_lp<kSplit>(a, pd, cur_w, wave, lane);
+            ew = pd.lp_exp[cur_w];
+            wait_vmem_all();
+        }
+        const int nn = nxt + nb;
+        const DescV dnn = load_desc_v(items, min(nn, last));
+        __syncthreads();
+        const int es = exp_of_bits(max(max(smax[buf][0], smax[buf][1]), max(smax[buf][2], smax[buf][3])));
+        put_s_lp<kBf16, kSplit, kVec16>(lds_hi[buf], lds_lo[buf], sr, d.f,
+                                        __builtin_amdgcn_ldexpf(1.0f, -es));
+        __syncthreads();
+        const bool more = nxt < hi;
+        const DescV du = uniform(dn);
+        load_s<kVec16>(sr, du.f > 0 ? du.S : sink, du.f);
+        contract_store_lp<kBf16, kSplit>(lds_hi[buf], lds_lo[buf], a, d.f, ew + es, d.R, sink,
+                                         wave, lane);
+        if (!more)
+            break;
+        d = du;
+        dn = dnn;
+        nxt = nn;
+        buf ^= 1;
+    }
+}
+
+static const BfItem *items_of(BfHeader *blk)
+{
+    return reinterpret_cast<const BfItem *>(reinterpret_cast<const char *>(blk) +
+                                            sizeof(BfHeader) + kSinkBytes);
 }
 
 template <bool kVec16>
 static hipError_t launch_fp32_t(const LaunchCfg &cfg, BfHeader *blk, int n_items,
-                                const float2 *a_pool, int a_w_stride, int pairs, hipStream_t st)
+                                const PlanDev &pd, hipStream_t st)
 {
-    const BfItem *items = reinterpret_cast<const BfItem *>(reinterpret_cast<const char *>(blk) +
-                                                           sizeof(BfHeader) + kSinkBytes);
+    const BfItem *items = items_of(blk);
     switch (cfg.schedule) {
     case 0:
         hipLaunchKernelGGL(apply_fp32_single<kVec16>, dim3(n_items), dim3(kThreads), 0, st, blk,
-                           items, n_items, a_pool, a_w_stride, pairs);
+                           items, n_items, pd.a_fp32, pd.a_fp32_stride, pd.pairs);
         break;
     case 1:
         hipLaunchKernelGGL(apply_fp32_claim<kVec16>, dim3(cfg.grid), dim3(kThreads), 0, st, blk,
-                           items, n_items, a_pool, a_w_stride, pairs);
+                           items, n_items, pd.a_fp32, pd.a_fp32_stride, pd.pairs);
         break;
     default:
         hipLaunchKernelGGL(apply_fp32_stream<kVec16>, dim3(cfg.grid), dim3(kThreads), 0, st, blk,
-                           items, n_items, a_pool, a_w_stride, pairs);
+                           items, n_items, pd.a_fp32, pd.a_fp32_stride, pd.pairs);
         break;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_apply(const LaunchCfg &cfg, BfHeader *blk, int n_items, const void *a_pool,
-                        size_t a_w_stride, int pairs, const float *, hipStream_t st)
+template <bool kBf16, bool kSplit, bool kVec16>
+static hipError_t launch_lp_t(const LaunchCfg &cfg, BfHeader *blk, int n_items, const PlanDev &pd,
+                              hipStream_t st)
+{
+    const BfItem *items = items_of(blk);
+    if (cfg.schedule == 0)
+        hipLaunchKernelGGL((apply_lp_single<kBf16, kSplit, kVec16>), dim3(n_items), dim3(kThreads), 0,
+                           st, blk, items, n_items, pd);
+    else
+        hipLaunchKernelGGL((apply_lp_stream<kBf16, kSplit, kVec16>), dim3(cfg.grid), dim3(kThreads),
+                           0, st, blk, items, n_items, pd);
+    return hipGetLastError();
+}
+
+template <bool kBf16, bool kSplit>
+static hipError_t launch_lp_v(const LaunchCfg &cfg, BfHeader *blk, int n_items, const PlanDev &pd,
+                              hipStream_t st)
+{
+    return cfg.vec16 ? launch_lp_t<kBf16, kSplit, true>(cfg, blk, n_items, pd, st)
+                     : launch_lp_t<kBf16, kSplit, false>(cfg, blk, n_items, pd, st);
+}
+
+hipError_t launch_apply(const LaunchCfg &cfg, BfHeader *blk, int n_items, const PlanDev &pd,
+                        hipStream_t st)
 {
     if (n_items <= 0 || cfg.grid <= 0)
         return hipSuccess;
-    if (cfg.prec != BF_FP32)
-        return hipErrorNotSupported;
-    const float2 *a = static_cast<const float2 *>(a_pool);
-    return cfg.vec16 ? launch_fp32_t<true>(cfg, blk, n_items, a, (int)a_w_stride, pairs, st)
-                     : launch_fp32_t<false>(cfg, blk, n_items, a, (int)a_w_stride, pairs, st);
+    switch (cfg.prec) {
+    case BF_FP32:
+        return cfg.vec16 ? launch_fp32_t<true>(cfg, blk, n_items, pd, st)
+                         : launch_fp32_t<false>(cfg, blk, n_items, pd, st);
+    case BF_FP16: return launch_lp_v<false, false>(cfg, blk, n_items, pd, st);
+    case BF_BF16: return launch_lp_v<true, false>(cfg, blk, n_items, pd, st);
+    case BF_FP16X2: return launch_lp_v<false, true>(cfg, blk, n_items, pd, st);
+    case BF_BF16X2: return launch_lp_v<true, true>(cfg, blk, n_items, pd, st);
+    }
+    return hipErrorNotSupported;
 }
 
 template <typename K>
@@ -492,10 +931,25 @@ static int occ_of(K kernel)
     return (e == hipSuccess && blocks > 0) ? blocks : 1;
 }
 
+template <bool kBf16, bool kSplit>
+static int occ_lp(int schedule, bool vec16)
+{
+    if (schedule == 0)
+        return vec16 ? occ_of(apply_lp_single<kBf16, kSplit, true>)
+                     : occ_of(apply_lp_single<kBf16, kSplit, false>);
+    return vec16 ? occ_of(apply_lp_stream<kBf16, kSplit, true>)
+                 : occ_of(apply_lp_stream<kBf16, kSplit, false>);
+}
+
 int apply_occupancy(int prec, int schedule, bool vec16)
 {
-    if (prec != BF_FP32)
-        return 1;
+    switch (prec) {
+    case BF_FP16: return occ_lp<false, false>(schedule, vec16);
+    case BF_BF16: return occ_lp<true, false>(schedule, vec16);
+    case BF_FP16X2: return occ_lp<false, true>(schedule, vec16);
+    case BF_BF16X2: return occ_lp<true, true>(schedule, vec16);
+    default: break;
+    }
     switch (schedule) {
     case 0: return vec16 ? occ_of(apply_fp32_single<true>) : occ_of(apply_fp32_single<false>);
     case 1: return vec16 ? occ_of(apply_fp32_claim<true>) : occ_of(apply_fp32_claim<false>);

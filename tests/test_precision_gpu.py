@@ -1,0 +1,102 @@
+"""GPU parity of the 16-bit forms against the FP64 oracle.
+
+Bars (relative Frobenius error per product):
+* split forms (FP16x2, BF16x2): 2e-5, the bar the FP32-recovery target sets;
+* plain forms: reported; the test bounds them by 4u*sqrt(2) with u the
+  unit roundoff of the 16-bit type (2^-11 FP16, 2^-8 BF16): each product
+  term carries at most two relative roundings of size u, and a
+  normwise bound of 2u*sqrt(2) doubled leaves room for the FP32
+  accumulation and the unlucky alignment of a few large terms.
+Exact-integer inputs (Gaussian-integer W, odd QAM levels) are exact in
+every form, so there the comparison is bitwise.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_util import announce, rel_errors, require_gpu, run_batch
+from oracle import oracle as orc
+from paper_1810_11451_amd import bf
+from paper_1810_11451_amd import workloads as wl
+from paper_1810_11451_amd.device import DeviceBatch
+
+pytestmark = pytest.mark.gpu
+
+LP = {"fp16": bf.BF_FP16, "bf16": bf.BF_BF16, "fp16x2": bf.BF_FP16X2, "bf16x2": bf.BF_BF16X2}
+U = {"fp16": 2.0 ** -11, "bf16": 2.0 ** -8}
+BAR = {"fp16x2": 2e-5, "bf16x2": 2e-5,
+       "fp16": 4 * U["fp16"] * math.sqrt(2), "bf16": 4 * U["bf16"] * math.sqrt(2)}
+VARIANTS = {"one-per-wg": (0, 0, 0), "stream": (2, 0, 1), "stream-2-asgiven": (2, 2, 0)}
+
+
+@pytest.mark.parametrize("form", sorted(LP))
+def test_exact_integers_bitwise(form):
+    rng = np.random.default_rng(601)
+    b = wl.exact_integer_batch(rng, 150, 4)
+    announce(f"exact integers form={form}")
+    R = run_batch(b, prec=LP[form])
+    ref = orc.apply(b)
+    assert np.array_equal(R.astype(np.complex128), ref)
+
+
+@pytest.mark.parametrize("vname", sorted(VARIANTS))
+@pytest.mark.parametrize("form", sorted(LP))
+def test_ragged_random(form, vname):
+    rng = np.random.default_rng(602)
+    f_values = np.repeat(np.arange(0, 37), 2)
+    b = wl.random_batch(rng, len(f_values), 5, f_values=f_values, dist="qam")
+    announce(f"ragged form={form} variant={vname}")
+    R = run_batch(b, prec=LP[form], variant=VARIANTS[vname])
+    err, _ = rel_errors(b, R)
+    nz = b.f > 0
+    assert np.all(R[~nz] == 0)
+    assert np.max(err[nz]) <= BAR[form], f"{form}: max rel err {np.max(err[nz]):.3g}"
+
+
+@pytest.mark.parametrize("form", sorted(LP))
+def test_gains_do_not_change_accuracy(form):
+    """S scaled by gains 1e-3 .. 1e3: the per-product power-of-two scaling
+    keeps every 16-bit operand in range, so the error stays at the bar."""
+    rng = np.random.default_rng(603)
+    base = wl.qam256(rng, (36, wl.B))
+    gains = np.array([1e-3, 3.7e-2, 1.0, 29.0, 1e3])
+    W = wl.unit_norm_pool(rng, 1, 36)
+    blocks = [base * g for g in gains]
+    b = wl._pack("gains", W, np.zeros(len(gains), np.int32), np.full(len(gains), 36), blocks)
+    announce(f"gains form={form}")
+    R = run_batch(b, prec=LP[form])
+    err, _ = rel_errors(b, R)
+    assert np.max(err) <= BAR[form], f"{form}: {err}"
+
+
+def test_all_forms_from_one_plan():
+    require_gpu()
+    rng = np.random.default_rng(604)
+    b = wl.random_batch(rng, 64, 3, dist="qam")
+    plan = bf.bf_plan_create(b.W, bf.PREC_ALL)
+    assert bf.bf_plan_info(plan)[2] == bf.PREC_ALL
+    ref = orc.apply(b)
+    nz = b.f > 0
+    for name, p in [("fp32", bf.BF_FP32)] + sorted(LP.items()):
+        announce(f"one plan, form={name}")
+        R = run_batch(b, prec=p, plan=plan)
+        err = orc.rel_frobenius(R, ref)
+        bar = 2e-6 if name == "fp32" else BAR[name]
+        assert np.max(err[nz]) <= bar, name
+    plan.close()
+
+
+@pytest.mark.parametrize("form", sorted(LP))
+def test_gain_workload_sampled(form):
+    """16384 products of 64x36 by 36x60 with gains 10^U(-3,3), the launch the
+    benchmark times; 512 seeded products checked."""
+    b = wl.config4()
+    announce(f"gain workload n={b.n} form={form}")
+    R = run_batch(b, prec=LP[form])
+    assert not np.any(np.isnan(R.view(np.float32)))
+    items = np.random.default_rng(11).choice(b.n, size=512, replace=False)
+    err, _ = rel_errors(b, R, items=items)
+    print(f"[{form}] rel err min {err.min():.3g} p50 {np.median(err):.3g} "
+          f"p99 {np.percentile(err, 99):.3g} max {err.max():.3g}", flush=True)
+    assert np.max(err) <= BAR[form]
