@@ -40,7 +40,7 @@ PEAK_FP32_TFLOPS = 157.3
 PEAK_LP_TFLOPS = 2500.0
 PRECS = {"fp32": bf.BF_FP32, "fp16": bf.BF_FP16, "bf16": bf.BF_BF16,
          "fp16x2": bf.BF_FP16X2, "bf16x2": bf.BF_BF16X2}
-CONFIGS = {1: wl.config1, 2: wl.config2, 3: wl.config3, 4: wl.config4}
+CONFIGS = {1: wl.config1, 2: wl.config2, 3: wl.config3, 4: wl.config4, 5: None}
 KERNEL_SOURCES = ["paper_1810_11451_amd/csrc/bf_kernels.hip",
                   "paper_1810_11451_amd/csrc/bf_internal.h"]
 
@@ -100,6 +100,96 @@ def load_traffic(workload_key: str):
     return entry.get("traffic_bytes_per_launch")
 
 
+def _qam_on_device(torch, n, seed):
+    """n normalised 256-QAM symbols generated on the device (seeded)."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    lv = torch.randint(0, 16, (2, n), generator=g, device="cuda", dtype=torch.int32)
+    x = ((2 * lv - 15).to(torch.float32) / float(np.sqrt(170.0)))
+    return torch.complex(x[0], x[1])
+
+
+def serve_bench(args, torch) -> dict:
+    """Serving workload: Poisson arrivals of requests (W id from a pool of
+    1024, f ~ U{1..36}, 1..64 S blocks of normalised 256-QAM), admission by
+    an HBM budget, 0.5 ms per-request deadline.  Offered load = half the
+    measured closed-loop capacity of the FP32 form (submit path included)."""
+    rng = np.random.default_rng(5)
+    n_w, n_req = 1024, args.requests
+    W = wl.unit_norm_pool(rng, n_w, wl.F_MAX)
+    split = PRECS[args.serve_split]
+    plan = bf.bf_plan_create(W, bf.BF_PREC_BIT(bf.BF_FP32) | bf.BF_PREC_BIT(split))
+    w_ids = rng.integers(0, n_w, n_req).astype(np.int32)
+    f = rng.integers(1, wl.F_MAX + 1, n_req).astype(np.int32)
+    ns = rng.integers(1, 65, n_req).astype(np.int32)
+    s_elems = 1 << 27                                   # 1 GiB S arena
+    S = _qam_on_device(torch, s_elems, 5)
+    need = f.astype(np.int64) * ns * wl.B
+    s_off = (rng.integers(0, s_elems - need.max(), n_req) // 2 * 2).astype(np.int64)
+    budget = args.budget_gib << 30
+    r_blocks = (2 * budget) // (wl.M * wl.B * 8)        # R ring twice the budget
+    R = torch.empty((int(r_blocks), wl.M, wl.B), dtype=torch.complex64, device="cuda")
+    r_off = np.zeros(n_req, np.int64)
+    pos = 0
+    for i in range(n_req):
+        if pos + ns[i] > r_blocks:
+            pos = 0
+        r_off[i] = pos
+        pos += ns[i]
+    reqs = np.zeros(n_req, bf.REQUEST_DTYPE)
+    reqs["w_id"], reqs["f"], reqs["n_s"] = w_ids, f, ns
+    reqs["S"] = S.data_ptr() + s_off * 8
+    reqs["R"] = R.data_ptr() + r_off * (wl.M * wl.B * 8)
+    flops_req = 8 * wl.M * wl.B * f.astype(np.int64) * ns
+    bytes_req = ns.astype(np.int64) * (f.astype(np.int64) * wl.B * 8 + wl.M * wl.B * 8)
+
+    def run(prec, t_off, n, budget_bytes, streams):
+        with bf.bf_server_create(plan, hbm_budget_bytes=budget_bytes, deadline_us=500,
+                                 n_streams=streams, max_batch_items=16384, prec=prec) as srv:
+            done, busy = bf.loadgen_replay(srv, reqs[:n].copy(), t_off[:n])
+            st = bf.bf_server_stats_get(srv)
+        assert np.all(done["status"] == bf.BF_OK), "serving run reported errors"
+        return done, busy, st
+
+    def summary(done, busy, st, n):
+        k0 = n // 100                                    # first 1% is warm-up
+        d = done[k0:n]
+        lat = (d["t_done_ns"] - d["t_arrival_ns"]) / 1e3
+        queue = (d["t_launch_ns"] - d["t_arrival_ns"]) / 1e3
+        span = (done["t_done_ns"].max() - done["t_arrival_ns"].min()) / 1e9
+        return {"requests": int(n), "p50_us": round(float(np.percentile(lat, 50)), 1),
+                "p99_us": round(float(np.percentile(lat, 99)), 1),
+                "queue_p50_us": round(float(np.percentile(queue, 50)), 1),
+                "deadline_miss_rate": round(float(np.mean(d["deadline_missed"])), 5),
+                "complex_gflops": round(float(flops_req[:n].sum()) / span / 1e9, 1),
+                "gbs": round(float(bytes_req[:n].sum()) / span / 1e9, 1),
+                "req_per_s": round(n / span, 1), "launches": st["launches"],
+                "peak_inflight_mb": round(st["peak_inflight_bytes"] / 2 ** 20, 1),
+                "queue_full_retries": busy}
+
+    streams = args.streams
+    n_cap = min(n_req, 20000)
+    run(bf.BF_FP32, np.zeros(n_cap, np.int64), min(n_cap, 2000), budget, streams)   # warm-up
+    done, busy, st = run(bf.BF_FP32, np.zeros(n_cap, np.int64), n_cap, budget, streams)
+    span = (done["t_done_ns"].max() - done["t_arrival_ns"].min()) / 1e9
+    capacity = n_cap / span
+    lam = 0.5 * capacity
+    gaps = rng.exponential(1e9 / lam, n_req)
+    t_off = np.cumsum(gaps).astype(np.int64)
+    out = {"capacity_req_per_s": round(capacity, 1),
+           "capacity_gbs": round(float(bytes_req[:n_cap].sum()) / span / 1e9, 1),
+           "offered_req_per_s": round(lam, 1),
+           "offered_gbs": round(lam * float(bytes_req.mean()) / 1e9, 1)}
+    for name, prec in (("fp32", bf.BF_FP32), (args.serve_split, split)):
+        print(f"[bench] serving {name} at {lam:.0f} req/s", file=sys.stderr, flush=True)
+        out[name] = summary(*run(prec, t_off, n_req, budget, streams), n_req)
+    n_small = min(n_req, 20000)
+    print("[bench] serving fp32 with a 16 MiB budget", file=sys.stderr, flush=True)
+    out["fp32_budget_16mib"] = summary(*run(bf.BF_FP32, t_off, n_small, 16 << 20, streams), n_small)
+    plan.close()
+    return out
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +201,11 @@ def main(argv=None) -> int:
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="tune the variant before timing")
+    ap.add_argument("--requests", type=int, default=200000, help="serving: requests replayed")
+    ap.add_argument("--budget-gib", type=int, default=16, help="serving: HBM budget")
+    ap.add_argument("--streams", type=int, default=2, help="serving: device streams")
+    ap.add_argument("--serve-split", default="fp16x2", choices=["fp16x2", "bf16x2", "fp16", "bf16"],
+                    help="serving: the 16-bit form compared with FP32")
     ap.add_argument("--variant", default=None,
                     help="force schedule:wg_per_cu:order (e.g. 2:3:1) instead of the plan table")
     args = ap.parse_args(argv)
@@ -128,6 +223,20 @@ def main(argv=None) -> int:
     from paper_1810_11451_amd.device import DeviceBatch
 
     torch.cuda.set_device(0)
+    if args.config == 5:
+        res = serve_bench(args, torch)
+        fp = res["fp32"]
+        out = {"metric": METRIC, "value": fp["complex_gflops"], "unit": "complex GFLOP/s",
+               "n_gpus": 1, "steps": fp["requests"], "warmup": 0,
+               "ms_per_step": round(1e3 / fp["req_per_s"], 6), "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+               "config": {"workload": "serving: Poisson requests, pool 1024 W 64x36, f~U{1..36}, "
+                                      "1..64 S of 256-QAM, 0.5 ms deadline",
+                          "budget_gib": args.budget_gib, "streams": args.streams},
+               "latency_us": {"p50": fp["p50_us"], "p99": fp["p99_us"]},
+               "serving": res}
+        print(json.dumps(out), flush=True)
+        return 0
     prec = PRECS[args.prec]
     batch = CONFIGS[args.config]()
     print(f"[bench] config {args.config}: {batch.name}, prec {args.prec}", file=sys.stderr, flush=True)

@@ -66,6 +66,7 @@ typedef enum { BF_FP32 = 0, BF_FP16 = 1, BF_BF16 = 2, BF_FP16X2 = 3, BF_BF16X2 =
 
 typedef struct bf_plan_s *bf_plan;
 typedef struct bf_graph_s *bf_graph;
+typedef struct bf_server_s *bf_server;
 
 /* ---- plan: the resident W pool --------------------------------------
  * W is constant across many products (Section III), so its preparation
@@ -153,6 +154,81 @@ bf_status bf_autotune(bf_plan plan, int32_t batch, const int32_t *w_ids, const i
                       void *hip_stream, bf_variant *best, float *best_us);
 bf_status bf_tune_save(bf_plan plan, const char *path);
 bf_status bf_tune_load(bf_plan plan, const char *path);
+
+/* ---- serving: continuous batching of arriving requests ----------------
+ * The pipeline of Section II runs its stages continuously on arriving
+ * signal; this is the request loop for the beamforming stage.  A request
+ * is (W id, f, n_s S blocks contiguous at S, n_s R blocks contiguous at
+ * R); the W pool stays resident in the plan.  bf_submit enqueues it and
+ * returns a ticket at once.  A batcher thread admits queued requests in
+ * arrival order while the S + R bytes of admitted, unfinished requests
+ * stay within hbm_budget_bytes, and packs the admitted requests into one
+ * launch whenever one of n_streams device streams is free; a launch is
+ * closed early when the running throughput estimate says a larger one
+ * would finish after its oldest member's deadline.  A completion thread
+ * reports each finished request through bf_poll and returns its bytes to
+ * the budget.  Requests that arrive while earlier launches run join the
+ * next launch, so device work of consecutive launches overlaps across
+ * the streams.  Results are the same as for bf_apply on each request
+ * alone: every product is computed independently, with the same kernels. */
+typedef struct {
+    uint64_t hbm_budget_bytes;  /* bound on S+R bytes of admitted, unfinished requests */
+    int64_t deadline_us;        /* per-request deadline after t_arrival (<= 0: none) */
+    int32_t n_streams;          /* device streams used round-robin, 1..8 */
+    int32_t max_batch_items;    /* upper bound on S blocks per launch */
+    int32_t queue_capacity;     /* submission queue slots (power of two) */
+    int32_t prec;               /* bf_prec used for every launch */
+} bf_server_cfg;
+
+typedef struct {
+    int32_t w_id;
+    int32_t f;
+    int32_t n_s;            /* number of S blocks, >= 1 */
+    int32_t reserved;
+    const void *S;          /* device, n_s contiguous f x 60 complex64 blocks */
+    void *R;                /* device, n_s contiguous 64 x 60 complex64 blocks */
+    uint64_t tag;           /* opaque, returned in the completion */
+    int64_t t_arrival_ns;   /* CLOCK_MONOTONIC arrival time (0: taken at submit) */
+} bf_request;
+
+typedef struct {
+    uint64_t ticket;
+    uint64_t tag;
+    int32_t status;          /* BF_OK or a bf_status */
+    int32_t deadline_missed; /* 1 if t_done > t_arrival + deadline */
+    int64_t t_arrival_ns;
+    int64_t t_submit_ns;     /* when bf_submit accepted it */
+    int64_t t_launch_ns;     /* when its launch was enqueued */
+    int64_t t_done_ns;       /* when its completion was observed */
+} bf_completion;
+
+typedef struct {
+    uint64_t submitted, admitted, completed, refused, launches, deadline_misses;
+    uint64_t inflight_bytes, peak_inflight_bytes, queued;
+} bf_server_stats;
+
+/* cfg may be NULL for defaults: 16 GiB budget, no deadline, 2 streams,
+ * 16384 items per launch, 65536 queue slots, FP32.  The plan must outlive
+ * the server and must have the precision form prepared.  Errors:
+ * BF_ERR_INVALID, BF_ERR_UNSUPPORTED, BF_ERR_OOM, BF_ERR_DEVICE. */
+bf_status bf_server_create(bf_server *out, bf_plan plan, const bf_server_cfg *cfg);
+/* Enqueue one request.  BF_ERR_INVALID for a bad request (also one larger
+ * than the whole budget), BF_ERR_BUSY if the queue is full.  One thread
+ * at a time may submit to a server. */
+bf_status bf_submit(bf_server server, const bf_request *req, uint64_t *ticket);
+/* Copy up to max completions into out, waiting up to timeout_us for the
+ * first (0: no wait, < 0: forever).  Returns the count (>= 0) or a
+ * bf_status (BF_ERR_TIMEOUT when nothing completed in time).  May be
+ * called from a thread other than the submitter. */
+int32_t bf_poll(bf_server server, bf_completion *out, int32_t max, int64_t timeout_us);
+bf_status bf_server_stats_get(bf_server server, bf_server_stats *out);
+/* Drains every submitted request, then stops the threads and frees.
+ * Completions not yet polled are discarded. */
+bf_status bf_server_destroy(bf_server server);
+/* CLOCK_MONOTONIC in nanoseconds (the clock of t_arrival_ns and t_done_ns). */
+int64_t bf_now_ns(void);
+
+
 
 /* ---- diagnostics ------------------------------------------------------ */
 const char *bf_status_str(bf_status s);

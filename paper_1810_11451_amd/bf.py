@@ -47,6 +47,29 @@ class bf_variant(ctypes.Structure):
         return (self.schedule, self.wg_per_cu, self.order)
 
 
+class bf_server_cfg(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("deadline_us", ctypes.c_int64),
+                ("n_streams", ctypes.c_int32), ("max_batch_items", ctypes.c_int32),
+                ("queue_capacity", ctypes.c_int32), ("prec", ctypes.c_int32)]
+
+
+class bf_server_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in
+                ("submitted", "admitted", "completed", "refused", "launches", "deadline_misses",
+                 "inflight_bytes", "peak_inflight_bytes", "queued")]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+# numpy layouts of bf_request (48 bytes) and bf_completion (56 bytes)
+REQUEST_DTYPE = np.dtype([("w_id", "<i4"), ("f", "<i4"), ("n_s", "<i4"), ("reserved", "<i4"),
+                          ("S", "<u8"), ("R", "<u8"), ("tag", "<u8"), ("t_arrival_ns", "<i8")])
+COMPLETION_DTYPE = np.dtype([("ticket", "<u8"), ("tag", "<u8"), ("status", "<i4"),
+                             ("deadline_missed", "<i4"), ("t_arrival_ns", "<i8"),
+                             ("t_submit_ns", "<i8"), ("t_launch_ns", "<i8"), ("t_done_ns", "<i8")])
+assert REQUEST_DTYPE.itemsize == 48 and COMPLETION_DTYPE.itemsize == 56
+
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
 _i64 = ctypes.c_int64
@@ -72,6 +95,12 @@ _SIGS = {
     "bf_last_error": (ctypes.c_char_p, []),
     "bf_build_info": (ctypes.c_char_p, []),
     "bf_device_cu_count": (_i32, []),
+    "bf_server_create": (_i32, [ctypes.POINTER(_vp), _vp, ctypes.POINTER(bf_server_cfg)]),
+    "bf_submit": (_i32, [_vp, _vp, ctypes.POINTER(ctypes.c_uint64)]),
+    "bf_poll": (_i32, [_vp, _vp, _i32, _i64]),
+    "bf_server_stats_get": (_i32, [_vp, ctypes.POINTER(bf_server_stats)]),
+    "bf_server_destroy": (_i32, [_vp]),
+    "bf_now_ns": (_i64, []),
 }
 
 _lib = None
@@ -334,3 +363,99 @@ def bf_tune_load(plan: Plan, path: str) -> None:
 
 def bf_device_cu_count() -> int:
     return _check(lib().bf_device_cu_count(), "bf_device_cu_count")
+
+
+# ---- serving ---------------------------------------------------------------
+
+class Server:
+    def __init__(self, handle: int, plan: Plan):
+        self.handle = handle
+        self.plan = plan   # keeps the plan alive while the server runs
+
+    def close(self):
+        if self.handle:
+            h, self.handle = self.handle, None
+            _check(lib().bf_server_destroy(h), "bf_server_destroy")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def bf_server_create(plan: Plan, hbm_budget_bytes: int = 16 << 30, deadline_us: int = 0,
+                     n_streams: int = 2, max_batch_items: int = 16384,
+                     queue_capacity: int = 65536, prec: int = BF_FP32) -> Server:
+    cfg = bf_server_cfg(int(hbm_budget_bytes), int(deadline_us), int(n_streams),
+                        int(max_batch_items), int(queue_capacity), int(prec))
+    h = _vp()
+    _check(lib().bf_server_create(ctypes.byref(h), plan.handle, ctypes.byref(cfg)),
+           "bf_server_create")
+    return Server(h.value, plan)
+
+
+def make_request(w_id: int, f: int, n_s: int, S, R, tag: int = 0, t_arrival_ns: int = 0):
+    r = np.zeros(1, REQUEST_DTYPE)
+    r["w_id"], r["f"], r["n_s"] = w_id, f, n_s
+    r["S"], r["R"], r["tag"], r["t_arrival_ns"] = _ptr(S), _ptr(R), tag, t_arrival_ns
+    return r
+
+
+def bf_submit(server: Server, req) -> int:
+    """Submit one request (a REQUEST_DTYPE record); returns its ticket."""
+    req = np.ascontiguousarray(req, dtype=REQUEST_DTYPE)
+    t = ctypes.c_uint64()
+    _check(lib().bf_submit(server.handle, req.ctypes.data, ctypes.byref(t)), "bf_submit")
+    return int(t.value)
+
+
+def bf_poll(server: Server, max_n: int = 1024, timeout_us: int = 0) -> np.ndarray:
+    """Up to max_n completions (COMPLETION_DTYPE); empty on timeout."""
+    out = np.zeros(max_n, COMPLETION_DTYPE)
+    rc = lib().bf_poll(server.handle, out.ctypes.data, int(max_n), int(timeout_us))
+    if rc == BF_ERR_TIMEOUT:
+        return out[:0]
+    _check(rc, "bf_poll")
+    return out[:rc]
+
+
+def bf_server_stats_get(server: Server) -> dict:
+    st = bf_server_stats()
+    _check(lib().bf_server_stats_get(server.handle, ctypes.byref(st)), "bf_server_stats_get")
+    return st.as_dict()
+
+
+def bf_server_destroy(server: Server) -> None:
+    server.close()
+
+
+def bf_now_ns() -> int:
+    return int(lib().bf_now_ns())
+
+
+LOADGEN_PATH = LIB_PATH.parent / "loadgen" / "libbf_loadgen.so"
+_loadgen = None
+
+
+def loadgen_replay(server: Server, reqs: np.ndarray, t_offset_ns: np.ndarray) -> tuple:
+    """Replays reqs (REQUEST_DTYPE) at the given offsets from a native thread
+    (benchmark helper); returns (completions in request order, busy retries)."""
+    global _loadgen
+    lib()
+    if _loadgen is None:
+        if not LOADGEN_PATH.exists():
+            raise RuntimeError(f"{LOADGEN_PATH} is not built")
+        L = ctypes.CDLL(str(LOADGEN_PATH))
+        L.bf_loadgen_replay.restype = _i64
+        L.bf_loadgen_replay.argtypes = [_vp, _vp, _vp, _i64, _vp]
+        _loadgen = L
+    reqs = np.ascontiguousarray(reqs, dtype=REQUEST_DTYPE)
+    t_off = np.ascontiguousarray(t_offset_ns, dtype=np.int64)
+    if t_off.shape != (reqs.shape[0],):
+        raise ValueError("one offset per request")
+    done = np.zeros(reqs.shape[0], COMPLETION_DTYPE)
+    rc = _loadgen.bf_loadgen_replay(server.handle, reqs.ctypes.data, t_off.ctypes.data,
+                                   reqs.shape[0], done.ctypes.data)
+    _check(rc, "bf_loadgen_replay")
+    return done, int(rc)

@@ -344,6 +344,21 @@ static bf_status ensure_slot(StagingSlot &s, size_t bytes)
     return BF_OK;
 }
 
+// Gives every staging slot room for a block of n items up front, so that a
+// hot loop never reallocates (a device free waits for the whole device).
+bf_status reserve_staging(bf_plan p, int n)
+{
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (p->ring.empty())
+        p->ring.resize(kRingSlots);
+    for (StagingSlot &slot : p->ring) {
+        bf_status s = ensure_slot(slot, block_bytes(n));
+        if (s != BF_OK)
+            return s;
+    }
+    return BF_OK;
+}
+
 // Common tail of bf_apply / bf_apply_packed / the serving batcher: items
 // are already validated and written by `fill` into host memory.
 bf_status enqueue_items(bf_plan p, bf_prec prec, int n, const FillFn &fill, hipStream_t st,

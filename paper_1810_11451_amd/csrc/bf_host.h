@@ -66,6 +66,7 @@ bf_status bf_fail(bf_status s, const char *fmt, ...) __attribute__((format(print
 void order_items(const BfItem *in, BfItem *out, int n, int n_w, std::vector<int> &scratch);
 bfk::LaunchCfg choose_launch(bf_plan p, bf_prec prec, int n, int max_f, bool vec16,
                              const bf_variant *force);
+bf_status reserve_staging(bf_plan p, int n);
 bf_status enqueue_items(bf_plan p, bf_prec prec, int n, const FillFn &fill, hipStream_t st,
                         const bf_variant *force, int *grid_out);
 hipError_t launch_for_plan(bf_plan p, const bfk::LaunchCfg &cfg, BfHeader *blk, int n,

@@ -45,9 +45,7 @@ def test_library_exports_every_declared_symbol(L):
 def test_binding_names_match_header():
     import paper_1810_11451_amd.bf as mod
     for n in declared_functions():
-        if n in ("bf_server_stats_get",):
-            continue
-        assert hasattr(mod, n) or n in mod._SIGS, n
+        assert hasattr(mod, n) and n in mod._SIGS, n
 
 
 def test_status_strings(L):
@@ -118,6 +116,27 @@ def test_calls_on_null_handles(L):
     assert L.bf_graph_launch(None, None) == bf.BF_ERR_INVALID
     assert L.bf_graph_destroy(None) == bf.BF_ERR_INVALID
     assert L.bf_tune_save(None, b"/tmp/x") == bf.BF_ERR_INVALID
+
+
+def test_server_create_rejects_null_plan(L):
+    h = ctypes.c_void_p()
+    assert L.bf_server_create(ctypes.byref(h), None, None) == bf.BF_ERR_INVALID
+    assert L.bf_submit(None, None, None) == bf.BF_ERR_INVALID
+    assert L.bf_poll(None, None, 0, 0) == bf.BF_ERR_INVALID
+    assert L.bf_server_destroy(None) == bf.BF_ERR_INVALID
+
+
+def test_record_layouts_match_header():
+    assert ctypes.sizeof(bf.bf_server_cfg) == 32
+    assert ctypes.sizeof(bf.bf_server_stats) == 72
+    assert bf.REQUEST_DTYPE.itemsize == 48 and bf.COMPLETION_DTYPE.itemsize == 56
+
+
+def test_monotonic_clock(L):
+    import time
+    a = bf.bf_now_ns()
+    b = time.monotonic_ns()
+    assert abs(a - b) < 10_000_000_000
 
 
 def test_f_bucket(L):
