@@ -55,14 +55,23 @@ typedef enum {
 
 /* Arithmetic forms of the contraction.  All read complex64 S and write
  * complex64 R with FP32 accumulation.
- *   BF_FP32    FP32 operands on the FP32 matrix cores.
+ *   BF_FP32    FP32 operands on the FP32 matrix cores, four real products
+ *              per complex product.
+ *   BF_FP32_3M FP32 operands, three real products per complex product
+ *              (Gauss): Re = Wr Sr - Wi Si, Im = (Wr + Wi)(Sr + Si) - Wr Sr
+ *              - Wi Si, with Wr + Wi formed once in the plan.  A quarter
+ *              fewer matrix-core steps; rounding differs from BF_FP32 (for
+ *              example an identity W no longer returns S bit for bit) but
+ *              stays within the FP32 error bar.
  *   BF_FP16,   operands rounded to FP16 / BF16 (S scaled per product by a
  *   BF_BF16    power of two first; exact and undone on output).
  *   BF_FP16X2, 2-term split: x = hi + lo, products hi*hi + hi*lo + lo*hi
  *   BF_BF16X2  accumulated in FP32, recovering close to FP32 accuracy. */
-typedef enum { BF_FP32 = 0, BF_FP16 = 1, BF_BF16 = 2, BF_FP16X2 = 3, BF_BF16X2 = 4 } bf_prec;
+typedef enum {
+    BF_FP32 = 0, BF_FP16 = 1, BF_BF16 = 2, BF_FP16X2 = 3, BF_BF16X2 = 4, BF_FP32_3M = 5
+} bf_prec;
 #define BF_PREC_BIT(p) (1u << (unsigned)(p))
-#define BF_PREC_ALL 0x1Fu
+#define BF_PREC_ALL 0x3Fu
 
 typedef struct bf_plan_s *bf_plan;
 typedef struct bf_graph_s *bf_graph;
@@ -120,10 +129,13 @@ bf_status bf_check_batch(int32_t n_w, int32_t f_max, int32_t batch, const int32_
 /* ---- graph: a fixed batch replayed many times ------------------------
  * A 5G slot loop often repeats the same set of products over the same
  * (double-buffered) S and R buffers.  bf_graph_create validates the batch
- * once, uploads its descriptors (ordered longest-first for balance) to
- * device memory owned by the graph, and captures the persistent kernel
- * into a hipGraph; bf_graph_launch replays it on any stream with no host
- * work besides the launch.  Arguments as for bf_apply. */
+ * once, uploads its descriptors (in the order the plan's variant for this
+ * batch asks for) to device memory owned by the graph, and captures the
+ * apply kernel into a hipGraph; bf_graph_launch replays it on any stream
+ * with no host work besides the launch.  Replays of one graph must not
+ * overlap (one stream, or ordered by the caller): the persistent claim
+ * schedule re-arms its counter at the end of each replay.  Arguments as
+ * for bf_apply. */
 bf_status bf_graph_create(bf_graph *out, bf_plan plan, int32_t batch, const int32_t *w_ids,
                           const int32_t *f, const void *const *S, void *const *R,
                           bf_prec prec, void *hip_stream);
@@ -131,10 +143,11 @@ bf_status bf_graph_launch(bf_graph graph, void *hip_stream);
 bf_status bf_graph_destroy(bf_graph graph);
 
 /* ---- kernel variants and tuning --------------------------------------
- * A variant fixes how the batch is spread over the chip: work
- * distribution (one product per workgroup, or persistent workgroups that
- * claim products from an atomic counter), workgroups per CU and product
- * order.  bf_autotune times every candidate on the given batch and stores
+ * A variant fixes how the batch is spread over the chip and how R leaves
+ * it: work distribution (one product per workgroup, persistent workgroups
+ * claiming products from an atomic counter, or persistent workgroups with
+ * a static share that prefetch the next S), workgroups per CU, product
+ * order, and the R store path.  bf_autotune times every candidate on the given batch and stores
  * the fastest for (prec, f bucket) in the plan; bf_apply uses it from
  * then on.  The table can be saved to and loaded from a text file. */
 typedef struct {
@@ -142,7 +155,9 @@ typedef struct {
                               2: persistent, static share per XCD, next S prefetched */
     int32_t wg_per_cu;     /* persistent grid = wg_per_cu * CU count (ignored for 0) */
     int32_t order;         /* 0: as given; 1: longest f first, then by W id */
-    int32_t reserved;
+    int32_t store;         /* 0: lanes write their accumulators directly;
+                              1: each wave stages its 16 rows of R in LDS and writes
+                              them as contiguous 16-byte stores (not for schedule 1) */
 } bf_variant;
 
 bf_status bf_set_variant(bf_plan plan, bf_prec prec, int32_t f_bucket, const bf_variant *v);

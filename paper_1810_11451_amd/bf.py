@@ -22,10 +22,10 @@ LIB_PATH = Path(__file__).resolve().with_name("libbf.so")
 BF_M, BF_B, BF_FMAX = 64, 60, 36
 BF_OK, BF_ERR_INVALID, BF_ERR_OOM, BF_ERR_DEVICE = 0, -1, -2, -3
 BF_ERR_BUSY, BF_ERR_TIMEOUT, BF_ERR_UNSUPPORTED = -4, -5, -6
-BF_FP32, BF_FP16, BF_BF16, BF_FP16X2, BF_BF16X2 = 0, 1, 2, 3, 4
+BF_FP32, BF_FP16, BF_BF16, BF_FP16X2, BF_BF16X2, BF_FP32_3M = 0, 1, 2, 3, 4, 5
 PREC_NAMES = {BF_FP32: "fp32", BF_FP16: "fp16", BF_BF16: "bf16",
-              BF_FP16X2: "fp16x2", BF_BF16X2: "bf16x2"}
-PREC_ALL = 0x1F
+              BF_FP16X2: "fp16x2", BF_BF16X2: "bf16x2", BF_FP32_3M: "fp32_3m"}
+PREC_ALL = 0x3F
 
 
 def BF_PREC_BIT(p: int) -> int:
@@ -41,10 +41,10 @@ class BfError(RuntimeError):
 
 class bf_variant(ctypes.Structure):
     _fields_ = [("schedule", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
-                ("order", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("order", ctypes.c_int32), ("store", ctypes.c_int32)]
 
     def as_tuple(self):
-        return (self.schedule, self.wg_per_cu, self.order)
+        return (self.schedule, self.wg_per_cu, self.order, self.store)
 
 
 class bf_server_cfg(ctypes.Structure):
@@ -325,8 +325,8 @@ def batch_bucket(f) -> int:
 
 
 def bf_set_variant(plan: Plan, prec: int, bucket: int, schedule: int, wg_per_cu: int = 0,
-                   order: int = 1) -> None:
-    v = bf_variant(schedule, wg_per_cu, order, 0)
+                   order: int = 1, store: int = 0) -> None:
+    v = bf_variant(schedule, wg_per_cu, order, store)
     _check(lib().bf_set_variant(plan.handle, int(prec), int(bucket), ctypes.byref(v)),
            "bf_set_variant")
 

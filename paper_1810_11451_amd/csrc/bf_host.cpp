@@ -94,9 +94,10 @@ static bf_status default_variants(bf_plan p)
         for (int b = 0; b < kBucketCount; ++b) {
             bf_variant v{};
             const bool full = b == kBucketCount - 1;
-            v.schedule = full ? 2 : 0;
+            v.schedule = full ? (pr == BF_FP32 || pr == BF_FP32_3M ? 3 : 2) : 0;
             v.wg_per_cu = 0;   // 0: the kernel's occupancy
             v.order = full ? 1 : 0;
+            v.store = full ? 1 : 0;
             p->table[pr][b] = v;
         }
     return BF_OK;
@@ -174,6 +175,18 @@ extern "C" bf_status bf_plan_create(bf_plan *out, const void *w_pool, int32_t n_
             return fail_dev("FP32 W layout", e);
         }
     }
+    if (prec_mask & BF_PREC_BIT(BF_FP32_3M)) {
+        p->a_3m_stride = bfk::fp32_3m_w_stride(p->pairs);
+        const size_t bytes = std::max<size_t>(16, (size_t)n_w * p->a_3m_stride * sizeof(float4));
+        e = hipMalloc(&p->a_3m, bytes);
+        if (e == hipSuccess && p->pairs > 0)
+            e = bfk::launch_w_transform_3m(w_dev, n_w, f_max, p->a_3m, p->pairs, st);
+        if (e != hipSuccess) {
+            if (w_dev)
+                (void)hipFree(w_dev);
+            return fail_dev("three-product W layout", e);
+        }
+    }
     p->lp_stride = bfk::lp_w_units(f_max);
     for (int ty = 0; ty < 2; ++ty) {
         const bf_prec plain = ty == 0 ? BF_FP16 : BF_BF16;
@@ -217,6 +230,8 @@ extern "C" bf_status bf_plan_destroy(bf_plan p)
     }
     if (p->a_fp32)
         (void)hipFree(p->a_fp32);
+    if (p->a_3m)
+        (void)hipFree(p->a_3m);
     for (int ty = 0; ty < 2; ++ty) {
         if (p->lp_hi[ty])
             (void)hipFree(p->lp_hi[ty]);
@@ -295,13 +310,16 @@ bfk::LaunchCfg choose_launch(bf_plan p, bf_prec prec, int n, int max_f, bool vec
     bfk::LaunchCfg cfg{};
     cfg.prec = prec;
     cfg.schedule = v.schedule;
-    if (prec != BF_FP32 && cfg.schedule == 1)
-        cfg.schedule = 2;   // the 16-bit forms have no claim schedule
+    if (prec == BF_FP32_3M && cfg.schedule != 0)
+        cfg.schedule = 3;   // the three-product form runs one-per-workgroup or wave-specialised
+    else if (prec != BF_FP32 && prec != BF_FP32_3M && (cfg.schedule == 1 || cfg.schedule == 3))
+        cfg.schedule = 2;   // the 16-bit forms have no claim or wave-specialised schedule
     cfg.vec16 = vec16;
+    cfg.stage = cfg.schedule == 3 || prec == BF_FP32_3M || (v.store == 1 && cfg.schedule != 1);
     if (v.schedule == 0) {
         cfg.grid = n;
     } else {
-        const int occ = bfk::apply_occupancy(prec, cfg.schedule, vec16);
+        const int occ = bfk::apply_occupancy(prec, cfg.schedule, vec16, cfg.stage);
         const int per_cu = v.wg_per_cu > 0 ? v.wg_per_cu : occ;
         const long g = (long)per_cu * p->n_cu;
         cfg.grid = (int)std::min<long>(g, n);
@@ -422,6 +440,8 @@ hipError_t launch_for_plan(bf_plan p, const bfk::LaunchCfg &cfg, BfHeader *blk, 
     pd.a_fp32 = p->a_fp32;
     pd.a_fp32_stride = (int)p->a_fp32_stride;
     pd.pairs = p->pairs;
+    pd.a_3m = p->a_3m;
+    pd.a_3m_stride = (int)p->a_3m_stride;
     const int ty = (cfg.prec == BF_BF16 || cfg.prec == BF_BF16X2) ? 1 : 0;
     pd.lp_hi = p->lp_hi[ty];
     pd.lp_lo = p->lp_lo[ty];
@@ -557,9 +577,7 @@ extern "C" bf_status bf_graph_create(bf_graph *out, bf_plan p, int32_t batch, co
             vec16 = false;
     }
     std::vector<int> scratch;
-    bf_variant v = p->table[prec][batch_bucket(sum_f, batch)];
-    if (v.schedule == 0)
-        v.schedule = 2;   // a graph replays a persistent launch
+    const bf_variant v = p->table[prec][batch_bucket(sum_f, batch)];
     if (v.order == 1)
         order_items(raw.data(), items.data(), batch, p->n_w, scratch);
     else
@@ -634,8 +652,8 @@ extern "C" bf_status bf_graph_destroy(bf_graph g)
 
 static bool valid_variant(const bf_variant &v)
 {
-    return v.schedule >= 0 && v.schedule <= 2 && v.wg_per_cu >= 0 && v.wg_per_cu <= 64 &&
-           (v.order == 0 || v.order == 1);
+    return v.schedule >= 0 && v.schedule <= 3 && v.wg_per_cu >= 0 && v.wg_per_cu <= 64 &&
+           (v.order == 0 || v.order == 1) && (v.store == 0 || v.store == 1);
 }
 
 extern "C" bf_status bf_set_variant(bf_plan p, bf_prec prec, int32_t bucket, const bf_variant *v)
@@ -682,13 +700,17 @@ extern "C" bf_status bf_autotune(bf_plan p, int32_t batch, const int32_t *w_ids,
         sum_f += f[t];
 
     std::vector<bf_variant> cands;
-    cands.push_back(bf_variant{0, 0, 0, 0});
-    cands.push_back(bf_variant{0, 0, 1, 0});
-    const int per_cu[] = {1, 2, 3, 4, 6, 8};
-    for (int sc = 1; sc <= 2; ++sc)
+    for (int st = 0; st < 2; ++st) {
+        cands.push_back(bf_variant{0, 0, 0, st});
+        cands.push_back(bf_variant{0, 0, 1, st});
+    }
+    const int per_cu[] = {1, 2, 3, 4, 6};
+    for (int w : per_cu)
+        cands.push_back(bf_variant{1, w, 1, 0});
+    for (int st = 0; st < 2; ++st)
         for (int w : per_cu)
             for (int o = 0; o < 2; ++o)
-                cands.push_back(bf_variant{sc, w, o, 0});
+                cands.push_back(bf_variant{2, w, o, st});
 
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -766,11 +788,11 @@ extern "C" bf_status bf_tune_save(bf_plan p, const char *path)
         return bf_fail(BF_ERR_INVALID, "cannot open %s for writing", path);
     std::lock_guard<std::mutex> lk(p->mu);
     fprintf(fp, "# bf tune v1 arch=%s\n", arch_name().c_str());
-    fprintf(fp, "# prec bucket schedule wg_per_cu order\n");
+    fprintf(fp, "# prec bucket schedule wg_per_cu order store\n");
     for (int pr = 0; pr < kPrecCount; ++pr)
         for (int b = 0; b < kBucketCount; ++b) {
             const bf_variant &v = p->table[pr][b];
-            fprintf(fp, "%d %d %d %d %d\n", pr, b, v.schedule, v.wg_per_cu, v.order);
+            fprintf(fp, "%d %d %d %d %d %d\n", pr, b, v.schedule, v.wg_per_cu, v.order, v.store);
         }
     fclose(fp);
     return BF_OK;
@@ -789,13 +811,13 @@ extern "C" bf_status bf_tune_load(bf_plan p, const char *path)
     while (fgets(line, sizeof line, fp)) {
         if (line[0] == '#' || line[0] == '\n')
             continue;
-        int pr, b, sc, w, o;
-        if (sscanf(line, "%d %d %d %d %d", &pr, &b, &sc, &w, &o) != 5 || pr < 0 ||
-            pr >= kPrecCount || b < 0 || b >= kBucketCount) {
+        int pr, b, sc, w, o, st = 0;
+        const int got = sscanf(line, "%d %d %d %d %d %d", &pr, &b, &sc, &w, &o, &st);
+        if (got < 5 || pr < 0 || pr >= kPrecCount || b < 0 || b >= kBucketCount) {
             ok = false;
             break;
         }
-        bf_variant v{sc, w, o, 0};
+        bf_variant v{sc, w, o, st};
         if (!valid_variant(v)) {
             ok = false;
             break;
@@ -833,7 +855,7 @@ extern "C" const char *bf_last_error(void) { return g_last_error.c_str(); }
 extern "C" const char *bf_build_info(void)
 {
     return "libbf gfx950 hip-" BF_STRINGIFY(HIP_VERSION_MAJOR) "." BF_STRINGIFY(HIP_VERSION_MINOR)
-           " fp32-mfma fp16/bf16-mfma split";
+           " fp32-mfma fp32-3m fp16/bf16-mfma split";
 }
 
 extern "C" int32_t bf_device_cu_count(void)

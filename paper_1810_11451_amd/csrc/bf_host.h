@@ -12,7 +12,7 @@
 #define BF_STRINGIFY2(x) #x
 #define BF_STRINGIFY(x) BF_STRINGIFY2(x)
 
-constexpr int kPrecCount = 5;
+constexpr int kPrecCount = 6;
 constexpr int kBucketCount = 5;
 constexpr int kRingSlots = 8;
 constexpr uint32_t kSupportedMask = BF_PREC_ALL;
@@ -38,6 +38,8 @@ struct bf_plan_s {
 
     float2 *a_fp32 = nullptr;   // FP32 operand layout, a_fp32_stride float2 per W
     size_t a_fp32_stride = 0;
+    float4 *a_3m = nullptr;     // FP32 three-product layout, a_3m_stride float4 per W
+    size_t a_3m_stride = 0;
     // 16-bit operand layouts, index 0 = FP16, 1 = BF16 (lo only for split forms)
     void *lp_hi[2] = {nullptr, nullptr};
     void *lp_lo[2] = {nullptr, nullptr};

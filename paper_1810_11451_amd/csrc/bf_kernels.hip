@@ -23,6 +23,8 @@
 // staged once per item in LDS and read by all four waves.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "bf_internal.h"
 
 namespace bfk {
@@ -35,6 +37,7 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) f2v g_f2v;
 typedef __attribute__((address_space(1))) const f2v g_cf2v;
 typedef __attribute__((address_space(1))) const f4v g_cf4v;
+typedef __attribute__((address_space(1))) f4v g_f4v;
 
 constexpr int kLdsCols = 64;   // LDS row pitch of a staged S, in complex elements
 
@@ -86,6 +89,46 @@ hipError_t launch_w_transform_fp32(const float2 *w_dev, int n_w, int f_max, floa
     return hipGetLastError();
 }
 
+// Plan-time operand layout, three-product FP32 form.  For
+// v_mfma_f32_32x32x2_f32 with real rows = antennas: lane l of antenna half
+// mt holds, for pair p, antenna i = 32 mt + l % 32 and flow k = 2p + l / 32:
+// (Wr, Wi, Wr + Wi, 0), the sum rounded once here.  Flows k >= f_max hold
+// zeros.
+__global__ void w_transform_3m_kernel(const float2 *__restrict__ w, int n_w, int f_max,
+                                      float4 *__restrict__ a, int pairs)
+{
+    const size_t total = (size_t)n_w * 2 * pairs * 64;
+    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        const int lane = (int)(idx % 64);
+        const int p = (int)((idx / 64) % pairs);
+        const int mt = (int)((idx / (64 * (size_t)pairs)) % 2);
+        const size_t wi = idx / (64 * (size_t)pairs * 2);
+        const int i = 32 * mt + (lane & 31);
+        const int k = 2 * p + (lane >> 5);
+        float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (k < f_max) {
+            const float2 v = w[(wi * kM + i) * (size_t)f_max + k];
+            out = make_float4(v.x, v.y, v.x + v.y, 0.f);
+        }
+        a[idx] = out;
+    }
+}
+
+hipError_t launch_w_transform_3m(const float2 *w_dev, int n_w, int f_max, float4 *a_out,
+                                 int pairs, hipStream_t st)
+{
+    const size_t total = (size_t)n_w * 2 * pairs * 64;
+    if (total == 0)
+        return hipSuccess;
+    const int block = 256;
+    const size_t want = (total + block - 1) / block;
+    const int grid = (int)(want < 65535 ? want : 65535);
+    hipLaunchKernelGGL(w_transform_3m_kernel, dim3(grid), dim3(block), 0, st, w_dev, n_w, f_max,
+                       a_out, pairs);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Memory access discipline.  Every global load and store inside the
 // per-product loop is unconditional: indices are clamped into range (the
@@ -115,9 +158,9 @@ struct SRegs<false> {
 // 16-byte chunks t, t + 256, ... (8-byte elements when S is only 8-byte
 // aligned).  For f = 0, S must point at the sink and one chunk is read.
 template <bool kVec16>
-__device__ __forceinline__ void load_s(SRegs<kVec16> &r, const float2 *__restrict__ S, int f)
+__device__ __forceinline__ void load_s(SRegs<kVec16> &r, const float2 *__restrict__ S, int f,
+                                       int tid = threadIdx.x)
 {
-    const int tid = threadIdx.x;
     if constexpr (kVec16) {
         g_cf4v *src = (g_cf4v *)S;
         const int last = (f > 0 ? f * (kB / 2) : 1) - 1;
@@ -141,9 +184,9 @@ __device__ __forceinline__ void load_s(SRegs<kVec16> &r, const float2 *__restric
 // k (pitch 64 complex).  For odd f, row f is cleared so the second half of
 // the last K pair multiplies zeros.
 template <bool kVec16>
-__device__ __forceinline__ void put_s(f2v *__restrict__ lds, const SRegs<kVec16> &r, int f)
+__device__ __forceinline__ void put_s(f2v *__restrict__ lds, const SRegs<kVec16> &r, int f,
+                                      int tid = threadIdx.x)
 {
-    const int tid = threadIdx.x;
     if constexpr (kVec16) {
         const int chunks = f * (kB / 2);
 #pragma unroll
@@ -196,18 +239,77 @@ __device__ __forceinline__ void store_r(float2 *__restrict__ Rp, float2 *__restr
     }
 }
 
-// Issues as many stores as store_r (16), into the sink.  Placed after the
-// first S loads of a persistent loop, it makes the loop-entry path carry the
-// same outstanding-operation pattern as the back edge (S loads followed by
-// 16 stores), so the compiler's wait before the first LDS write counts only
+// Issues kN stores into the sink: as many as one product's R write issues
+// (16 for store_r, 8 for write_r_staged).  Placed after the first S loads
+// of a persistent loop, it makes the loop-entry path carry the same
+// outstanding-operation pattern as the back edge (S loads followed by the
+// R stores), so the compiler's wait before the first LDS write counts only
 // the S loads on both paths instead of falling back to the stricter count.
+template <int kN>
 __device__ __forceinline__ void prime_store_count(float2 *__restrict__ sink, int lane)
 {
     g_f2v *pad = (g_f2v *)sink + lane;
 #pragma unroll
-    for (int k = 0; k < 16; ++k)
+    for (int k = 0; k < kN; ++k)
         __builtin_nontemporal_store(f2v{0.f, 0.f}, pad + 64 * k);
 }
+
+// R of one wave: rows 16 wave .. 16 wave + 15, i.e. 960 complex values
+// (7680 bytes) contiguous in memory.
+constexpr int kWaveOut = 16 * kB;
+
+// Writes the wave's two accumulator tiles to R through the wave's own LDS
+// area: first to LDS in R's row-major layout, then read back and written
+// as 7 contiguous 16-byte stores plus one 8-byte store per lane (whole
+// 128-byte lines, no padding lanes).  Only this wave touches its area, and
+// a wave's LDS operations complete in order, so no barrier is needed.
+__device__ __forceinline__ void stage_acc(f2v *__restrict__ stage, int lane, const floatx16 &acc0,
+                                          const floatx16 &acc1)
+{
+    const int h = lane >> 5;
+    const int n = lane & 31;
+#pragma unroll
+    for (int r = 0; r < 16; r += 2) {
+        const int il = 4 * (r >> 2) + 2 * h + ((r & 3) >> 1);
+        stage[il * kB + n] = f2v{acc0[r], acc0[r + 1]};
+        if (n < kB - 32)
+            stage[il * kB + 32 + n] = f2v{acc1[r], acc1[r + 1]};
+    }
+}
+
+__device__ __forceinline__ void store_staged(float2 *__restrict__ Rp, const f2v *__restrict__ stage,
+                                             int wave, int lane)
+{
+    g_f2v *dst = (g_f2v *)Rp + (size_t)(16 * wave) * kB;
+    const f4v *src4 = reinterpret_cast<const f4v *>(stage);
+#pragma unroll
+    for (int u = 0; u < 7; ++u) {
+        const int c = u * 64 + lane;
+        __builtin_nontemporal_store(src4[c], (g_f4v *)dst + c);
+    }
+    __builtin_nontemporal_store(stage[896 + lane], dst + 896 + lane);
+}
+
+__device__ __forceinline__ void write_r_staged(float2 *__restrict__ Rp, f2v *__restrict__ stage,
+                                               int wave, int lane, const floatx16 &acc0,
+                                               const floatx16 &acc1)
+{
+    stage_acc(stage, lane, acc0, acc1);
+    store_staged(Rp, stage, wave, lane);
+}
+
+template <bool kStage>
+__device__ __forceinline__ void write_r(float2 *__restrict__ Rp, float2 *__restrict__ sink,
+                                        f2v *__restrict__ stage, int wave, int lane,
+                                        const floatx16 &acc0, const floatx16 &acc1)
+{
+    if constexpr (kStage)
+        write_r_staged(Rp, stage, wave, lane, acc0, acc1);
+    else
+        store_r(Rp, sink, wave, lane, acc0, acc1);
+}
+template <bool kStage>
+constexpr int kStoresPerProduct = kStage ? 8 : 16;
 
 // ---------------------------------------------------------------------------
 // FP32 apply kernels.
@@ -224,16 +326,28 @@ __device__ __forceinline__ void load_a_fp32(f2v (&a)[kPairsMax], const float2 *_
 }
 
 // One product from a staged S: 2 * np matrix-core steps per 32 x 32 tile.
-__device__ __forceinline__ void contract_store_fp32(const f2v *__restrict__ lds,
-                                                    const f2v (&a)[kPairsMax], int f,
-                                                    float2 *__restrict__ R, float2 *__restrict__ sink,
-                                                    int wave, int lane)
+__device__ __forceinline__ void contract_fp32(const f2v *__restrict__ lds, const f2v (&a)[kPairsMax],
+                                              int f, int lane, floatx16 &acc0, floatx16 &acc1)
 {
     const int h = lane >> 5;
     const int n = lane & 31;
     const int np = (f + 1) >> 1;
-    floatx16 acc0 = {};
-    floatx16 acc1 = {};
+    acc0 = floatx16{};
+    acc1 = floatx16{};
+    if (np == kPairsMax) {
+        // Full width: straight-line code, so the LDS reads of later pairs can
+        // be issued while earlier pairs are on the matrix cores.
+#pragma unroll
+        for (int p = 0; p < kPairsMax; ++p) {
+            const f2v b0 = lds[(2 * p + h) * kLdsCols + n];
+            const f2v b1 = lds[(2 * p + h) * kLdsCols + 32 + n];
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a[p].x, b0.x, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a[p].x, b1.x, acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a[p].y, b0.y, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a[p].y, b1.y, acc1, 0, 0, 0);
+        }
+        return;
+    }
 #pragma unroll
     for (int p = 0; p < kPairsMax; ++p) {
         if (p < np) {
@@ -245,7 +359,63 @@ __device__ __forceinline__ void contract_store_fp32(const f2v *__restrict__ lds,
             acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a[p].y, b1.y, acc1, 0, 0, 0);
         }
     }
-    store_r(R, sink, wave, lane, acc0, acc1);
+}
+
+// ---------------------------------------------------------------------------
+// Three-product FP32 form.  Wave w of a workgroup owns the 32 x 32 quadrant
+// (antennas 32 mt .. 32 mt + 31, columns 32 nt .. 32 nt + 31), mt = w / 2,
+// nt = w % 2, and accumulates T1 = Wr Sr, T2 = Wi Si, T3 = (Wr + Wi)(Sr + Si)
+// over the flows; then Re R = T1 - T2 and Im R = (T3 - T1) - T2.
+
+// Loads the wave's operands of pool entry w: pairs >= 1, entries past
+// `pairs` repeat the last one and are never used.
+__device__ __forceinline__ void load_a_3m(f4v (&a)[kPairsMax], const float4 *__restrict__ apool,
+                                          int w, int a_w_stride, int pairs, int mt, int lane)
+{
+    const g_cf4v *ap = (const g_cf4v *)(apool + (size_t)w * a_w_stride + (size_t)mt * pairs * 64 + lane);
+#pragma unroll
+    for (int p = 0; p < kPairsMax; ++p)
+        a[p] = ap[min(p, pairs - 1) * 64];
+}
+
+__device__ __forceinline__ void mfma3(const f4v &a, const f2v &b, floatx16 &t1, floatx16 &t2,
+                                      floatx16 &t3)
+{
+    t1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, t1, 0, 0, 0);
+    t2 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b.y, t2, 0, 0, 0);
+    t3 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, b.x + b.y, t3, 0, 0, 0);
+}
+
+// Contracts the staged S (LDS, pitch kLdsCols) and writes the wave's
+// quadrant of R, row-major 64 x 60, into `tile` (LDS).
+__device__ __forceinline__ void contract_stage_3m(const f2v *__restrict__ lds,
+                                                  const f4v (&a)[kPairsMax], int f, int wave,
+                                                  int lane, f2v *__restrict__ tile)
+{
+    const int h = lane >> 5;
+    const int n = lane & 31;
+    const int mt = wave >> 1;
+    const int nt = wave & 1;
+    const int np = (f + 1) >> 1;
+    floatx16 t1 = {}, t2 = {}, t3 = {};
+    const f2v *col = lds + h * kLdsCols + 32 * nt + n;
+    if (np == kPairsMax) {
+#pragma unroll
+        for (int p = 0; p < kPairsMax; ++p)
+            mfma3(a[p], col[2 * p * kLdsCols], t1, t2, t3);
+    } else {
+#pragma unroll
+        for (int p = 0; p < kPairsMax; ++p)
+            if (p < np)
+                mfma3(a[p], col[2 * p * kLdsCols], t1, t2, t3);
+    }
+    const int j = 32 * nt + n;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = 32 * mt + 8 * (r >> 2) + 4 * h + (r & 3);
+        if (j < kB)
+            tile[i * kB + j] = f2v{t1[r] - t2[r], (t3[r] - t1[r]) - t2[r]};
+    }
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (block b runs on
@@ -266,8 +436,35 @@ __device__ __forceinline__ float2 *sink_of(BfHeader *blk)
     return reinterpret_cast<float2 *>(reinterpret_cast<char *>(blk) + sizeof(BfHeader));
 }
 
-// kSched 0: one product per workgroup.
+// kSched 0 for the three-product form: one product per workgroup.
 template <bool kVec16>
+__global__ __launch_bounds__(kThreads) void apply_fp32_3m_single(BfHeader *__restrict__ blk,
+                                                                 const BfItem *__restrict__ items,
+                                                                 int n_items,
+                                                                 const float4 *__restrict__ apool,
+                                                                 int a_w_stride, int pairs)
+{
+    __shared__ f2v lds_s[kFMax * kLdsCols];
+    __shared__ f2v tile[kWaves * kWaveOut];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    float2 *sink = sink_of(blk);
+    const int it = xcd_contiguous(blockIdx.x, n_items);
+    const BfItem d = items[it];
+    f4v a[kPairsMax];
+    SRegs<kVec16> sr;
+    load_s<kVec16>(sr, d.f > 0 ? d.S : sink, d.f);
+    if (pairs > 0)
+        load_a_3m(a, apool, d.w_id, a_w_stride, pairs, wave >> 1, lane);
+    put_s<kVec16>(lds_s, sr, d.f);
+    __syncthreads();
+    contract_stage_3m(lds_s, a, d.f, wave, lane, tile);
+    __syncthreads();
+    store_staged(d.R, tile + wave * kWaveOut, wave, lane);
+}
+
+// kSched 0: one product per workgroup.
+template <bool kVec16, bool kStage>
 __global__ __launch_bounds__(kThreads) void apply_fp32_single(BfHeader *__restrict__ blk,
                                                               const BfItem *__restrict__ items,
                                                               int n_items,
@@ -275,6 +472,7 @@ __global__ __launch_bounds__(kThreads) void apply_fp32_single(BfHeader *__restri
                                                               int a_w_stride, int pairs)
 {
     __shared__ f2v lds_s[kFMax * kLdsCols];
+    __shared__ f2v stage[kStage ? kWaves : 1][kStage ? kWaveOut : 1];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     float2 *sink = sink_of(blk);
@@ -287,7 +485,9 @@ __global__ __launch_bounds__(kThreads) void apply_fp32_single(BfHeader *__restri
         load_a_fp32(a, apool, d.w_id, a_w_stride, pairs, wave, lane);
     put_s<kVec16>(lds_s, sr, d.f);
     __syncthreads();
-    contract_store_fp32(lds_s, a, d.f, d.R, sink, wave, lane);
+    floatx16 acc0, acc1;
+    contract_fp32(lds_s, a, d.f, lane, acc0, acc1);
+    write_r<kStage>(d.R, sink, stage[kStage ? wave : 0], wave, lane, acc0, acc1);
 }
 
 // kSched 1: persistent; workgroups claim items from blk->next.  The last
@@ -323,7 +523,9 @@ __global__ __launch_bounds__(kThreads) void apply_fp32_claim(BfHeader *__restric
         __syncthreads();
         if (threadIdx.x == 0)
             claim = (int)atomicAdd(&blk->next, 1u);
-        contract_store_fp32(lds_s, a, d.f, d.R, sink, wave, lane);
+        floatx16 acc0, acc1;
+        contract_fp32(lds_s, a, d.f, lane, acc0, acc1);
+        store_r(d.R, sink, wave, lane, acc0, acc1);
         __syncthreads();   // LDS is reused by the next item; `claim` is ready
         it = __builtin_amdgcn_readfirstlane(claim);
     }
@@ -385,7 +587,7 @@ __device__ __forceinline__ DescV uniform(const DescV &d)
 // S(i+1) and R(i) traffic overlaps the compute.  Two LDS buffers alternate
 // (the one written in iteration i+1 was last read in iteration i-1, before
 // iteration i's barrier).
-template <bool kVec16>
+template <bool kVec16, bool kStage>
 __global__ __launch_bounds__(kThreads) void apply_fp32_stream(BfHeader *__restrict__ blk,
                                                               const BfItem *__restrict__ items,
                                                               int n_items,
@@ -393,6 +595,7 @@ __global__ __launch_bounds__(kThreads) void apply_fp32_stream(BfHeader *__restri
                                                               int a_w_stride, int pairs)
 {
     __shared__ f2v lds_s[2][kFMax * kLdsCols];
+    __shared__ f2v stage[kStage ? kWaves : 1][kStage ? kWaveOut : 1];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     float2 *sink = sink_of(blk);
@@ -415,7 +618,7 @@ __global__ __launch_bounds__(kThreads) void apply_fp32_stream(BfHeader *__restri
     DescV dn = load_desc_v(items, min(nxt, last));
     SRegs<kVec16> sr;
     load_s<kVec16>(sr, d.f > 0 ? d.S : sink, d.f);
-    prime_store_count(sink, lane);
+    prime_store_count<kStoresPerProduct<kStage>>(sink, lane);
     f2v a[kPairsMax];
     int cur_w = -1;
     int buf = 0;
@@ -432,13 +635,124 @@ __global__ __launch_bounds__(kThreads) void apply_fp32_stream(BfHeader *__restri
         const bool more = nxt < hi;
         const DescV du = uniform(dn);
         load_s<kVec16>(sr, du.f > 0 ? du.S : sink, du.f);
-        contract_store_fp32(lds_s[buf], a, d.f, d.R, sink, wave, lane);
+        floatx16 acc0, acc1;
+        contract_fp32(lds_s[buf], a, d.f, lane, acc0, acc1);
+        write_r<kStage>(d.R, sink, stage[kStage ? wave : 0], wave, lane, acc0, acc1);
         if (!more)
             break;
         d = du;
         dn = dnn;
         nxt = nn;
         buf ^= 1;
+    }
+}
+
+// kSched 3: wave-specialised persistent kernel (FP32).  Eight waves per
+// workgroup: waves 0-3 (one per SIMD) only run matrix-core steps from LDS,
+// waves 4-7 only move data.  Per product t of the workgroup's share (a
+// contiguous run of its XCD group's range):
+//   consumers: contract S(t) from s_buf[t % 2], accumulators -> r_buf[t % 2];
+//   producers: write R(t-1) from r_buf[(t-1) % 2] with contiguous 16-byte
+//              stores; move S(t+1) from registers to s_buf[(t+1) % 2]; issue
+//              the loads of S(t+2) into registers;
+//   one barrier.
+// A buffer written in iteration t was last read in iteration t-1, before
+// that iteration's barrier; one written in t is read in t+1.  The two roles
+// run separate loops with the same number of barriers, so neither role's
+// memory waits hold up the other's instructions.
+constexpr int kWsThreads = 2 * kThreads;
+
+template <bool kVec16, bool k3M>
+__global__ __launch_bounds__(kWsThreads) void apply_fp32_ws(BfHeader *__restrict__ blk,
+                                                            const BfItem *__restrict__ items,
+                                                            int n_items, const void *__restrict__ apool,
+                                                            int a_w_stride, int pairs)
+{
+    __shared__ f2v s_buf[2][kFMax * kLdsCols];
+    __shared__ f2v r_buf[2][kWaves][kWaveOut];
+    __shared__ int meta[2][2];   // (W id, f) of the product staged in s_buf[i]
+    const int wave8 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int wave = wave8 & (kWaves - 1);
+    float2 *sink = sink_of(blk);
+
+    const int G = gridDim.x;
+    const int X = G < 8 ? G : 8;
+    const int x = blockIdx.x % X;
+    const int j = blockIdx.x / X;
+    const int nb = G / X + (x < G % X ? 1 : 0);
+    const int q = n_items / X, r = n_items % X;
+    const int lo = x * q + (x < r ? x : r);
+    const int cnt = q + (x < r ? 1 : 0);
+    const int per = cnt / nb, extra = cnt % nb;
+    const int start = lo + j * per + (j < extra ? j : extra);
+    const int n_my = per + (j < extra ? 1 : 0);
+    if (n_my <= 0)
+        return;
+
+    if (wave8 < kWaves) {
+        // consumer
+        using AReg = typename std::conditional<k3M, f4v, f2v>::type;
+        AReg a[kPairsMax];
+        int cur_w = -1;
+        __syncthreads();
+        for (int t = 0; t < n_my; ++t) {
+            const int w_id = __builtin_amdgcn_readfirstlane(meta[t & 1][0]);
+            const int f = __builtin_amdgcn_readfirstlane(meta[t & 1][1]);
+            if (w_id != cur_w && pairs > 0) {
+                cur_w = w_id;
+                if constexpr (k3M)
+                    load_a_3m(a, static_cast<const float4 *>(apool), cur_w, a_w_stride, pairs,
+                              wave >> 1, lane);
+                else
+                    load_a_fp32(a, static_cast<const float2 *>(apool), cur_w, a_w_stride, pairs,
+                                wave, lane);
+            }
+            if constexpr (k3M) {
+                contract_stage_3m(s_buf[t & 1], a, f, wave, lane, &r_buf[t & 1][0][0]);
+            } else {
+                floatx16 acc0, acc1;
+                contract_fp32(s_buf[t & 1], a, f, lane, acc0, acc1);
+                stage_acc(r_buf[t & 1][wave], lane, acc0, acc1);
+            }
+            __syncthreads();
+        }
+    } else {
+        // producer
+        const int ptid = threadIdx.x - kThreads;
+        SRegs<kVec16> sr;
+        {
+            const BfItem d0 = items[start];
+            load_s<kVec16>(sr, d0.f > 0 ? d0.S : sink, d0.f, ptid);
+            put_s<kVec16>(s_buf[0], sr, d0.f, ptid);
+            if (ptid == 0) {
+                meta[0][0] = d0.w_id;
+                meta[0][1] = d0.f;
+            }
+        }
+        if (n_my > 1) {
+            const BfItem d1 = items[start + 1];
+            load_s<kVec16>(sr, d1.f > 0 ? d1.S : sink, d1.f, ptid);
+        }
+        __syncthreads();
+        for (int t = 0; t < n_my; ++t) {
+            if (t >= 1)
+                store_staged(items[start + t - 1].R, r_buf[(t - 1) & 1][wave], wave, lane);
+            if (t + 1 < n_my) {
+                const BfItem d1 = items[start + t + 1];
+                put_s<kVec16>(s_buf[(t + 1) & 1], sr, d1.f, ptid);
+                if (ptid == 0) {
+                    meta[(t + 1) & 1][0] = d1.w_id;
+                    meta[(t + 1) & 1][1] = d1.f;
+                }
+            }
+            if (t + 2 < n_my) {
+                const BfItem dn = items[start + t + 2];
+                load_s<kVec16>(sr, dn.f > 0 ? dn.S : sink, dn.f, ptid);
+            }
+            __syncthreads();
+        }
+        store_staged(items[start + n_my - 1].R, r_buf[(n_my - 1) & 1][wave], wave, lane);
     }
 }
 
@@ -710,11 +1024,9 @@ __device__ __forceinline__ void load_a_lp(LpA<kSplit> &a, const PlanDev &pd, int
 // Matrix-core steps of one product from the staged 16-bit tile, then the
 // rescaled result to R.
 template <bool kBf16, bool kSplit>
-__device__ __forceinline__ void contract_store_lp(const uint32_t *__restrict__ bhi,
-                                                  const uint32_t *__restrict__ blo,
-                                                  const LpA<kSplit> &a, int f, int eo,
-                                                  float2 *__restrict__ R, float2 *__restrict__ sink,
-                                                  int wave, int lane)
+__device__ __forceinline__ void contract_lp(const uint32_t *__restrict__ bhi,
+                                            const uint32_t *__restrict__ blo, const LpA<kSplit> &a,
+                                            int f, int eo, int lane, floatx16 &o0, floatx16 &o1)
 {
     const int h = lane >> 5;
     const int n = lane & 31;
@@ -738,7 +1050,6 @@ __device__ __forceinline__ void contract_store_lp(const uint32_t *__restrict__ b
             }
         }
     }
-    floatx16 o0, o1;
     const float back = __builtin_amdgcn_ldexpf(1.0f, -Lp<kBf16>::kShift);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -750,13 +1061,12 @@ __device__ __forceinline__ void contract_store_lp(const uint32_t *__restrict__ b
         o0[r] = __builtin_amdgcn_ldexpf(v0, eo);
         o1[r] = __builtin_amdgcn_ldexpf(v1, eo);
     }
-    store_r(R, sink, wave, lane, o0, o1);
 }
 
 constexpr int kLpTile = 64 * kLpPitch;   // dwords per staged 16-bit tile
 
 // kSched 0 for the 16-bit forms: one product per workgroup.
-template <bool kBf16, bool kSplit, bool kVec16>
+template <bool kBf16, bool kSplit, bool kVec16, bool kStage>
 __global__ __launch_bounds__(kThreads) void apply_lp_single(BfHeader *__restrict__ blk,
                                                             const BfItem *__restrict__ items,
                                                             int n_items, PlanDev pd)
@@ -764,6 +1074,7 @@ __global__ __launch_bounds__(kThreads) void apply_lp_single(BfHeader *__restrict
     __shared__ uint32_t lds_hi[kLpTile];
     __shared__ uint32_t lds_lo[kSplit ? kLpTile : 1];
     __shared__ uint32_t smax[kWaves];
+    __shared__ f2v stage[kStage ? kWaves : 1][kStage ? kWaveOut : 1];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     float2 *sink = sink_of(blk);
@@ -784,13 +1095,15 @@ __global__ __launch_bounds__(kThreads) void apply_lp_single(BfHeader *__restrict
     const int es = exp_of_bits(max(max(smax[0], smax[1]), max(smax[2], smax[3])));
     put_s_lp<kBf16, kSplit, kVec16>(lds_hi, lds_lo, sr, d.f, __builtin_amdgcn_ldexpf(1.0f, -es));
     __syncthreads();
-    contract_store_lp<kBf16, kSplit>(lds_hi, lds_lo, a, d.f, ew + es, d.R, sink, wave, lane);
+    floatx16 o0, o1;
+    contract_lp<kBf16, kSplit>(lds_hi, lds_lo, a, d.f, ew + es, lane, o0, o1);
+    write_r<kStage>(d.R, sink, stage[kStage ? wave : 0], wave, lane, o0, o1);
 }
 
 // kSched 2 for the 16-bit forms: persistent, static share, next S
 // prefetched during the current product's matrix-core steps (as
 // apply_fp32_stream, with an extra barrier for the per-product scale).
-template <bool kBf16, bool kSplit, bool kVec16>
+template <bool kBf16, bool kSplit, bool kVec16, bool kStage>
 __global__ __launch_bounds__(kThreads) void apply_lp_stream(BfHeader *__restrict__ blk,
                                                             const BfItem *__restrict__ items,
                                                             int n_items, PlanDev pd)
@@ -798,6 +1111,7 @@ __global__ __launch_bounds__(kThreads) void apply_lp_stream(BfHeader *__restrict
     __shared__ uint32_t lds_hi[2][kLpTile];
     __shared__ uint32_t lds_lo[2][kSplit ? kLpTile : 1];
     __shared__ uint32_t smax[2][kWaves];
+    __shared__ f2v stage[kStage ? kWaves : 1][kStage ? kWaveOut : 1];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     float2 *sink = sink_of(blk);
@@ -820,7 +1134,7 @@ __global__ __launch_bounds__(kThreads) void apply_lp_stream(BfHeader *__restrict
     DescV dn = load_desc_v(items, min(nxt, last));
     SRegs<kVec16> sr;
     load_s<kVec16>(sr, d.f > 0 ? d.S : sink, d.f);
-    prime_store_count(sink, lane);
+    prime_store_count<kStoresPerProduct<kStage>>(sink, lane);
     LpA<kSplit> a;
     int cur_w = -1;
     int ew = 0;
@@ -845,8 +1159,9 @@ __global__ __launch_bounds__(kThreads) void apply_lp_stream(BfHeader *__restrict
         const bool more = nxt < hi;
         const DescV du = uniform(dn);
         load_s<kVec16>(sr, du.f > 0 ? du.S : sink, du.f);
-        contract_store_lp<kBf16, kSplit>(lds_hi[buf], lds_lo[buf], a, d.f, ew + es, d.R, sink,
-                                         wave, lane);
+        floatx16 o0, o1;
+        contract_lp<kBf16, kSplit>(lds_hi[buf], lds_lo[buf], a, d.f, ew + es, lane, o0, o1);
+        write_r<kStage>(d.R, sink, stage[kStage ? wave : 0], wave, lane, o0, o1);
         if (!more)
             break;
         d = du;
@@ -862,39 +1177,57 @@ static const BfItem *items_of(BfHeader *blk)
                                             sizeof(BfHeader) + kSinkBytes);
 }
 
-template <bool kVec16>
+template <bool kVec16, bool kStage>
 static hipError_t launch_fp32_t(const LaunchCfg &cfg, BfHeader *blk, int n_items,
                                 const PlanDev &pd, hipStream_t st)
 {
     const BfItem *items = items_of(blk);
     switch (cfg.schedule) {
     case 0:
-        hipLaunchKernelGGL(apply_fp32_single<kVec16>, dim3(n_items), dim3(kThreads), 0, st, blk,
-                           items, n_items, pd.a_fp32, pd.a_fp32_stride, pd.pairs);
+        hipLaunchKernelGGL((apply_fp32_single<kVec16, kStage>), dim3(n_items), dim3(kThreads), 0, st,
+                           blk, items, n_items, pd.a_fp32, pd.a_fp32_stride, pd.pairs);
         break;
     case 1:
         hipLaunchKernelGGL(apply_fp32_claim<kVec16>, dim3(cfg.grid), dim3(kThreads), 0, st, blk,
                            items, n_items, pd.a_fp32, pd.a_fp32_stride, pd.pairs);
         break;
+    case 3:
+        hipLaunchKernelGGL((apply_fp32_ws<kVec16, false>), dim3(cfg.grid), dim3(kWsThreads), 0, st,
+                           blk, items, n_items, (const void *)pd.a_fp32, pd.a_fp32_stride, pd.pairs);
+        break;
     default:
-        hipLaunchKernelGGL(apply_fp32_stream<kVec16>, dim3(cfg.grid), dim3(kThreads), 0, st, blk,
-                           items, n_items, pd.a_fp32, pd.a_fp32_stride, pd.pairs);
+        hipLaunchKernelGGL((apply_fp32_stream<kVec16, kStage>), dim3(cfg.grid), dim3(kThreads), 0,
+                           st, blk, items, n_items, pd.a_fp32, pd.a_fp32_stride, pd.pairs);
         break;
     }
     return hipGetLastError();
 }
 
-template <bool kBf16, bool kSplit, bool kVec16>
+template <bool kVec16>
+static hipError_t launch_3m_t(const LaunchCfg &cfg, BfHeader *blk, int n_items, const PlanDev &pd,
+                              hipStream_t st)
+{
+    const BfItem *items = items_of(blk);
+    if (cfg.schedule == 0)
+        hipLaunchKernelGGL(apply_fp32_3m_single<kVec16>, dim3(n_items), dim3(kThreads), 0, st, blk,
+                           items, n_items, pd.a_3m, pd.a_3m_stride, pd.pairs);
+    else
+        hipLaunchKernelGGL((apply_fp32_ws<kVec16, true>), dim3(cfg.grid), dim3(kWsThreads), 0, st,
+                           blk, items, n_items, (const void *)pd.a_3m, pd.a_3m_stride, pd.pairs);
+    return hipGetLastError();
+}
+
+template <bool kBf16, bool kSplit, bool kVec16, bool kStage>
 static hipError_t launch_lp_t(const LaunchCfg &cfg, BfHeader *blk, int n_items, const PlanDev &pd,
                               hipStream_t st)
 {
     const BfItem *items = items_of(blk);
     if (cfg.schedule == 0)
-        hipLaunchKernelGGL((apply_lp_single<kBf16, kSplit, kVec16>), dim3(n_items), dim3(kThreads), 0,
-                           st, blk, items, n_items, pd);
+        hipLaunchKernelGGL((apply_lp_single<kBf16, kSplit, kVec16, kStage>), dim3(n_items),
+                           dim3(kThreads), 0, st, blk, items, n_items, pd);
     else
-        hipLaunchKernelGGL((apply_lp_stream<kBf16, kSplit, kVec16>), dim3(cfg.grid), dim3(kThreads),
-                           0, st, blk, items, n_items, pd);
+        hipLaunchKernelGGL((apply_lp_stream<kBf16, kSplit, kVec16, kStage>), dim3(cfg.grid),
+                           dim3(kThreads), 0, st, blk, items, n_items, pd);
     return hipGetLastError();
 }
 
@@ -902,8 +1235,11 @@ template <bool kBf16, bool kSplit>
 static hipError_t launch_lp_v(const LaunchCfg &cfg, BfHeader *blk, int n_items, const PlanDev &pd,
                               hipStream_t st)
 {
-    return cfg.vec16 ? launch_lp_t<kBf16, kSplit, true>(cfg, blk, n_items, pd, st)
-                     : launch_lp_t<kBf16, kSplit, false>(cfg, blk, n_items, pd, st);
+    if (cfg.stage)
+        return cfg.vec16 ? launch_lp_t<kBf16, kSplit, true, true>(cfg, blk, n_items, pd, st)
+                         : launch_lp_t<kBf16, kSplit, false, true>(cfg, blk, n_items, pd, st);
+    return cfg.vec16 ? launch_lp_t<kBf16, kSplit, true, false>(cfg, blk, n_items, pd, st)
+                     : launch_lp_t<kBf16, kSplit, false, false>(cfg, blk, n_items, pd, st);
 }
 
 hipError_t launch_apply(const LaunchCfg &cfg, BfHeader *blk, int n_items, const PlanDev &pd,
@@ -913,8 +1249,14 @@ hipError_t launch_apply(const LaunchCfg &cfg, BfHeader *blk, int n_items, const 
         return hipSuccess;
     switch (cfg.prec) {
     case BF_FP32:
-        return cfg.vec16 ? launch_fp32_t<true>(cfg, blk, n_items, pd, st)
-                         : launch_fp32_t<false>(cfg, blk, n_items, pd, st);
+        if (cfg.stage)
+            return cfg.vec16 ? launch_fp32_t<true, true>(cfg, blk, n_items, pd, st)
+                             : launch_fp32_t<false, true>(cfg, blk, n_items, pd, st);
+        return cfg.vec16 ? launch_fp32_t<true, false>(cfg, blk, n_items, pd, st)
+                         : launch_fp32_t<false, false>(cfg, blk, n_items, pd, st);
+    case BF_FP32_3M:
+        return cfg.vec16 ? launch_3m_t<true>(cfg, blk, n_items, pd, st)
+                         : launch_3m_t<false>(cfg, blk, n_items, pd, st);
     case BF_FP16: return launch_lp_v<false, false>(cfg, blk, n_items, pd, st);
     case BF_BF16: return launch_lp_v<true, false>(cfg, blk, n_items, pd, st);
     case BF_FP16X2: return launch_lp_v<false, true>(cfg, blk, n_items, pd, st);
@@ -924,37 +1266,55 @@ hipError_t launch_apply(const LaunchCfg &cfg, BfHeader *blk, int n_items, const 
 }
 
 template <typename K>
-static int occ_of(K kernel)
+static int occ_of(K kernel, int threads = kThreads)
 {
     int blocks = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kernel, kThreads, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kernel, threads, 0);
     return (e == hipSuccess && blocks > 0) ? blocks : 1;
 }
 
-template <bool kBf16, bool kSplit>
+template <bool kBf16, bool kSplit, bool kStage>
 static int occ_lp(int schedule, bool vec16)
 {
     if (schedule == 0)
-        return vec16 ? occ_of(apply_lp_single<kBf16, kSplit, true>)
-                     : occ_of(apply_lp_single<kBf16, kSplit, false>);
-    return vec16 ? occ_of(apply_lp_stream<kBf16, kSplit, true>)
-                 : occ_of(apply_lp_stream<kBf16, kSplit, false>);
+        return vec16 ? occ_of(apply_lp_single<kBf16, kSplit, true, kStage>)
+                     : occ_of(apply_lp_single<kBf16, kSplit, false, kStage>);
+    return vec16 ? occ_of(apply_lp_stream<kBf16, kSplit, true, kStage>)
+                 : occ_of(apply_lp_stream<kBf16, kSplit, false, kStage>);
 }
 
-int apply_occupancy(int prec, int schedule, bool vec16)
+template <bool kStage>
+static int occ_fp32(int schedule, bool vec16)
+{
+    switch (schedule) {
+    case 0: return vec16 ? occ_of(apply_fp32_single<true, kStage>) : occ_of(apply_fp32_single<false, kStage>);
+    case 1: return vec16 ? occ_of(apply_fp32_claim<true>) : occ_of(apply_fp32_claim<false>);
+    case 3: return vec16 ? occ_of(apply_fp32_ws<true, false>, kWsThreads)
+                         : occ_of(apply_fp32_ws<false, false>, kWsThreads);
+    default: return vec16 ? occ_of(apply_fp32_stream<true, kStage>) : occ_of(apply_fp32_stream<false, kStage>);
+    }
+}
+
+template <bool kStage>
+static int occ_any(int prec, int schedule, bool vec16)
 {
     switch (prec) {
-    case BF_FP16: return occ_lp<false, false>(schedule, vec16);
-    case BF_BF16: return occ_lp<true, false>(schedule, vec16);
-    case BF_FP16X2: return occ_lp<false, true>(schedule, vec16);
-    case BF_BF16X2: return occ_lp<true, true>(schedule, vec16);
-    default: break;
+    case BF_FP32_3M:
+        if (schedule == 0)
+            return vec16 ? occ_of(apply_fp32_3m_single<true>) : occ_of(apply_fp32_3m_single<false>);
+        return vec16 ? occ_of(apply_fp32_ws<true, true>, kWsThreads)
+                     : occ_of(apply_fp32_ws<false, true>, kWsThreads);
+    case BF_FP16: return occ_lp<false, false, kStage>(schedule, vec16);
+    case BF_BF16: return occ_lp<true, false, kStage>(schedule, vec16);
+    case BF_FP16X2: return occ_lp<false, true, kStage>(schedule, vec16);
+    case BF_BF16X2: return occ_lp<true, true, kStage>(schedule, vec16);
+    default: return occ_fp32<kStage>(schedule, vec16);
     }
-    switch (schedule) {
-    case 0: return vec16 ? occ_of(apply_fp32_single<true>) : occ_of(apply_fp32_single<false>);
-    case 1: return vec16 ? occ_of(apply_fp32_claim<true>) : occ_of(apply_fp32_claim<false>);
-    default: return vec16 ? occ_of(apply_fp32_stream<true>) : occ_of(apply_fp32_stream<false>);
-    }
+}
+
+int apply_occupancy(int prec, int schedule, bool vec16, bool stage)
+{
+    return stage ? occ_any<true>(prec, schedule, vec16) : occ_any<false>(prec, schedule, vec16);
 }
 
 }  // namespace bfk

@@ -35,31 +35,37 @@ def main(argv=None) -> int:
     ap.add_argument("--grid", type=int, default=0, help="workgroups (0: 256 CUs x 8)")
     ap.add_argument("--variant", type=int, default=1,
                     help="bit 0 non-temporal, bits 1-2 log2 unroll (default 1: plain nt copy)")
+    ap.add_argument("--mode", default="copy", choices=["copy", "read", "write"])
     a = ap.parse_args(argv)
     import torch
     if not LIB.exists():
         raise RuntimeError(f"{LIB} not built")
     L = ctypes.CDLL(str(LIB))
-    L.bfprobe_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
-                               ctypes.c_int, ctypes.c_void_p]
+    L.bfprobe_stream.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
+                                 ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+    mode = {"copy": 0, "read": 1, "write": 2}[a.mode]
     nbytes = a.mib << 20
     src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     grid = a.grid or 256 * 8
     st = torch.cuda.current_stream()
     for _ in range(3):
-        assert L.bfprobe_copy(src.data_ptr(), dst.data_ptr(), nbytes, grid, a.variant, st.cuda_stream) == 0
+        assert L.bfprobe_stream(src.data_ptr(), dst.data_ptr(), nbytes, grid, a.variant, mode,
+                                st.cuda_stream) == 0
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(st)
     for _ in range(a.iters):
-        L.bfprobe_copy(src.data_ptr(), dst.data_ptr(), nbytes, grid, a.variant, st.cuda_stream)
+        L.bfprobe_stream(src.data_ptr(), dst.data_ptr(), nbytes, grid, a.variant, mode, st.cuda_stream)
     e1.record(st)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / a.iters
-    assert bool(torch.equal(src[:1024], dst[:1024]))
-    print(json.dumps({"probe": "hbm_copy", "bytes_read": nbytes, "bytes_written": nbytes,
-                      "us": round(ms * 1e3, 2), "GBps_rw": round(2 * nbytes / ms / 1e6, 1),
+    rd = nbytes if mode != 2 else 0
+    wr = nbytes if mode != 1 else 0
+    if mode == 0:
+        assert bool(torch.equal(src[:1024], dst[:1024]))
+    print(json.dumps({"probe": "hbm_" + a.mode, "bytes_read": rd, "bytes_written": wr,
+                      "us": round(ms * 1e3, 2), "GBps": round((rd + wr) / ms / 1e6, 1),
                       "grid": grid, "variant": a.variant}), flush=True)
     return 0
 

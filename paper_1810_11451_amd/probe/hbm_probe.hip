@@ -1,7 +1,8 @@
-// HBM reference kernels: a plain streaming copy of known size.  Used to
-// measure achievable bandwidth next to the spec-sheet peak, and to scale
-// the FETCH_SIZE / WRITE_SIZE counters (bytes a counter reports for a copy
-// whose traffic is known).
+// HBM reference kernels.  A plain streaming copy of known size measures
+// achievable bandwidth next to the spec-sheet peak and scales the
+// FETCH_SIZE / WRITE_SIZE counters (bytes a counter reports for a copy
+// whose traffic is known); read-only and write-only streams give the
+// ceilings of each direction alone.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -35,25 +36,74 @@ __global__ __launch_bounds__(256) void copy_kernel(const f4v *__restrict__ src,
     }
 }
 
-// variant: bit 0 = non-temporal, bits 1-2 = log2 of the per-thread unroll.
-extern "C" int bfprobe_copy(const void *src, void *dst, uint64_t bytes, int grid, int variant,
-                            void *stream)
+// Read-only stream: each thread sums what it reads and writes one value
+// per thread (negligible traffic), so the loads cannot be dropped.
+template <int kU>
+__global__ __launch_bounds__(256) void read_kernel(const f4v *__restrict__ src, f4v *__restrict__ dst,
+                                                   size_t n)
 {
-    if (!src || !dst || (bytes & 15) || grid <= 0 || variant < 0 || variant > 7)
+    const size_t step = (size_t)gridDim.x * 256 * kU;
+    f4v acc = {0.f, 0.f, 0.f, 0.f};
+    for (size_t base = (size_t)blockIdx.x * 256 * kU + threadIdx.x; base < n; base += step) {
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const size_t i = base + (size_t)u * 256;
+            if (i < n)
+                acc += __builtin_nontemporal_load(src + i);
+        }
+    }
+    dst[(size_t)blockIdx.x * 256 + threadIdx.x] = acc;
+}
+
+// Write-only stream of a constant.
+template <int kU>
+__global__ __launch_bounds__(256) void write_kernel(f4v *__restrict__ dst, size_t n, float v)
+{
+    const size_t step = (size_t)gridDim.x * 256 * kU;
+    const f4v x = {v, v, v, v};
+    for (size_t base = (size_t)blockIdx.x * 256 * kU + threadIdx.x; base < n; base += step) {
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const size_t i = base + (size_t)u * 256;
+            if (i < n)
+                __builtin_nontemporal_store(x, dst + i);
+        }
+    }
+}
+
+// variant: bit 0 = non-temporal, bits 1-2 = log2 of the per-thread unroll.
+// mode: 0 copy, 1 read only (dst needs grid * 256 * 16 bytes), 2 write only.
+extern "C" int bfprobe_stream(const void *src, void *dst, uint64_t bytes, int grid, int variant,
+                              int mode, void *stream)
+{
+    if (!dst || (bytes & 15) || grid <= 0 || variant < 0 || variant > 7 || mode < 0 || mode > 2 ||
+        (mode != 2 && !src))
         return -1;
     const size_t n = bytes / 16;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const f4v *s = static_cast<const f4v *>(src);
     f4v *d = static_cast<f4v *>(dst);
-    switch (variant) {
-    case 0: hipLaunchKernelGGL((copy_kernel<1, false>), dim3(grid), dim3(256), 0, st, s, d, n); break;
-    case 1: hipLaunchKernelGGL((copy_kernel<1, true>), dim3(grid), dim3(256), 0, st, s, d, n); break;
-    case 2: hipLaunchKernelGGL((copy_kernel<2, false>), dim3(grid), dim3(256), 0, st, s, d, n); break;
-    case 3: hipLaunchKernelGGL((copy_kernel<2, true>), dim3(grid), dim3(256), 0, st, s, d, n); break;
-    case 4: hipLaunchKernelGGL((copy_kernel<4, false>), dim3(grid), dim3(256), 0, st, s, d, n); break;
-    case 5: hipLaunchKernelGGL((copy_kernel<4, true>), dim3(grid), dim3(256), 0, st, s, d, n); break;
-    case 6: hipLaunchKernelGGL((copy_kernel<8, false>), dim3(grid), dim3(256), 0, st, s, d, n); break;
-    default: hipLaunchKernelGGL((copy_kernel<8, true>), dim3(grid), dim3(256), 0, st, s, d, n); break;
+    if (mode == 1) {
+        hipLaunchKernelGGL((read_kernel<4>), dim3(grid), dim3(256), 0, st, s, d, n);
+    } else if (mode == 2) {
+        hipLaunchKernelGGL((write_kernel<4>), dim3(grid), dim3(256), 0, st, d, n, 1.0f);
+    } else {
+        switch (variant) {
+        case 0: hipLaunchKernelGGL((copy_kernel<1, false>), dim3(grid), dim3(256), 0, st, s, d, n); break;
+        case 1: hipLaunchKernelGGL((copy_kernel<1, true>), dim3(grid), dim3(256), 0, st, s, d, n); break;
+        case 2: hipLaunchKernelGGL((copy_kernel<2, false>), dim3(grid), dim3(256), 0, st, s, d, n); break;
+        case 3: hipLaunchKernelGGL((copy_kernel<2, true>), dim3(grid), dim3(256), 0, st, s, d, n); break;
+        case 4: hipLaunchKernelGGL((copy_kernel<4, false>), dim3(grid), dim3(256), 0, st, s, d, n); break;
+        case 5: hipLaunchKernelGGL((copy_kernel<4, true>), dim3(grid), dim3(256), 0, st, s, d, n); break;
+        case 6: hipLaunchKernelGGL((copy_kernel<8, false>), dim3(grid), dim3(256), 0, st, s, d, n); break;
+        default: hipLaunchKernelGGL((copy_kernel<8, true>), dim3(grid), dim3(256), 0, st, s, d, n); break;
+        }
     }
     return hipGetLastError() == hipSuccess ? 0 : -3;
+}
+
+extern "C" int bfprobe_copy(const void *src, void *dst, uint64_t bytes, int grid, int variant,
+                            void *stream)
+{
+    return bfprobe_stream(src, dst, bytes, grid, variant, 0, stream);
 }

@@ -1,0 +1,86 @@
+"""GPU parity of the three-product (Gauss) FP32 form against the FP64 oracle.
+
+Bar: relative Frobenius error <= 2e-6 per product, as for the four-product
+form.  Exact-integer inputs stay exact (every partial sum, including
+(Wr + Wi)(Sr + Si), is an integer far below 2^24), so there the comparison
+is bitwise.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import FP32_TOL, announce, rel_errors, run_batch
+from oracle import oracle as orc
+from paper_1810_11451_amd import bf
+from paper_1810_11451_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+P = bf.BF_FP32_3M
+VARIANTS = {"one-per-wg": (0, 0, 0), "ws-sorted": (3, 0, 1), "ws-asgiven": (3, 0, 0),
+            "mapped-from-stream": (2, 2, 1)}
+
+
+@pytest.mark.parametrize("vname", sorted(VARIANTS))
+@pytest.mark.parametrize("seed", [801, 802])
+def test_ragged_all_f(vname, seed):
+    rng = np.random.default_rng(seed)
+    f_values = np.repeat(np.arange(0, 37), 3)
+    b = wl.random_batch(rng, len(f_values), 6, f_values=f_values)
+    announce(f"3m ragged seed={seed} variant={vname}")
+    R = run_batch(b, prec=P, variant=VARIANTS[vname])
+    err, _ = rel_errors(b, R)
+    nz = b.f > 0
+    assert np.all(R[~nz] == 0)
+    assert np.max(err[nz]) <= FP32_TOL, f"max rel err {np.max(err[nz]):.3g}"
+
+
+@pytest.mark.parametrize("vname", ["one-per-wg", "ws-sorted"])
+def test_exact_integers_bitwise(vname):
+    rng = np.random.default_rng(803)
+    b = wl.exact_integer_batch(rng, 200, 5)
+    announce(f"3m exact integers variant={vname}")
+    R = run_batch(b, prec=P, variant=VARIANTS[vname])
+    assert np.array_equal(R.astype(np.complex128), orc.apply(b))
+
+
+@pytest.mark.parametrize("f_max", [1, 2, 7, 36])
+def test_small_pools(f_max):
+    rng = np.random.default_rng(810 + f_max)
+    b = wl.random_batch(rng, 60, 3, f_max=f_max)
+    announce(f"3m pool f_max={f_max}")
+    R = run_batch(b, prec=P)
+    err, _ = rel_errors(b, R)
+    nz = b.f > 0
+    assert np.max(err[nz], initial=0) <= FP32_TOL
+    assert np.all(R[~nz] == 0)
+
+
+def test_dft_and_identity_within_bar():
+    rng = np.random.default_rng(804)
+    W = np.stack([wl.dft_w(36), wl.identity_w(36, 36)])
+    f = np.array([36, 36, 17, 36], np.int32)
+    w_ids = np.array([0, 1, 1, 0], np.int32)
+    blocks = [wl.qam256(rng, (int(x), wl.B)) for x in f]
+    b = wl._pack("dft+identity", W, w_ids, f, blocks)
+    announce("3m dft + identity")
+    R = run_batch(b, prec=P)
+    err, _ = rel_errors(b, R)
+    assert np.max(err) <= FP32_TOL
+
+
+def test_full_width_workload_sampled():
+    b = wl.config2()
+    announce(f"3m full-width n={b.n}")
+    R = run_batch(b, prec=P)
+    assert not np.any(np.isnan(R.view(np.float32)))
+    items = np.concatenate([np.random.default_rng(8).choice(b.n, 1024, replace=False), [0, b.n - 1]])
+    err, _ = rel_errors(b, R, items=items)
+    print(f"[fp32_3m] rel err p50 {np.median(err):.3g} max {err.max():.3g}", flush=True)
+    assert np.max(err) <= FP32_TOL
+
+
+def test_uneven_workload_all_items():
+    b = wl.config3()
+    announce(f"3m uneven n={b.n}")
+    R = run_batch(b, prec=P)
+    err, _ = rel_errors(b, R)
+    assert np.max(err) <= FP32_TOL

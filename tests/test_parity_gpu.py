@@ -25,6 +25,12 @@ VARIANTS = {
     "stream-occ-sorted": (2, 0, 1),
     "stream-1-asgiven": (2, 1, 0),
     "stream-2-sorted": (2, 2, 1),
+    "single-staged": (0, 0, 0, 1),
+    "stream-staged": (2, 0, 1, 1),
+    "stream-1-staged-asgiven": (2, 1, 0, 1),
+    "ws-sorted": (3, 0, 1),
+    "ws-asgiven": (3, 0, 0),
+    "ws-2-per-cu": (3, 2, 1),
 }
 
 

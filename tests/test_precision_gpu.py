@@ -27,7 +27,8 @@ LP = {"fp16": bf.BF_FP16, "bf16": bf.BF_BF16, "fp16x2": bf.BF_FP16X2, "bf16x2": 
 U = {"fp16": 2.0 ** -11, "bf16": 2.0 ** -8}
 BAR = {"fp16x2": 2e-5, "bf16x2": 2e-5,
        "fp16": 4 * U["fp16"] * math.sqrt(2), "bf16": 4 * U["bf16"] * math.sqrt(2)}
-VARIANTS = {"one-per-wg": (0, 0, 0), "stream": (2, 0, 1), "stream-2-asgiven": (2, 2, 0)}
+VARIANTS = {"one-per-wg": (0, 0, 0), "stream": (2, 0, 1), "stream-2-asgiven": (2, 2, 0),
+            "single-staged": (0, 0, 0, 1), "stream-staged": (2, 0, 1, 1)}
 
 
 @pytest.mark.parametrize("form", sorted(LP))
@@ -78,11 +79,11 @@ def test_all_forms_from_one_plan():
     assert bf.bf_plan_info(plan)[2] == bf.PREC_ALL
     ref = orc.apply(b)
     nz = b.f > 0
-    for name, p in [("fp32", bf.BF_FP32)] + sorted(LP.items()):
+    for name, p in [("fp32", bf.BF_FP32), ("fp32_3m", bf.BF_FP32_3M)] + sorted(LP.items()):
         announce(f"one plan, form={name}")
         R = run_batch(b, prec=p, plan=plan)
         err = orc.rel_frobenius(R, ref)
-        bar = 2e-6 if name == "fp32" else BAR[name]
+        bar = 2e-6 if name.startswith("fp32") else BAR[name]
         assert np.max(err[nz]) <= bar, name
     plan.close()
 
