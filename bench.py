@@ -213,7 +213,10 @@ def main(argv=None) -> int:
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", type=int, default=2, choices=sorted(CONFIGS))
-    ap.add_argument("--prec", default="fp32", choices=sorted(PRECS))
+    ap.add_argument("--prec", default="fp32_3m", choices=sorted(PRECS),
+                    help="arithmetic form (default: FP32, three real products per complex one)")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip timing the four-product FP32 kernel alongside")
     ap.add_argument("--copies", type=int, default=3, help="disjoint S/R buffer sets rotated")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -292,6 +295,19 @@ def main(argv=None) -> int:
     kern_ms = kernel_time_graph(plan, db, batch, prec, K, args.copies, torch, stream)
     kern_s = float(np.mean(kern_ms)) / 1e3
 
+    compare = None
+    if prec == bf.BF_FP32_3M and not args.no_compare:
+        # The four-product FP32 form on the same workload, kernel time only.
+        plan4 = bf.bf_plan_create(batch.W, bf.BF_PREC_BIT(bf.BF_FP32))
+        k4 = kernel_time_graph(plan4, db, batch, bf.BF_FP32, K, args.copies, torch, stream)
+        v4 = bf.bf_get_variant(plan4, bf.BF_FP32, bf.batch_bucket(batch.f))
+        plan4.close()
+        t4 = float(np.mean(k4)) / 1e3
+        compare = {"prec": "fp32", "kernel_us_mean": round(t4 * 1e6, 2),
+                   "tflops": round(batch.flops() / t4 / 1e12, 2),
+                   "frac": round(batch.flops() / t4 / 1e12 / PEAK_FP32_TFLOPS, 4),
+                   "variant": list(v4)}
+
     flops = batch.flops()
     nbytes = batch.bytes_moved()
     value = flops * K / wall / 1e9
@@ -337,7 +353,7 @@ def main(argv=None) -> int:
         "config": {"workload": batch.name, "n_products": batch.n, "n_w": batch.n_w,
                    "f": int(batch.f.max()) if batch.f.min() == batch.f.max() else "U{1..36}",
                    "prec": args.prec, "variant": {"schedule": variant[0], "wg_per_cu": variant[1],
-                                                  "order": variant[2]},
+                                                  "order": variant[2], "store": variant[3]},
                    "buffer_sets": args.copies},
         "latency_us": {"p50": round(float(np.percentile(step_ms, 50)) * 1e3, 2),
                        "p99": round(float(np.percentile(step_ms, 99)) * 1e3, 2)},
@@ -345,6 +361,11 @@ def main(argv=None) -> int:
     }
     if tuned is not None:
         out["config"]["autotuned_us"] = round(tuned[1], 2)
+    if prec == bf.BF_FP32_3M:
+        out["config"]["product"] = ("FP32, three real products per complex product (Gauss); "
+                                    "flops counted as 8 per complex multiply-add")
+    if compare is not None:
+        out["compare_fp32_four_product"] = compare
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(batch, args.cpu_seconds)
     plan.close()

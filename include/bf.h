@@ -152,12 +152,16 @@ bf_status bf_graph_destroy(bf_graph graph);
  * then on.  The table can be saved to and loaded from a text file. */
 typedef struct {
     int32_t schedule;      /* 0: one product per workgroup; 1: persistent, atomic claim;
-                              2: persistent, static share per XCD, next S prefetched */
+                              2: persistent, static share per XCD, next S prefetched;
+                              3: persistent, wave-specialised (matrix-core waves and
+                              data-movement waves), FP32 forms only */
     int32_t wg_per_cu;     /* persistent grid = wg_per_cu * CU count (ignored for 0) */
     int32_t order;         /* 0: as given; 1: longest f first, then by W id */
-    int32_t store;         /* 0: lanes write their accumulators directly;
-                              1: each wave stages its 16 rows of R in LDS and writes
-                              them as contiguous 16-byte stores (not for schedule 1) */
+    int32_t store;         /* schedules 0 and 2: 0 = lanes write their accumulators
+                              directly, 1 = each wave stages its 16 rows of R in LDS
+                              and writes them as contiguous 16-byte stores;
+                              schedule 3 (always staged): producer waves per
+                              workgroup, 0 = 4, 1 = 8 */
 } bf_variant;
 
 bf_status bf_set_variant(bf_plan plan, bf_prec prec, int32_t f_bucket, const bf_variant *v);

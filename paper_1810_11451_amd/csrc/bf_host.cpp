@@ -85,19 +85,22 @@ static void release_slot(StagingSlot &s)
     s = StagingSlot{};
 }
 
-// Defaults measured on MI355X: full-width batches (mean f 36) stream
-// through persistent workgroups with the next S prefetched; batches of
-// mixed or small f run one product per workgroup in the order given.
+// Defaults measured on MI355X (see the tuning notes in the design
+// document): full-width batches (mean f 36) run persistent workgroups,
+// batches of mixed or small f one product per workgroup in the order given.
 static bf_status default_variants(bf_plan p)
 {
     for (int pr = 0; pr < kPrecCount; ++pr)
         for (int b = 0; b < kBucketCount; ++b) {
             bf_variant v{};
             const bool full = b == kBucketCount - 1;
-            v.schedule = full ? (pr == BF_FP32 || pr == BF_FP32_3M ? 3 : 2) : 0;
-            v.wg_per_cu = 0;   // 0: the kernel's occupancy
-            v.order = full ? 1 : 0;
-            v.store = full ? 1 : 0;
+            const bool fp32 = pr == BF_FP32 || pr == BF_FP32_3M;
+            if (full && fp32)
+                v = bf_variant{3, 0, 1, 1};   // wave-specialised, 8 producer waves
+            else if (full)
+                v = bf_variant{2, 2, 0, 0};   // 16-bit forms: streaming, 2 per CU
+            else
+                v = bf_variant{0, 0, 0, 0};   // mixed or small f: one per workgroup
             p->table[pr][b] = v;
         }
     return BF_OK;
@@ -315,7 +318,11 @@ bfk::LaunchCfg choose_launch(bf_plan p, bf_prec prec, int n, int max_f, bool vec
     else if (prec != BF_FP32 && prec != BF_FP32_3M && (cfg.schedule == 1 || cfg.schedule == 3))
         cfg.schedule = 2;   // the 16-bit forms have no claim or wave-specialised schedule
     cfg.vec16 = vec16;
+    if (cfg.schedule == 3 && !vec16)   // its producers move S in 16-byte chunks only
+        cfg.schedule = prec == BF_FP32_3M ? 0 : 2;
     cfg.stage = cfg.schedule == 3 || prec == BF_FP32_3M || (v.store == 1 && cfg.schedule != 1);
+    // For schedule 3 the store field selects the producer count: 0 -> 4, 1 -> 8.
+    cfg.producers = (cfg.schedule == 3 && v.store == 1) ? 8 : 4;
     if (v.schedule == 0) {
         cfg.grid = n;
     } else {

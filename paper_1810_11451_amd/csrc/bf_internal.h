@@ -84,6 +84,7 @@ struct LaunchCfg {
     int grid;        // workgroups
     bool vec16;      // all S 16-byte aligned
     bool stage;      // R rows staged in LDS and written as contiguous 16-byte stores
+    int producers;   // schedule 3: producer waves per workgroup (4 or 8)
 };
 
 hipError_t launch_apply(const LaunchCfg &cfg, BfHeader *blk, int n_items, const PlanDev &pd,

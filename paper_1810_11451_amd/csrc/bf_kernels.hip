@@ -647,11 +647,11 @@ __global__ __launch_bounds__(kThreads) void apply_fp32_stream(BfHeader *__restri
     }
 }
 
-// kSched 3: wave-specialised persistent kernel (FP32).  Eight waves per
-// workgroup: waves 0-3 (one per SIMD) only run matrix-core steps from LDS,
-// waves 4-7 only move data.  Per product t of the workgroup's share (a
-// contiguous run of its XCD group's range):
-//   consumers: contract S(t) from s_buf[t % 2], accumulators -> r_buf[t % 2];
+// kSched 3: wave-specialised persistent kernel (FP32 forms).  4 + kProd
+// waves per workgroup: waves 0-3 (one per SIMD) only run matrix-core steps
+// from LDS; the kProd producer waves only move data.  Per product t of the
+// workgroup's share (a contiguous run of its XCD group's range):
+//   consumers: contract S(t) from s_buf[t % 2], results -> r_buf[t % 2];
 //   producers: write R(t-1) from r_buf[(t-1) % 2] with contiguous 16-byte
 //              stores; move S(t+1) from registers to s_buf[(t+1) % 2]; issue
 //              the loads of S(t+2) into registers;
@@ -660,20 +660,71 @@ __global__ __launch_bounds__(kThreads) void apply_fp32_stream(BfHeader *__restri
 // that iteration's barrier; one written in t is read in t+1.  The two roles
 // run separate loops with the same number of barriers, so neither role's
 // memory waits hold up the other's instructions.
-constexpr int kWsThreads = 2 * kThreads;
 
-template <bool kVec16, bool k3M>
-__global__ __launch_bounds__(kWsThreads) void apply_fp32_ws(BfHeader *__restrict__ blk,
-                                                            const BfItem *__restrict__ items,
-                                                            int n_items, const void *__restrict__ apool,
-                                                            int a_w_stride, int pairs)
+// Producer-side staging of S over kProd waves (16-byte chunks, clamped).
+template <int kProd>
+struct PRegs {
+    static constexpr int kN = (kFMax * kB / 2 + 64 * kProd - 1) / (64 * kProd);
+    f4v v[kN];
+};
+
+template <int kProd>
+__device__ __forceinline__ void p_load_s(PRegs<kProd> &r, const float2 *__restrict__ S, int f, int ptid)
+{
+    g_cf4v *src = (g_cf4v *)S;
+    const int last = (f > 0 ? f * (kB / 2) : 1) - 1;
+#pragma unroll
+    for (int u = 0; u < PRegs<kProd>::kN; ++u)
+        r.v[u] = __builtin_nontemporal_load(src + min(ptid + u * 64 * kProd, last));
+}
+
+template <int kProd>
+__device__ __forceinline__ void p_put_s(f2v *__restrict__ lds, const PRegs<kProd> &r, int f, int ptid)
+{
+    const int chunks = f * (kB / 2);
+#pragma unroll
+    for (int u = 0; u < PRegs<kProd>::kN; ++u) {
+        const int c = ptid + u * 64 * kProd;
+        if (c < chunks) {
+            const int row = c / (kB / 2);
+            const int col2 = c - row * (kB / 2);
+            *reinterpret_cast<f4v *>(lds + row * kLdsCols + 2 * col2) = r.v[u];
+        }
+    }
+    if (f & 1) {
+        if (ptid < kLdsCols)
+            lds[f * kLdsCols + ptid] = f2v{0.f, 0.f};
+    }
+}
+
+// Writes the whole staged R tile (64 x 60 complex, 1920 16-byte chunks) with
+// kProd waves.  Chunk indices past the end are clamped: those threads write
+// the last chunk again with the same data, so every store is unconditional.
+template <int kProd>
+__device__ __forceinline__ void p_store_r(float2 *__restrict__ Rp, const f2v *__restrict__ tile, int ptid)
+{
+    constexpr int kChunks = kM * kB / 2;
+    constexpr int kRounds = (kChunks + 64 * kProd - 1) / (64 * kProd);
+    g_f4v *dst = (g_f4v *)Rp;
+    const f4v *src = reinterpret_cast<const f4v *>(tile);
+#pragma unroll
+    for (int u = 0; u < kRounds; ++u) {
+        const int c = min(ptid + u * 64 * kProd, kChunks - 1);
+        __builtin_nontemporal_store(src[c], dst + c);
+    }
+}
+
+// S must be 16-byte aligned (the host routes other batches elsewhere).
+template <bool k3M, int kProd>
+__global__ __launch_bounds__(64 * (kWaves + kProd)) void apply_fp32_ws(
+    BfHeader *__restrict__ blk, const BfItem *__restrict__ items, int n_items,
+    const void *__restrict__ apool, int a_w_stride, int pairs)
 {
     __shared__ f2v s_buf[2][kFMax * kLdsCols];
-    __shared__ f2v r_buf[2][kWaves][kWaveOut];
+    __shared__ f2v r_buf[2][kM * kB];
     __shared__ int meta[2][2];   // (W id, f) of the product staged in s_buf[i]
     const int wave8 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int wave = wave8 & (kWaves - 1);
     float2 *sink = sink_of(blk);
 
     const int G = gridDim.x;
@@ -692,6 +743,7 @@ __global__ __launch_bounds__(kWsThreads) void apply_fp32_ws(BfHeader *__restrict
 
     if (wave8 < kWaves) {
         // consumer
+        const int wave = wave8;
         using AReg = typename std::conditional<k3M, f4v, f2v>::type;
         AReg a[kPairsMax];
         int cur_w = -1;
@@ -709,22 +761,22 @@ __global__ __launch_bounds__(kWsThreads) void apply_fp32_ws(BfHeader *__restrict
                                 wave, lane);
             }
             if constexpr (k3M) {
-                contract_stage_3m(s_buf[t & 1], a, f, wave, lane, &r_buf[t & 1][0][0]);
+                contract_stage_3m(s_buf[t & 1], a, f, wave, lane, r_buf[t & 1]);
             } else {
                 floatx16 acc0, acc1;
                 contract_fp32(s_buf[t & 1], a, f, lane, acc0, acc1);
-                stage_acc(r_buf[t & 1][wave], lane, acc0, acc1);
+                stage_acc(r_buf[t & 1] + wave * kWaveOut, lane, acc0, acc1);
             }
             __syncthreads();
         }
     } else {
         // producer
-        const int ptid = threadIdx.x - kThreads;
-        SRegs<kVec16> sr;
+        const int ptid = threadIdx.x - 64 * kWaves;
+        PRegs<kProd> sr;
         {
             const BfItem d0 = items[start];
-            load_s<kVec16>(sr, d0.f > 0 ? d0.S : sink, d0.f, ptid);
-            put_s<kVec16>(s_buf[0], sr, d0.f, ptid);
+            p_load_s<kProd>(sr, d0.f > 0 ? d0.S : sink, d0.f, ptid);
+            p_put_s<kProd>(s_buf[0], sr, d0.f, ptid);
             if (ptid == 0) {
                 meta[0][0] = d0.w_id;
                 meta[0][1] = d0.f;
@@ -732,15 +784,15 @@ __global__ __launch_bounds__(kWsThreads) void apply_fp32_ws(BfHeader *__restrict
         }
         if (n_my > 1) {
             const BfItem d1 = items[start + 1];
-            load_s<kVec16>(sr, d1.f > 0 ? d1.S : sink, d1.f, ptid);
+            p_load_s<kProd>(sr, d1.f > 0 ? d1.S : sink, d1.f, ptid);
         }
         __syncthreads();
         for (int t = 0; t < n_my; ++t) {
             if (t >= 1)
-                store_staged(items[start + t - 1].R, r_buf[(t - 1) & 1][wave], wave, lane);
+                p_store_r<kProd>(items[start + t - 1].R, r_buf[(t - 1) & 1], ptid);
             if (t + 1 < n_my) {
                 const BfItem d1 = items[start + t + 1];
-                put_s<kVec16>(s_buf[(t + 1) & 1], sr, d1.f, ptid);
+                p_put_s<kProd>(s_buf[(t + 1) & 1], sr, d1.f, ptid);
                 if (ptid == 0) {
                     meta[(t + 1) & 1][0] = d1.w_id;
                     meta[(t + 1) & 1][1] = d1.f;
@@ -748,11 +800,11 @@ __global__ __launch_bounds__(kWsThreads) void apply_fp32_ws(BfHeader *__restrict
             }
             if (t + 2 < n_my) {
                 const BfItem dn = items[start + t + 2];
-                load_s<kVec16>(sr, dn.f > 0 ? dn.S : sink, dn.f, ptid);
+                p_load_s<kProd>(sr, dn.f > 0 ? dn.S : sink, dn.f, ptid);
             }
             __syncthreads();
         }
-        store_staged(items[start + n_my - 1].R, r_buf[(n_my - 1) & 1][wave], wave, lane);
+        p_store_r<kProd>(items[start + n_my - 1].R, r_buf[(n_my - 1) & 1], ptid);
     }
 }
 
@@ -1192,8 +1244,14 @@ static hipError_t launch_fp32_t(const LaunchCfg &cfg, BfHeader *blk, int n_items
                            items, n_items, pd.a_fp32, pd.a_fp32_stride, pd.pairs);
         break;
     case 3:
-        hipLaunchKernelGGL((apply_fp32_ws<kVec16, false>), dim3(cfg.grid), dim3(kWsThreads), 0, st,
-                           blk, items, n_items, (const void *)pd.a_fp32, pd.a_fp32_stride, pd.pairs);
+        if (cfg.producers == 8)
+            hipLaunchKernelGGL((apply_fp32_ws<false, 8>), dim3(cfg.grid), dim3(64 * 12), 0,
+                               st, blk, items, n_items, (const void *)pd.a_fp32, pd.a_fp32_stride,
+                               pd.pairs);
+        else
+            hipLaunchKernelGGL((apply_fp32_ws<false, 4>), dim3(cfg.grid), dim3(64 * 8), 0,
+                               st, blk, items, n_items, (const void *)pd.a_fp32, pd.a_fp32_stride,
+                               pd.pairs);
         break;
     default:
         hipLaunchKernelGGL((apply_fp32_stream<kVec16, kStage>), dim3(cfg.grid), dim3(kThreads), 0,
@@ -1211,8 +1269,11 @@ static hipError_t launch_3m_t(const LaunchCfg &cfg, BfHeader *blk, int n_items, 
     if (cfg.schedule == 0)
         hipLaunchKernelGGL(apply_fp32_3m_single<kVec16>, dim3(n_items), dim3(kThreads), 0, st, blk,
                            items, n_items, pd.a_3m, pd.a_3m_stride, pd.pairs);
+    else if (cfg.producers == 8)
+        hipLaunchKernelGGL((apply_fp32_ws<true, 8>), dim3(cfg.grid), dim3(64 * 12), 0, st,
+                           blk, items, n_items, (const void *)pd.a_3m, pd.a_3m_stride, pd.pairs);
     else
-        hipLaunchKernelGGL((apply_fp32_ws<kVec16, true>), dim3(cfg.grid), dim3(kWsThreads), 0, st,
+        hipLaunchKernelGGL((apply_fp32_ws<true, 4>), dim3(cfg.grid), dim3(64 * 8), 0, st,
                            blk, items, n_items, (const void *)pd.a_3m, pd.a_3m_stride, pd.pairs);
     return hipGetLastError();
 }
@@ -1289,8 +1350,7 @@ static int occ_fp32(int schedule, bool vec16)
     switch (schedule) {
     case 0: return vec16 ? occ_of(apply_fp32_single<true, kStage>) : occ_of(apply_fp32_single<false, kStage>);
     case 1: return vec16 ? occ_of(apply_fp32_claim<true>) : occ_of(apply_fp32_claim<false>);
-    case 3: return vec16 ? occ_of(apply_fp32_ws<true, false>, kWsThreads)
-                         : occ_of(apply_fp32_ws<false, false>, kWsThreads);
+    case 3: return occ_of(apply_fp32_ws<false, 4>, 512);
     default: return vec16 ? occ_of(apply_fp32_stream<true, kStage>) : occ_of(apply_fp32_stream<false, kStage>);
     }
 }
@@ -1302,8 +1362,7 @@ static int occ_any(int prec, int schedule, bool vec16)
     case BF_FP32_3M:
         if (schedule == 0)
             return vec16 ? occ_of(apply_fp32_3m_single<true>) : occ_of(apply_fp32_3m_single<false>);
-        return vec16 ? occ_of(apply_fp32_ws<true, true>, kWsThreads)
-                     : occ_of(apply_fp32_ws<false, true>, kWsThreads);
+        return occ_of(apply_fp32_ws<true, 4>, 512);
     case BF_FP16: return occ_lp<false, false, kStage>(schedule, vec16);
     case BF_BF16: return occ_lp<true, false, kStage>(schedule, vec16);
     case BF_FP16X2: return occ_lp<false, true, kStage>(schedule, vec16);

@@ -16,7 +16,7 @@ from paper_1810_11451_amd import workloads as wl
 pytestmark = pytest.mark.gpu
 P = bf.BF_FP32_3M
 VARIANTS = {"one-per-wg": (0, 0, 0), "ws-sorted": (3, 0, 1), "ws-asgiven": (3, 0, 0),
-            "mapped-from-stream": (2, 2, 1)}
+            "mapped-from-stream": (2, 2, 1), "ws-8-producers": (3, 0, 1, 1)}
 
 
 @pytest.mark.parametrize("vname", sorted(VARIANTS))

@@ -31,6 +31,7 @@ VARIANTS = {
     "ws-sorted": (3, 0, 1),
     "ws-asgiven": (3, 0, 0),
     "ws-2-per-cu": (3, 2, 1),
+    "ws-8-producers": (3, 0, 1, 1),
 }
 
 
