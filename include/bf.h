@@ -161,12 +161,15 @@ typedef struct {
                               directly, 1 = each wave stages its 16 rows of R in LDS
                               and writes them as contiguous 16-byte stores;
                               schedule 3 (always staged): producer waves per
-                              workgroup, 0 = 4, 1 = 8 */
+                              workgroup and products prefetched in their
+                              registers, 0 = (4, 1), 1 = (8, 1), 2 = (8, 2),
+                              3 = (8, 3), 4 = (12, 1), 5 = (12, 2) */
 } bf_variant;
 
 bf_status bf_set_variant(bf_plan plan, bf_prec prec, int32_t f_bucket, const bf_variant *v);
 bf_status bf_get_variant(bf_plan plan, bf_prec prec, int32_t f_bucket, bf_variant *v);
-/* f_bucket of a batch: its largest f divided by 9, i.e. 0..4. */
+/* Bucket of f: f / 9, i.e. 0..4.  A batch uses the bucket of its mean f
+ * (rounded to nearest). */
 int32_t bf_f_bucket(int32_t f);
 bf_status bf_autotune(bf_plan plan, int32_t batch, const int32_t *w_ids, const int32_t *f,
                       const void *const *S, void *const *R, bf_prec prec, int32_t reps,

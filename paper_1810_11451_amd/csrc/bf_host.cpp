@@ -96,7 +96,7 @@ static bf_status default_variants(bf_plan p)
             const bool full = b == kBucketCount - 1;
             const bool fp32 = pr == BF_FP32 || pr == BF_FP32_3M;
             if (full && fp32)
-                v = bf_variant{3, 0, 1, 1};   // wave-specialised, 8 producer waves
+                v = bf_variant{3, 0, 0, 5};   // wave-specialised, 12 producers, depth 2, as given
             else if (full)
                 v = bf_variant{2, 2, 0, 0};   // 16-bit forms: streaming, 2 per CU
             else
@@ -180,7 +180,7 @@ extern "C" bf_status bf_plan_create(bf_plan *out, const void *w_pool, int32_t n_
     }
     if (prec_mask & BF_PREC_BIT(BF_FP32_3M)) {
         p->a_3m_stride = bfk::fp32_3m_w_stride(p->pairs);
-        const size_t bytes = std::max<size_t>(16, (size_t)n_w * p->a_3m_stride * sizeof(float4));
+        const size_t bytes = std::max<size_t>(16, (size_t)n_w * p->a_3m_stride * sizeof(float));
         e = hipMalloc(&p->a_3m, bytes);
         if (e == hipSuccess && p->pairs > 0)
             e = bfk::launch_w_transform_3m(w_dev, n_w, f_max, p->a_3m, p->pairs, st);
@@ -320,9 +320,15 @@ bfk::LaunchCfg choose_launch(bf_plan p, bf_prec prec, int n, int max_f, bool vec
     cfg.vec16 = vec16;
     if (cfg.schedule == 3 && !vec16)   // its producers move S in 16-byte chunks only
         cfg.schedule = prec == BF_FP32_3M ? 0 : 2;
-    cfg.stage = cfg.schedule == 3 || prec == BF_FP32_3M || (v.store == 1 && cfg.schedule != 1);
-    // For schedule 3 the store field selects the producer count: 0 -> 4, 1 -> 8.
-    cfg.producers = (cfg.schedule == 3 && v.store == 1) ? 8 : 4;
+    cfg.stage = cfg.schedule == 3 || prec == BF_FP32_3M || (v.store >= 1 && cfg.schedule != 1);
+    // For schedule 3 the store field selects producer waves and prefetch
+    // depth: 0 -> (4, 1), 1 -> (8, 1), 2 -> (8, 2), 3 -> (8, 3), 4 -> (12, 1),
+    // 5 -> (12, 2).
+    static const int kProducers[6] = {4, 8, 8, 8, 12, 12};
+    static const int kDepths[6] = {1, 1, 2, 3, 1, 2};
+    const int ws = (cfg.schedule == 3 && v.store >= 0 && v.store <= 5) ? v.store : 0;
+    cfg.producers = kProducers[ws];
+    cfg.depth = kDepths[ws];
     if (v.schedule == 0) {
         cfg.grid = n;
     } else {
@@ -660,7 +666,7 @@ extern "C" bf_status bf_graph_destroy(bf_graph g)
 static bool valid_variant(const bf_variant &v)
 {
     return v.schedule >= 0 && v.schedule <= 3 && v.wg_per_cu >= 0 && v.wg_per_cu <= 64 &&
-           (v.order == 0 || v.order == 1) && (v.store == 0 || v.store == 1);
+           (v.order == 0 || v.order == 1) && v.store >= 0 && v.store <= (v.schedule == 3 ? 5 : 1);
 }
 
 extern "C" bf_status bf_set_variant(bf_plan p, bf_prec prec, int32_t bucket, const bf_variant *v)
@@ -718,6 +724,10 @@ extern "C" bf_status bf_autotune(bf_plan p, int32_t batch, const int32_t *w_ids,
         for (int w : per_cu)
             for (int o = 0; o < 2; ++o)
                 cands.push_back(bf_variant{2, w, o, st});
+    if (prec == BF_FP32 || prec == BF_FP32_3M)
+        for (int o = 0; o < 2; ++o)
+            for (int st = 0; st < 6; ++st)
+                cands.push_back(bf_variant{3, 0, o, st});
 
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -731,7 +741,7 @@ extern "C" bf_status bf_autotune(bf_plan p, int32_t batch, const int32_t *w_ids,
                 items[t] = BfItem{static_cast<const float2 *>(S[t]), static_cast<float2 *>(R[t]),
                                   w_ids[t], f[t], 0, 0};
                 fs.max_f = std::max(fs.max_f, (int)f[t]);
-            fs.sum_f += f[t];
+                fs.sum_f += f[t];
                 if (f[t] > 0 && !aligned16(S[t]))
                     fs.vec16 = false;
             }

@@ -38,7 +38,7 @@ struct bf_plan_s {
 
     float2 *a_fp32 = nullptr;   // FP32 operand layout, a_fp32_stride float2 per W
     size_t a_fp32_stride = 0;
-    float4 *a_3m = nullptr;     // FP32 three-product layout, a_3m_stride float4 per W
+    float *a_3m = nullptr;      // FP32 three-product layout, a_3m_stride floats per W
     size_t a_3m_stride = 0;
     // 16-bit operand layouts, index 0 = FP16, 1 = BF16 (lo only for split forms)
     void *lp_hi[2] = {nullptr, nullptr};

@@ -47,17 +47,17 @@ constexpr int kThreads = 64 * kWaves;
 // Operand layout of one W for the FP32 matrix-core form: float2 entries
 // [kWaves][pairs][64 lanes]; see bf_kernels.hip.
 inline size_t fp32_w_stride(int pairs) { return (size_t)kWaves * pairs * 64; }
-// Three-product FP32 form: float4 (Wr, Wi, Wr + Wi, 0) entries
-// [2 antenna halves][pairs][64 lanes] per W.
-inline size_t fp32_3m_w_stride(int pairs) { return (size_t)2 * pairs * 64; }
+// Three-product FP32 form: floats [2 antenna halves][pairs][3][64 lanes] per
+// W, the 3 being Wr, Wi and Wr + Wi of the lane's (antenna, flow).
+inline size_t fp32_3m_w_stride(int pairs) { return (size_t)2 * pairs * 3 * 64; }
 
 // Device-side view of a plan, as the apply kernels need it.
 struct PlanDev {
     const float2 *a_fp32;     // FP32 form: kWaves x pairs x 64 float2 per W
     int a_fp32_stride;        // float2 per W
     int pairs;                // ceil(f_max / 2)
-    const float4 *a_3m;       // three-product form: 2 x pairs x 64 float4 per W
-    int a_3m_stride;          // float4 per W
+    const float *a_3m;        // three-product form: 2 x pairs x 3 x 64 floats per W
+    int a_3m_stride;          // floats per W
     const void *lp_hi;        // 16-bit forms: kWaves x chunks x 64 x 16 bytes per W
     const void *lp_lo;        // (lo part, split forms only)
     const int *lp_exp;        // per-W power-of-two exponent of the 16-bit operands
@@ -71,7 +71,7 @@ inline size_t lp_w_units(int f_max) { return (size_t)kWaves * lp_chunks(f_max) *
 
 hipError_t launch_w_transform_fp32(const float2 *w_dev, int n_w, int f_max, float2 *a_out,
                                    int pairs, hipStream_t st);
-hipError_t launch_w_transform_3m(const float2 *w_dev, int n_w, int f_max, float4 *a_out,
+hipError_t launch_w_transform_3m(const float2 *w_dev, int n_w, int f_max, float *a_out,
                                  int pairs, hipStream_t st);
 // bf16 selects BF16 (else FP16); lo may be null (plain forms only).
 hipError_t launch_w_transform_lp(const float2 *w_dev, int n_w, int f_max, bool bf16, void *hi,
@@ -80,11 +80,12 @@ hipError_t launch_w_transform_lp(const float2 *w_dev, int n_w, int f_max, bool b
 struct LaunchCfg {
     int prec;        // bf_prec
     int schedule;    // 0 one product per workgroup, 1 persistent with atomic claim,
-                     // 2 persistent static share with prefetch
+                     // 2 persistent static share with prefetch, 3 wave-specialised
     int grid;        // workgroups
     bool vec16;      // all S 16-byte aligned
     bool stage;      // R rows staged in LDS and written as contiguous 16-byte stores
     int producers;   // schedule 3: producer waves per workgroup (4 or 8)
+    int depth;       // schedule 3: products of S prefetched in producer registers (1..3)
 };
 
 hipError_t launch_apply(const LaunchCfg &cfg, BfHeader *blk, int n_items, const PlanDev &pd,

@@ -32,12 +32,30 @@ namespace bfk {
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef float f2v __attribute__((ext_vector_type(2)));
 typedef float f4v __attribute__((ext_vector_type(4)));
+typedef float f3v __attribute__((ext_vector_type(3)));
 // Global-memory (address space 1) views, so that accesses through pointers
 // read from descriptors compile to global_* rather than flat_* instructions.
 typedef __attribute__((address_space(1))) f2v g_f2v;
 typedef __attribute__((address_space(1))) const f2v g_cf2v;
 typedef __attribute__((address_space(1))) const f4v g_cf4v;
 typedef __attribute__((address_space(1))) f4v g_f4v;
+// Descriptors are never written by a kernel; reading them through the
+// constant address space lets the compiler use scalar loads, which wait on
+// their own counter instead of behind the vector memory queue.
+typedef __attribute__((address_space(4))) const BfItem c_item;
+
+// Item k of a share that starts at p and takes every stride-th item.
+__device__ __forceinline__ BfItem item_at(c_item *p, int k, int stride)
+{
+    const int i = k * stride;
+    BfItem d;
+    d.S = p[i].S;
+    d.R = p[i].R;
+    d.w_id = p[i].w_id;
+    d.f = p[i].f;
+    d.pad0 = d.pad1 = 0;
+    return d;
+}
 
 constexpr int kLdsCols = 64;   // LDS row pitch of a staged S, in complex elements
 
@@ -95,30 +113,33 @@ hipError_t launch_w_transform_fp32(const float2 *w_dev, int n_w, int f_max, floa
 // (Wr, Wi, Wr + Wi, 0), the sum rounded once here.  Flows k >= f_max hold
 // zeros.
 __global__ void w_transform_3m_kernel(const float2 *__restrict__ w, int n_w, int f_max,
-                                      float4 *__restrict__ a, int pairs)
+                                      float *__restrict__ a, int pairs)
 {
-    const size_t total = (size_t)n_w * 2 * pairs * 64;
+    // Entry (W wi, half mt, pair p, component c, lane): antenna 32 mt + lane % 32,
+    // flow 2 p + lane / 32; c = 0, 1, 2 -> Wr, Wi, Wr + Wi (zero past f_max).
+    const size_t total = (size_t)n_w * 2 * pairs * 3 * 64;
     for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
          idx += (size_t)gridDim.x * blockDim.x) {
         const int lane = (int)(idx % 64);
-        const int p = (int)((idx / 64) % pairs);
-        const int mt = (int)((idx / (64 * (size_t)pairs)) % 2);
-        const size_t wi = idx / (64 * (size_t)pairs * 2);
+        const int c = (int)((idx / 64) % 3);
+        const int p = (int)((idx / (64 * 3)) % pairs);
+        const int mt = (int)((idx / (64 * 3 * (size_t)pairs)) % 2);
+        const size_t wi = idx / (64 * 3 * (size_t)pairs * 2);
         const int i = 32 * mt + (lane & 31);
         const int k = 2 * p + (lane >> 5);
-        float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
+        float out = 0.f;
         if (k < f_max) {
             const float2 v = w[(wi * kM + i) * (size_t)f_max + k];
-            out = make_float4(v.x, v.y, v.x + v.y, 0.f);
+            out = c == 0 ? v.x : (c == 1 ? v.y : v.x + v.y);
         }
         a[idx] = out;
     }
 }
 
-hipError_t launch_w_transform_3m(const float2 *w_dev, int n_w, int f_max, float4 *a_out,
+hipError_t launch_w_transform_3m(const float2 *w_dev, int n_w, int f_max, float *a_out,
                                  int pairs, hipStream_t st)
 {
-    const size_t total = (size_t)n_w * 2 * pairs * 64;
+    const size_t total = (size_t)n_w * 2 * pairs * 3 * 64;
     if (total == 0)
         return hipSuccess;
     const int block = 256;
@@ -361,6 +382,52 @@ __device__ __forceinline__ void contract_fp32(const f2v *__restrict__ lds, const
     }
 }
 
+// contract_fp32 for the wave-specialised schedule: once a pair's matrix-core
+// steps are issued its operand registers are free, and they are reloaded
+// there with the same pair of pool entry w_next (the next product's W), so
+// the next W arrives during this product's chain at no register cost.
+__device__ __forceinline__ void contract_fp32_reload(const f2v *__restrict__ lds, f2v (&a)[kPairsMax],
+                                                     int f, int lane, floatx16 &acc0, floatx16 &acc1,
+                                                     const float2 *__restrict__ apool, int w_next,
+                                                     int a_w_stride, int pairs, int wave)
+{
+    const int h = lane >> 5;
+    const int n = lane & 31;
+    const int np = (f + 1) >> 1;
+    const g_cf2v *nx = (const g_cf2v *)(apool + (size_t)w_next * a_w_stride + (size_t)wave * pairs * 64 + lane);
+    acc0 = floatx16{};
+    acc1 = floatx16{};
+    // The staged rows are read ahead of their products (rows past f hold
+    // older data and feed no product) in batches of 6 pairs: batch k is
+    // issued once pair 6k - 4 is, so at most 10 pairs occupy registers.
+    constexpr int kBatch = 6, kLead = 4;
+    f2v b0[kPairsMax], b1[kPairsMax];
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+        b0[q] = lds[(2 * q + h) * kLdsCols + n];
+        b1[q] = lds[(2 * q + h) * kLdsCols + 32 + n];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int p = 0; p < kPairsMax; ++p) {
+        if (p + kLead < kPairsMax && (p + kLead) % kBatch == 0) {
+#pragma unroll
+            for (int q = p + kLead; q < p + kLead + kBatch; ++q) {
+                b0[q] = lds[(2 * q + h) * kLdsCols + n];
+                b1[q] = lds[(2 * q + h) * kLdsCols + 32 + n];
+            }
+        }
+        if (p < np) {
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a[p].x, b0[p].x, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a[p].x, b1[p].x, acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a[p].y, b0[p].y, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a[p].y, b1[p].y, acc1, 0, 0, 0);
+        }
+        a[p] = nx[min(p, pairs - 1) * 64];
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Three-product FP32 form.  Wave w of a workgroup owns the 32 x 32 quadrant
 // (antennas 32 mt .. 32 mt + 31, columns 32 nt .. 32 nt + 31), mt = w / 2,
@@ -369,16 +436,22 @@ __device__ __forceinline__ void contract_fp32(const f2v *__restrict__ lds, const
 
 // Loads the wave's operands of pool entry w: pairs >= 1, entries past
 // `pairs` repeat the last one and are never used.
-__device__ __forceinline__ void load_a_3m(f4v (&a)[kPairsMax], const float4 *__restrict__ apool,
+// Operands of pool entry w for antenna half mt: 3 registers per pair, read
+// from the plan's component planes; entries past `pairs` repeat the last
+// one and are never used.
+__device__ __forceinline__ void load_a_3m(f3v (&a)[kPairsMax], const float *__restrict__ apool,
                                           int w, int a_w_stride, int pairs, int mt, int lane)
 {
-    const g_cf4v *ap = (const g_cf4v *)(apool + (size_t)w * a_w_stride + (size_t)mt * pairs * 64 + lane);
+    typedef __attribute__((address_space(1))) const float g_cf;
+    const g_cf *ap = (const g_cf *)(apool + (size_t)w * a_w_stride + (size_t)mt * pairs * 192 + lane);
 #pragma unroll
-    for (int p = 0; p < kPairsMax; ++p)
-        a[p] = ap[min(p, pairs - 1) * 64];
+    for (int p = 0; p < kPairsMax; ++p) {
+        const int q = min(p, pairs - 1);
+        a[p] = f3v{ap[(3 * q) * 64], ap[(3 * q + 1) * 64], ap[(3 * q + 2) * 64]};
+    }
 }
 
-__device__ __forceinline__ void mfma3(const f4v &a, const f2v &b, floatx16 &t1, floatx16 &t2,
+__device__ __forceinline__ void mfma3(const f3v &a, const f2v &b, floatx16 &t1, floatx16 &t2,
                                       floatx16 &t3)
 {
     t1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, t1, 0, 0, 0);
@@ -389,7 +462,7 @@ __device__ __forceinline__ void mfma3(const f4v &a, const f2v &b, floatx16 &t1, 
 // Contracts the staged S (LDS, pitch kLdsCols) and writes the wave's
 // quadrant of R, row-major 64 x 60, into `tile` (LDS).
 __device__ __forceinline__ void contract_stage_3m(const f2v *__restrict__ lds,
-                                                  const f4v (&a)[kPairsMax], int f, int wave,
+                                                  const f3v (&a)[kPairsMax], int f, int wave,
                                                   int lane, f2v *__restrict__ tile)
 {
     const int h = lane >> 5;
@@ -400,14 +473,73 @@ __device__ __forceinline__ void contract_stage_3m(const f2v *__restrict__ lds,
     floatx16 t1 = {}, t2 = {}, t3 = {};
     const f2v *col = lds + h * kLdsCols + 32 * nt + n;
     if (np == kPairsMax) {
+        // All B operands are read before the first product: each wait then
+        // covers only the oldest outstanding read, and the matrix core never
+        // idles on LDS latency inside the chain.
+        f2v b[kPairsMax];
 #pragma unroll
         for (int p = 0; p < kPairsMax; ++p)
-            mfma3(a[p], col[2 * p * kLdsCols], t1, t2, t3);
+            b[p] = col[2 * p * kLdsCols];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int p = 0; p < kPairsMax; ++p)
+            mfma3(a[p], b[p], t1, t2, t3);
     } else {
 #pragma unroll
         for (int p = 0; p < kPairsMax; ++p)
             if (p < np)
                 mfma3(a[p], col[2 * p * kLdsCols], t1, t2, t3);
+    }
+    const int j = 32 * nt + n;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = 32 * mt + 8 * (r >> 2) + 4 * h + (r & 3);
+        if (j < kB)
+            tile[i * kB + j] = f2v{t1[r] - t2[r], (t3[r] - t1[r]) - t2[r]};
+    }
+}
+
+// contract_stage_3m for the wave-specialised schedule, with the operands of
+// W staged in LDS by the producer waves (component planes, as in the plan:
+// [2 halves][pairs][3][64 lanes] floats).  The A and B values of each pair
+// are read ahead of its products in batches of 6 pairs: batch k is issued
+// once pair 6k - 4 is, so at most 10 pairs occupy registers and each wait
+// covers only the oldest reads.  Rows past f and pairs past the plan's hold
+// older data and feed no product.
+__device__ __forceinline__ void contract_stage_3m_lds(const f2v *__restrict__ lds,
+                                                      const float *__restrict__ lds_a, int pairs,
+                                                      int f, int wave, int lane,
+                                                      f2v *__restrict__ tile)
+{
+    const int h = lane >> 5;
+    const int n = lane & 31;
+    const int mt = wave >> 1;
+    const int nt = wave & 1;
+    const int np = (f + 1) >> 1;
+    constexpr int kBatch = 6, kLead = 4;
+    const f2v *col = lds + h * kLdsCols + 32 * nt + n;
+    const float *ab = lds_a + mt * pairs * 192 + lane;
+    floatx16 t1 = {}, t2 = {}, t3 = {};
+    f3v a[kPairsMax];
+    f2v b[kPairsMax];
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+        b[q] = col[2 * q * kLdsCols];
+        a[q] = f3v{ab[(3 * q) * 64], ab[(3 * q + 1) * 64], ab[(3 * q + 2) * 64]};
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int p = 0; p < kPairsMax; ++p) {
+        if (p + kLead < kPairsMax && (p + kLead) % kBatch == 0) {
+#pragma unroll
+            for (int q = p + kLead; q < p + kLead + kBatch; ++q) {
+                b[q] = col[2 * q * kLdsCols];
+                a[q] = f3v{ab[(3 * q) * 64], ab[(3 * q + 1) * 64], ab[(3 * q + 2) * 64]};
+            }
+        }
+        if (p < np)
+            mfma3(a[p], b[p], t1, t2, t3);
+        __builtin_amdgcn_sched_barrier(0);
     }
     const int j = 32 * nt + n;
 #pragma unroll
@@ -441,7 +573,7 @@ template <bool kVec16>
 __global__ __launch_bounds__(kThreads) void apply_fp32_3m_single(BfHeader *__restrict__ blk,
                                                                  const BfItem *__restrict__ items,
                                                                  int n_items,
-                                                                 const float4 *__restrict__ apool,
+                                                                 const float *__restrict__ apool,
                                                                  int a_w_stride, int pairs)
 {
     __shared__ f2v lds_s[kFMax * kLdsCols];
@@ -451,7 +583,7 @@ __global__ __launch_bounds__(kThreads) void apply_fp32_3m_single(BfHeader *__res
     float2 *sink = sink_of(blk);
     const int it = xcd_contiguous(blockIdx.x, n_items);
     const BfItem d = items[it];
-    f4v a[kPairsMax];
+    f3v a[kPairsMax];
     SRegs<kVec16> sr;
     load_s<kVec16>(sr, d.f > 0 ? d.S : sink, d.f);
     if (pairs > 0)
@@ -650,40 +782,79 @@ __global__ __launch_bounds__(kThreads) void apply_fp32_stream(BfHeader *__restri
 // kSched 3: wave-specialised persistent kernel (FP32 forms).  4 + kProd
 // waves per workgroup: waves 0-3 (one per SIMD) only run matrix-core steps
 // from LDS; the kProd producer waves only move data.  Per product t of the
-// workgroup's share (a contiguous run of its XCD group's range):
-//   consumers: contract S(t) from s_buf[t % 2], results -> r_buf[t % 2];
+// workgroup's share (every nb-th item of its XCD's range):
+//   consumers: contract S(t) from s_buf[t % 2] (three-product form: with the
+//              W operands from a_buf[t % 2]), results -> r_buf[t % 2];
 //   producers: write R(t-1) from r_buf[(t-1) % 2] with contiguous 16-byte
-//              stores; move S(t+1) from registers to s_buf[(t+1) % 2]; issue
-//              the loads of S(t+2) into registers;
+//              stores; move S(t+1) (and W(t+1)) from registers to LDS; issue
+//              the loads for product t+1+kDepth into the register set that
+//              product t+1 has just left;
 //   one barrier.
 // A buffer written in iteration t was last read in iteration t-1, before
 // that iteration's barrier; one written in t is read in t+1.  The two roles
 // run separate loops with the same number of barriers, so neither role's
-// memory waits hold up the other's instructions.
+// memory waits hold up the other's instructions.  kDepth register sets give
+// each load kDepth products' time to arrive.  The four-product form keeps W
+// in consumer registers and reloads them during each chain; the
+// three-product form's operands (3 per pair) would not fit beside its three
+// accumulators, so they come through LDS, copied once per workgroup instead
+// of once per wave.
 
-// Producer-side staging of S over kProd waves (16-byte chunks, clamped).
-template <int kProd>
+// Producer-side staging over kProd waves, in 16-byte chunks with clamped
+// indices: S of one product and, for the three-product form (kW), the
+// operands of its W (the plan's 2 x pairs x 3 x 64 floats, 96 pairs chunks).
+constexpr int kWChunksMax = kPairsMax * 96;
+constexpr int kWFloatsMax = kPairsMax * 384;
+
+template <int kProd, bool kW = false>
 struct PRegs {
     static constexpr int kN = (kFMax * kB / 2 + 64 * kProd - 1) / (64 * kProd);
+    static constexpr int kNW = kW ? (kWChunksMax + 64 * kProd - 1) / (64 * kProd) : 1;
     f4v v[kN];
+    f4v w[kNW];
 };
 
-template <int kProd>
-__device__ __forceinline__ void p_load_s(PRegs<kProd> &r, const float2 *__restrict__ S, int f, int ptid)
+template <int kProd, bool kW>
+__device__ __forceinline__ void p_load_s(PRegs<kProd, kW> &r, const float2 *__restrict__ S, int f, int ptid)
 {
     g_cf4v *src = (g_cf4v *)S;
     const int last = (f > 0 ? f * (kB / 2) : 1) - 1;
 #pragma unroll
-    for (int u = 0; u < PRegs<kProd>::kN; ++u)
+    for (int u = 0; u < PRegs<kProd, kW>::kN; ++u)
         r.v[u] = __builtin_nontemporal_load(src + min(ptid + u * 64 * kProd, last));
 }
 
+// W operands (L2-resident pool: plain loads, no streaming hint).
 template <int kProd>
-__device__ __forceinline__ void p_put_s(f2v *__restrict__ lds, const PRegs<kProd> &r, int f, int ptid)
+__device__ __forceinline__ void p_load_w(PRegs<kProd, true> &r, const float *__restrict__ wsrc, int pairs,
+                                         int ptid)
+{
+    g_cf4v *src = (g_cf4v *)wsrc;
+    const int last = pairs * 96 - 1;
+#pragma unroll
+    for (int u = 0; u < PRegs<kProd, true>::kNW; ++u)
+        r.w[u] = src[min(ptid + u * 64 * kProd, last)];
+}
+
+template <int kProd>
+__device__ __forceinline__ void p_put_w(float *__restrict__ lds_a, const PRegs<kProd, true> &r, int pairs,
+                                        int ptid)
+{
+    const int chunks = pairs * 96;
+#pragma unroll
+    for (int u = 0; u < PRegs<kProd, true>::kNW; ++u) {
+        const int c = ptid + u * 64 * kProd;
+        if (c < chunks)
+            reinterpret_cast<f4v *>(lds_a)[c] = r.w[u];
+    }
+}
+
+template <int kProd, bool kW>
+__device__ __forceinline__ void p_put_s(f2v *__restrict__ lds, const PRegs<kProd, kW> &r, int f, int ptid)
 {
     const int chunks = f * (kB / 2);
 #pragma unroll
-    for (int u = 0; u < PRegs<kProd>::kN; ++u) {
+    for (int u = 0; u < PRegs<kProd, kW>::kN; ++u) {
         const int c = ptid + u * 64 * kProd;
         if (c < chunks) {
             const int row = c / (kB / 2);
@@ -701,10 +872,13 @@ __device__ __forceinline__ void p_put_s(f2v *__restrict__ lds, const PRegs<kProd
 // kProd waves.  Chunk indices past the end are clamped: those threads write
 // the last chunk again with the same data, so every store is unconditional.
 template <int kProd>
+constexpr int kPStoreRounds = (kM * kB / 2 + 64 * kProd - 1) / (64 * kProd);
+
+template <int kProd>
 __device__ __forceinline__ void p_store_r(float2 *__restrict__ Rp, const f2v *__restrict__ tile, int ptid)
 {
     constexpr int kChunks = kM * kB / 2;
-    constexpr int kRounds = (kChunks + 64 * kProd - 1) / (64 * kProd);
+    constexpr int kRounds = kPStoreRounds<kProd>;
     g_f4v *dst = (g_f4v *)Rp;
     const f4v *src = reinterpret_cast<const f4v *>(tile);
 #pragma unroll
@@ -714,15 +888,66 @@ __device__ __forceinline__ void p_store_r(float2 *__restrict__ Rp, const f2v *__
     }
 }
 
-// S must be 16-byte aligned (the host routes other batches elsewhere).
-template <bool k3M, int kProd>
+// Everything the producers move for one product: its S and, for the
+// three-product form, its W operands.
+template <int kProd, bool k3M>
+__device__ __forceinline__ void p_load_item(PRegs<kProd, k3M> &r, const BfItem &d, bool real, float2 *sink,
+                                            const void *apool, int a_w_stride, int pairs, int ptid)
+{
+    p_load_s<kProd, k3M>(r, real && d.f > 0 ? d.S : sink, real ? d.f : 0, ptid);
+    if constexpr (k3M)
+        p_load_w<kProd>(r, static_cast<const float *>(apool) + (size_t)d.w_id * a_w_stride, pairs, ptid);
+}
+
+template <int kProd, bool k3M>
+__device__ __forceinline__ void p_put_item(f2v *__restrict__ s_lds, float *__restrict__ a_lds,
+                                           const PRegs<kProd, k3M> &r, int f, int pairs, int ptid)
+{
+    p_put_s<kProd, k3M>(s_lds, r, f, ptid);
+    if constexpr (k3M)
+        p_put_w<kProd>(a_lds, r, pairs, ptid);
+}
+
+// Staged W operands of the workgroup (three-product form only).
+template <bool k3M>
+struct WBuf {
+    float v[2][kWFloatsMax];
+};
+template <>
+struct WBuf<false> {
+    float v[2][1];
+};
+
+// One producer iteration for product t >= 1 of the share: R(t-1) out, the
+// data of product t+1 into LDS from register set kPut, the loads for product
+// t+1+kDepth into that set.  Past the end of the share the descriptor index
+// is clamped and the S loads read the sink, so every memory instruction is
+// unconditional; a put past the end fills LDS buffers nobody reads any more.
+template <int kProd, int kDepth, int kPut, bool k3M>
+__device__ __forceinline__ void ws_produce_step(PRegs<kProd, k3M> (&sr)[kDepth], c_item *my, int stride,
+                                                int t, int n_my, float2 *sink,
+                                                f2v (*s_buf)[kFMax * kLdsCols], WBuf<k3M> &a_buf,
+                                                const f2v (*r_buf)[kM * kB], const void *apool,
+                                                int a_w_stride, int pairs, int ptid)
+{
+    p_store_r<kProd>(item_at(my, t - 1, stride).R, r_buf[(t - 1) & 1], ptid);
+    const BfItem d1 = item_at(my, min(t + 1, n_my - 1), stride);
+    p_put_item<kProd, k3M>(s_buf[(t + 1) & 1], a_buf.v[(t + 1) & 1], sr[kPut], d1.f, pairs, ptid);
+    const int tn = t + 1 + kDepth;
+    const BfItem dn = item_at(my, min(tn, n_my - 1), stride);
+    p_load_item<kProd, k3M>(sr[kPut], dn, tn < n_my, sink, apool, a_w_stride, pairs, ptid);
+}
+
+// kSched 3: wave-specialised persistent kernel (FP32 forms).  S must be
+// 16-byte aligned (the host routes other batches elsewhere).
+template <bool k3M, int kProd, int kDepth>
 __global__ __launch_bounds__(64 * (kWaves + kProd)) void apply_fp32_ws(
     BfHeader *__restrict__ blk, const BfItem *__restrict__ items, int n_items,
     const void *__restrict__ apool, int a_w_stride, int pairs)
 {
     __shared__ f2v s_buf[2][kFMax * kLdsCols];
     __shared__ f2v r_buf[2][kM * kB];
-    __shared__ int meta[2][2];   // (W id, f) of the product staged in s_buf[i]
+    __shared__ WBuf<k3M> a_buf;
     const int wave8 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     float2 *sink = sink_of(blk);
@@ -735,76 +960,125 @@ __global__ __launch_bounds__(64 * (kWaves + kProd)) void apply_fp32_ws(
     const int q = n_items / X, r = n_items % X;
     const int lo = x * q + (x < r ? x : r);
     const int cnt = q + (x < r ? 1 : 0);
-    const int per = cnt / nb, extra = cnt % nb;
-    const int start = lo + j * per + (j < extra ? j : extra);
-    const int n_my = per + (j < extra ? 1 : 0);
+    // The nb workgroups of an XCD take its items round-robin (item lo + j +
+    // k nb is product k of workgroup j), so at any moment they work on one
+    // contiguous window of the item list: R is written as one advancing
+    // front per XCD, which keeps HBM pages open far better than nb separate
+    // fronts would.
+    const int start = lo + j;
+    const int stride = nb;
+    const int n_my = j < cnt ? (cnt - j + nb - 1) / nb : 0;
     if (n_my <= 0)
         return;
 
+    c_item *my = (c_item *)items + start;
     if (wave8 < kWaves) {
-        // consumer
+        // consumer.  f of product t is read at the end of product t - 1,
+        // where the barrier waits for it: a wait for a scalar read also waits
+        // for every LDS read, so it must not fall among the chain's.
         const int wave = wave8;
-        using AReg = typename std::conditional<k3M, f4v, f2v>::type;
-        AReg a[kPairsMax];
-        int cur_w = -1;
-        __syncthreads();
-        for (int t = 0; t < n_my; ++t) {
-            const int w_id = __builtin_amdgcn_readfirstlane(meta[t & 1][0]);
-            const int f = __builtin_amdgcn_readfirstlane(meta[t & 1][1]);
-            if (w_id != cur_w && pairs > 0) {
-                cur_w = w_id;
-                if constexpr (k3M)
-                    load_a_3m(a, static_cast<const float4 *>(apool), cur_w, a_w_stride, pairs,
-                              wave >> 1, lane);
-                else
-                    load_a_fp32(a, static_cast<const float2 *>(apool), cur_w, a_w_stride, pairs,
-                                wave, lane);
-            }
-            if constexpr (k3M) {
-                contract_stage_3m(s_buf[t & 1], a, f, wave, lane, r_buf[t & 1]);
-            } else {
-                floatx16 acc0, acc1;
-                contract_fp32(s_buf[t & 1], a, f, lane, acc0, acc1);
-                stage_acc(r_buf[t & 1] + wave * kWaveOut, lane, acc0, acc1);
-            }
+        int f = item_at(my, 0, stride).f;
+        if constexpr (k3M) {
             __syncthreads();
+            for (int t = 0; t < n_my; ++t) {
+                contract_stage_3m_lds(s_buf[t & 1], a_buf.v[t & 1], pairs, f, wave, lane, r_buf[t & 1]);
+                __builtin_amdgcn_sched_barrier(0);
+                f = item_at(my, min(t + 1, n_my - 1), stride).f;
+                __syncthreads();
+            }
+        } else {
+            // W of product t is in registers when t starts; the chain of t
+            // reloads them with W of t + 1 (the last product reloads its own).
+            f2v a[kPairsMax];
+            load_a_fp32(a, static_cast<const float2 *>(apool), item_at(my, 0, stride).w_id, a_w_stride,
+                        pairs, wave, lane);
+            int w_next = item_at(my, min(1, n_my - 1), stride).w_id;
+            __syncthreads();
+            for (int t = 0; t < n_my; ++t) {
+                floatx16 acc0, acc1;
+                contract_fp32_reload(s_buf[t & 1], a, f, lane, acc0, acc1,
+                                     static_cast<const float2 *>(apool), w_next, a_w_stride, pairs, wave);
+                stage_acc(r_buf[t & 1] + wave * kWaveOut, lane, acc0, acc1);
+                __builtin_amdgcn_sched_barrier(0);
+                f = item_at(my, min(t + 1, n_my - 1), stride).f;
+                w_next = item_at(my, min(t + 2, n_my - 1), stride).w_id;
+                __syncthreads();
+            }
         }
     } else {
-        // producer
+        // producer: product 0 straight to LDS; products u = 1..kDepth into
+        // register set u % kDepth
         const int ptid = threadIdx.x - 64 * kWaves;
-        PRegs<kProd> sr;
+        PRegs<kProd, k3M> sr[kDepth];
         {
-            const BfItem d0 = items[start];
-            p_load_s<kProd>(sr, d0.f > 0 ? d0.S : sink, d0.f, ptid);
-            p_put_s<kProd>(s_buf[0], sr, d0.f, ptid);
-            if (ptid == 0) {
-                meta[0][0] = d0.w_id;
-                meta[0][1] = d0.f;
-            }
+            const BfItem d0 = item_at(my, 0, stride);
+            p_load_item<kProd, k3M>(sr[0], d0, true, sink, apool, a_w_stride, pairs, ptid);
+            p_put_item<kProd, k3M>(s_buf[0], a_buf.v[0], sr[0], d0.f, pairs, ptid);
         }
-        if (n_my > 1) {
-            const BfItem d1 = items[start + 1];
-            p_load_s<kProd>(sr, d1.f > 0 ? d1.S : sink, d1.f, ptid);
+        // Each load group is preceded by as many sink stores as an iteration
+        // issues R stores, and so is product 0, which has no R to write: the
+        // outstanding memory operations at the loop's entry then follow the
+        // same pattern as at its back edge, and the compiler's wait before
+        // each put counts only the loads that put needs.
+        const int plane = ptid & 63;
+#pragma unroll
+        for (int u = 1; u <= kDepth; ++u) {
+            prime_store_count<kPStoreRounds<kProd>>(sink, plane);
+            const BfItem d = item_at(my, min(u, n_my - 1), stride);
+            p_load_item<kProd, k3M>(sr[u % kDepth], d, u < n_my, sink, apool, a_w_stride, pairs, ptid);
         }
         __syncthreads();
-        for (int t = 0; t < n_my; ++t) {
-            if (t >= 1)
-                p_store_r<kProd>(items[start + t - 1].R, r_buf[(t - 1) & 1], ptid);
-            if (t + 1 < n_my) {
-                const BfItem d1 = items[start + t + 1];
-                p_put_s<kProd>(s_buf[(t + 1) & 1], sr, d1.f, ptid);
-                if (ptid == 0) {
-                    meta[(t + 1) & 1][0] = d1.w_id;
-                    meta[(t + 1) & 1][1] = d1.f;
-                }
-            }
-            if (t + 2 < n_my) {
-                const BfItem dn = items[start + t + 2];
-                p_load_s<kProd>(sr, dn.f > 0 ? dn.S : sink, dn.f, ptid);
-            }
+        // product 0
+        {
+            prime_store_count<kPStoreRounds<kProd>>(sink, plane);
+            const BfItem d1 = item_at(my, min(1, n_my - 1), stride);
+            p_put_item<kProd, k3M>(s_buf[1], a_buf.v[1], sr[1 % kDepth], d1.f, pairs, ptid);
+            const int tn = 1 + kDepth;
+            const BfItem dn = item_at(my, min(tn, n_my - 1), stride);
+            p_load_item<kProd, k3M>(sr[1 % kDepth], dn, tn < n_my, sink, apool, a_w_stride, pairs, ptid);
             __syncthreads();
         }
-        p_store_r<kProd>(items[start + n_my - 1].R, r_buf[(n_my - 1) & 1], ptid);
+        // Products 1.. in groups of kDepth, so that every register set index
+        // is a constant: product t puts product t+1 from set (t+1) % kDepth.
+        // The loop has a single exit at its end (a break in the middle becomes
+        // a flow block inside the loop, whose pessimistic memory-count state
+        // would then reach the loop's first put); the remaining products
+        // follow it.
+        static_assert(kDepth >= 1 && kDepth <= 3, "prefetch depth");
+        const int groups = (n_my - 1) / kDepth;
+        const int rest = (n_my - 1) - groups * kDepth;
+        int t = 1;
+        for (int g = 0; g < groups; ++g) {
+            ws_produce_step<kProd, kDepth, 2 % kDepth, k3M>(sr, my, stride, t, n_my, sink, s_buf, a_buf,
+                                                            r_buf, apool, a_w_stride, pairs, ptid);
+            __syncthreads();
+            if constexpr (kDepth >= 2) {
+                ws_produce_step<kProd, kDepth, 3 % kDepth, k3M>(sr, my, stride, t + 1, n_my, sink, s_buf,
+                                                                a_buf, r_buf, apool, a_w_stride, pairs, ptid);
+                __syncthreads();
+            }
+            if constexpr (kDepth >= 3) {
+                ws_produce_step<kProd, kDepth, 4 % kDepth, k3M>(sr, my, stride, t + 2, n_my, sink, s_buf,
+                                                                a_buf, r_buf, apool, a_w_stride, pairs, ptid);
+                __syncthreads();
+            }
+            t += kDepth;
+        }
+        if constexpr (kDepth >= 2) {
+            if (rest >= 1) {
+                ws_produce_step<kProd, kDepth, 2 % kDepth, k3M>(sr, my, stride, t, n_my, sink, s_buf, a_buf,
+                                                                r_buf, apool, a_w_stride, pairs, ptid);
+                __syncthreads();
+            }
+        }
+        if constexpr (kDepth >= 3) {
+            if (rest >= 2) {
+                ws_produce_step<kProd, kDepth, 3 % kDepth, k3M>(sr, my, stride, t + 1, n_my, sink, s_buf,
+                                                                a_buf, r_buf, apool, a_w_stride, pairs, ptid);
+                __syncthreads();
+            }
+        }
+        p_store_r<kProd>(item_at(my, n_my - 1, stride).R, r_buf[(n_my - 1) & 1], ptid);
     }
 }
 
@@ -1229,6 +1503,34 @@ static const BfItem *items_of(BfHeader *blk)
                                             sizeof(BfHeader) + kSinkBytes);
 }
 
+// Schedule 3 launch: producer waves and S prefetch depth from the variant.
+template <bool k3M>
+static hipError_t launch_ws(const LaunchCfg &cfg, BfHeader *blk, int n_items, const void *apool,
+                            int a_stride, int pairs, hipStream_t st)
+{
+    const BfItem *items = items_of(blk);
+    const dim3 grid(cfg.grid);
+    if (cfg.producers == 4)
+        hipLaunchKernelGGL((apply_fp32_ws<k3M, 4, 1>), grid, dim3(64 * 8), 0, st, blk, items,
+                           n_items, apool, a_stride, pairs);
+    else if (cfg.producers == 12 && cfg.depth == 2)
+        hipLaunchKernelGGL((apply_fp32_ws<k3M, 12, 2>), grid, dim3(64 * 16), 0, st, blk, items,
+                           n_items, apool, a_stride, pairs);
+    else if (cfg.producers == 12)
+        hipLaunchKernelGGL((apply_fp32_ws<k3M, 12, 1>), grid, dim3(64 * 16), 0, st, blk, items,
+                           n_items, apool, a_stride, pairs);
+    else if (cfg.depth == 3)
+        hipLaunchKernelGGL((apply_fp32_ws<k3M, 8, 3>), grid, dim3(64 * 12), 0, st, blk, items,
+                           n_items, apool, a_stride, pairs);
+    else if (cfg.depth == 2)
+        hipLaunchKernelGGL((apply_fp32_ws<k3M, 8, 2>), grid, dim3(64 * 12), 0, st, blk, items,
+                           n_items, apool, a_stride, pairs);
+    else
+        hipLaunchKernelGGL((apply_fp32_ws<k3M, 8, 1>), grid, dim3(64 * 12), 0, st, blk, items,
+                           n_items, apool, a_stride, pairs);
+    return hipGetLastError();
+}
+
 template <bool kVec16, bool kStage>
 static hipError_t launch_fp32_t(const LaunchCfg &cfg, BfHeader *blk, int n_items,
                                 const PlanDev &pd, hipStream_t st)
@@ -1244,15 +1546,7 @@ static hipError_t launch_fp32_t(const LaunchCfg &cfg, BfHeader *blk, int n_items
                            items, n_items, pd.a_fp32, pd.a_fp32_stride, pd.pairs);
         break;
     case 3:
-        if (cfg.producers == 8)
-            hipLaunchKernelGGL((apply_fp32_ws<false, 8>), dim3(cfg.grid), dim3(64 * 12), 0,
-                               st, blk, items, n_items, (const void *)pd.a_fp32, pd.a_fp32_stride,
-                               pd.pairs);
-        else
-            hipLaunchKernelGGL((apply_fp32_ws<false, 4>), dim3(cfg.grid), dim3(64 * 8), 0,
-                               st, blk, items, n_items, (const void *)pd.a_fp32, pd.a_fp32_stride,
-                               pd.pairs);
-        break;
+        return launch_ws<false>(cfg, blk, n_items, (const void *)pd.a_fp32, pd.a_fp32_stride, pd.pairs, st);
     default:
         hipLaunchKernelGGL((apply_fp32_stream<kVec16, kStage>), dim3(cfg.grid), dim3(kThreads), 0,
                            st, blk, items, n_items, pd.a_fp32, pd.a_fp32_stride, pd.pairs);
@@ -1269,12 +1563,8 @@ static hipError_t launch_3m_t(const LaunchCfg &cfg, BfHeader *blk, int n_items, 
     if (cfg.schedule == 0)
         hipLaunchKernelGGL(apply_fp32_3m_single<kVec16>, dim3(n_items), dim3(kThreads), 0, st, blk,
                            items, n_items, pd.a_3m, pd.a_3m_stride, pd.pairs);
-    else if (cfg.producers == 8)
-        hipLaunchKernelGGL((apply_fp32_ws<true, 8>), dim3(cfg.grid), dim3(64 * 12), 0, st,
-                           blk, items, n_items, (const void *)pd.a_3m, pd.a_3m_stride, pd.pairs);
     else
-        hipLaunchKernelGGL((apply_fp32_ws<true, 4>), dim3(cfg.grid), dim3(64 * 8), 0, st,
-                           blk, items, n_items, (const void *)pd.a_3m, pd.a_3m_stride, pd.pairs);
+        return launch_ws<true>(cfg, blk, n_items, (const void *)pd.a_3m, pd.a_3m_stride, pd.pairs, st);
     return hipGetLastError();
 }
 
@@ -1350,7 +1640,7 @@ static int occ_fp32(int schedule, bool vec16)
     switch (schedule) {
     case 0: return vec16 ? occ_of(apply_fp32_single<true, kStage>) : occ_of(apply_fp32_single<false, kStage>);
     case 1: return vec16 ? occ_of(apply_fp32_claim<true>) : occ_of(apply_fp32_claim<false>);
-    case 3: return occ_of(apply_fp32_ws<false, 4>, 512);
+    case 3: return occ_of(apply_fp32_ws<false, 4, 1>, 512);
     default: return vec16 ? occ_of(apply_fp32_stream<true, kStage>) : occ_of(apply_fp32_stream<false, kStage>);
     }
 }
@@ -1362,7 +1652,7 @@ static int occ_any(int prec, int schedule, bool vec16)
     case BF_FP32_3M:
         if (schedule == 0)
             return vec16 ? occ_of(apply_fp32_3m_single<true>) : occ_of(apply_fp32_3m_single<false>);
-        return occ_of(apply_fp32_ws<true, 4>, 512);
+        return occ_of(apply_fp32_ws<true, 4, 1>, 512);
     case BF_FP16: return occ_lp<false, false, kStage>(schedule, vec16);
     case BF_BF16: return occ_lp<true, false, kStage>(schedule, vec16);
     case BF_FP16X2: return occ_lp<false, true, kStage>(schedule, vec16);

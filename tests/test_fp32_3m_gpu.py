@@ -8,7 +8,7 @@ is bitwise.
 import numpy as np
 import pytest
 
-from gpu_util import FP32_TOL, announce, rel_errors, run_batch
+from gpu_util import FP32_TOL, announce, rel_errors, require_gpu, run_batch
 from oracle import oracle as orc
 from paper_1810_11451_amd import bf
 from paper_1810_11451_amd import workloads as wl
@@ -16,7 +16,9 @@ from paper_1810_11451_amd import workloads as wl
 pytestmark = pytest.mark.gpu
 P = bf.BF_FP32_3M
 VARIANTS = {"one-per-wg": (0, 0, 0), "ws-sorted": (3, 0, 1), "ws-asgiven": (3, 0, 0),
-            "mapped-from-stream": (2, 2, 1), "ws-8-producers": (3, 0, 1, 1)}
+            "mapped-from-stream": (2, 2, 1), "ws-8-producers": (3, 0, 1, 1),
+            "ws-8-producers-depth-2": (3, 0, 1, 2), "ws-8-producers-depth-3": (3, 0, 1, 3),
+            "ws-12-producers-asgiven": (3, 0, 0, 4), "ws-12-producers-depth-2": (3, 0, 1, 5)}
 
 
 @pytest.mark.parametrize("vname", sorted(VARIANTS))
@@ -84,3 +86,23 @@ def test_uneven_workload_all_items():
     R = run_batch(b, prec=P)
     err, _ = rel_errors(b, R)
     assert np.max(err) <= FP32_TOL
+
+
+@pytest.mark.parametrize("vname", ["ws-sorted", "ws-8-producers", "ws-8-producers-depth-2",
+                                   "ws-8-producers-depth-3", "ws-12-producers-asgiven",
+                                   "ws-12-producers-depth-2"])
+@pytest.mark.parametrize("per_wg", [5, 6, 7])
+def test_ws_long_shares(vname, per_wg):
+    """5-8 products per persistent workgroup: the producers' prefetch ring
+    wraps and every remainder of its unrolled loop occurs."""
+    require_gpu()
+    n_cu = bf.bf_device_cu_count()
+    n = n_cu * per_wg + (37 * per_wg) % n_cu
+    rng = np.random.default_rng(820 + per_wg)
+    b = wl.random_batch(rng, n, 9, f_values=np.arange(0, 37))
+    announce(f"3m ws long shares variant={vname} n={n}")
+    R = run_batch(b, prec=P, variant=VARIANTS[vname])
+    err, _ = rel_errors(b, R)
+    nz = b.f > 0
+    assert np.max(err[nz]) <= FP32_TOL, f"max rel err {np.max(err[nz]):.3g}"
+    assert np.all(R[~nz] == 0)

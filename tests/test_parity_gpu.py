@@ -32,7 +32,13 @@ VARIANTS = {
     "ws-asgiven": (3, 0, 0),
     "ws-2-per-cu": (3, 2, 1),
     "ws-8-producers": (3, 0, 1, 1),
+    "ws-8-producers-depth-2": (3, 0, 1, 2),
+    "ws-8-producers-depth-3": (3, 0, 1, 3),
+    "ws-12-producers-asgiven": (3, 0, 0, 4),
+    "ws-12-producers-depth-2": (3, 0, 1, 5),
 }
+WS_VARIANTS = ["ws-sorted", "ws-8-producers", "ws-8-producers-depth-2", "ws-8-producers-depth-3",
+               "ws-12-producers-asgiven", "ws-12-producers-depth-2"]
 
 
 @pytest.mark.parametrize("vname", sorted(VARIANTS))
@@ -240,3 +246,22 @@ def test_uneven_workload_all_items():
     R = run_batch(b)
     err, _ = rel_errors(b, R)
     assert np.max(err) <= FP32_TOL, f"max rel err {np.max(err):.3g}"
+
+
+@pytest.mark.parametrize("vname", WS_VARIANTS)
+@pytest.mark.parametrize("per_wg", [5, 6, 7])
+def test_ws_long_shares(vname, per_wg):
+    """Persistent wave-specialised schedule with 5-8 products per workgroup
+    (one workgroup per CU), so that the producers' prefetch ring wraps and
+    every remainder of its unrolled loop occurs; ragged f in random order."""
+    torch = require_gpu()
+    n_cu = bf.bf_device_cu_count()
+    n = n_cu * per_wg + (37 * per_wg) % n_cu
+    rng = np.random.default_rng(120 + per_wg)
+    b = wl.random_batch(rng, n, 9, f_values=np.arange(0, 37))
+    announce(f"ws long shares variant={vname} n={n}")
+    R = run_batch(b, variant=VARIANTS[vname])
+    err, _ = rel_errors(b, R)
+    nz = b.f > 0
+    assert np.max(err[nz]) <= FP32_TOL, f"max rel err {np.max(err[nz]):.3g}"
+    assert np.all(R[~nz] == 0)
