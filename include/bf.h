@@ -99,6 +99,32 @@ bf_status bf_plan_destroy(bf_plan plan);
 /* Plan facts: number of entries, f_max, prepared precision mask. */
 bf_status bf_plan_info(bf_plan plan, int32_t *n_w, int32_t *f_max, uint32_t *prec_mask);
 
+/* Replaces pool entry w_id.  Section III has W constant while S changes;
+ * in a running base station it stays constant only until the precoder is
+ * recomputed, and this swaps one entry without re-planning.
+ *   w          host complex64 [64][f_max], row-major; may be freed on return
+ *   hip_stream the caller's stream, which is made to wait for the update
+ * Every entry has two device slots in each prepared layout.  The new W is
+ * written into the slot not in use, on a stream of the plan's own, and
+ * becomes current when the call returns.  Then:
+ *   - bf_apply / bf_apply_packed calls and server launches issued after
+ *     this call read the new W; they wait on the device (on whatever
+ *     stream they run) for the update to finish.
+ *   - launches issued before it read the old W and are neither waited for
+ *     nor disturbed.
+ *   - the next update of the same entry rewrites the old slot only after
+ *     every launch issued before this call has finished (device-side wait
+ *     on the plan's stream; the host does not block).
+ * Graphs keep the slots current at bf_graph_create: re-create a graph after
+ * updating an entry it uses, and do not keep launching a graph created
+ * before an update once the same entry is updated again.
+ * Updates of one plan run one after another; the call blocks only while a
+ * previous update's W is still being uploaded.
+ * Errors: BF_ERR_INVALID (null plan or w, w_id outside [0, n_w)), BF_ERR_OOM,
+ * BF_ERR_DEVICE.  With f_max = 0 there is nothing to replace and the call
+ * only checks its arguments. */
+bf_status bf_plan_update(bf_plan plan, int32_t w_id, const void *w, void *hip_stream);
+
 /* ---- apply: one batch of products ------------------------------------
  * For t in [0, batch): R[t] = W_pool[w_ids[t]][:, :f[t]] x S[t].
  *   w_ids, f  host int32 [batch]

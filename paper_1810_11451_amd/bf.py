@@ -78,6 +78,7 @@ _SIGS = {
     "bf_plan_create": (_i32, [ctypes.POINTER(_vp), _vp, _i32, _i32, _u32, _vp]),
     "bf_plan_destroy": (_i32, [_vp]),
     "bf_plan_info": (_i32, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_u32)]),
+    "bf_plan_update": (_i32, [_vp, _i32, _vp, _vp]),
     "bf_apply": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _i32, _vp]),
     "bf_apply_packed": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _i32, _vp]),
     "bf_check_batch": (_i32, [_i32, _i32, _i32, _vp, _vp, _vp, _vp]),
@@ -237,6 +238,15 @@ def bf_plan_info(plan: Plan):
     _check(lib().bf_plan_info(plan.handle, ctypes.byref(n_w), ctypes.byref(f_max),
                               ctypes.byref(mask)), "bf_plan_info")
     return n_w.value, f_max.value, mask.value
+
+
+def bf_plan_update(plan: Plan, w_id: int, w: np.ndarray, stream=None) -> None:
+    """Replace pool entry w_id with w (complex64 [64, f_max]); see bf.h."""
+    w = np.ascontiguousarray(w, dtype=np.complex64)
+    if w.shape != (BF_M, plan.f_max):
+        raise ValueError(f"w must be [64, {plan.f_max}], got {w.shape}")
+    _check(lib().bf_plan_update(plan.handle, int(w_id), w.ctypes.data, _stream(stream)),
+           "bf_plan_update")
 
 
 def bf_apply(plan: Plan, w_ids, f, S_ptrs, R_ptrs, prec: int = BF_FP32, stream=None) -> None:

@@ -85,9 +85,9 @@ static void release_slot(StagingSlot &s)
     s = StagingSlot{};
 }
 
-// Defaults measured on MI355X (see the tuning notes in the design
-// document): full-width batches (mean f 36) run persistent workgroups,
-// batches of mixed or small f one product per workgroup in the order given.
+// Defaults measured on MI355X: full-width batches (mean f 36) run persistent
+// workgroups (FP32 forms wave-specialised), batches of mixed or small f one
+// product per workgroup, all in the order given.
 static bf_status default_variants(bf_plan p)
 {
     for (int pr = 0; pr < kPrecCount; ++pr)
@@ -134,6 +134,8 @@ extern "C" bf_status bf_plan_create(bf_plan *out, const void *w_pool, int32_t n_
     p->f_max = f_max;
     p->mask = prec_mask;
     p->pairs = (f_max + 1) / 2;
+    p->half.assign((size_t)n_w, 0);
+    p->guard.assign((size_t)n_w, nullptr);
     default_variants(p);
 
     auto fail_dev = [&](const char *what, hipError_t e) {
@@ -168,7 +170,7 @@ extern "C" bf_status bf_plan_create(bf_plan *out, const void *w_pool, int32_t n_
     }
     if (prec_mask & BF_PREC_BIT(BF_FP32)) {
         p->a_fp32_stride = bfk::fp32_w_stride(p->pairs);
-        const size_t bytes = std::max<size_t>(1, (size_t)n_w * p->a_fp32_stride * sizeof(float2));
+        const size_t bytes = std::max<size_t>(1, 2 * (size_t)n_w * p->a_fp32_stride * sizeof(float2));
         e = hipMalloc(&p->a_fp32, bytes);
         if (e == hipSuccess && p->pairs > 0)
             e = bfk::launch_w_transform_fp32(w_dev, n_w, f_max, p->a_fp32, p->pairs, st);
@@ -180,7 +182,7 @@ extern "C" bf_status bf_plan_create(bf_plan *out, const void *w_pool, int32_t n_
     }
     if (prec_mask & BF_PREC_BIT(BF_FP32_3M)) {
         p->a_3m_stride = bfk::fp32_3m_w_stride(p->pairs);
-        const size_t bytes = std::max<size_t>(16, (size_t)n_w * p->a_3m_stride * sizeof(float));
+        const size_t bytes = std::max<size_t>(16, 2 * (size_t)n_w * p->a_3m_stride * sizeof(float));
         e = hipMalloc(&p->a_3m, bytes);
         if (e == hipSuccess && p->pairs > 0)
             e = bfk::launch_w_transform_3m(w_dev, n_w, f_max, p->a_3m, p->pairs, st);
@@ -198,12 +200,12 @@ extern "C" bf_status bf_plan_create(bf_plan *out, const void *w_pool, int32_t n_
         if (!want)
             continue;
         const bool want_lo = prec_mask & BF_PREC_BIT(split);
-        const size_t bytes = std::max<size_t>(16, (size_t)n_w * p->lp_stride * 16);
+        const size_t bytes = std::max<size_t>(16, 2 * (size_t)n_w * p->lp_stride * 16);
         e = hipMalloc(&p->lp_hi[ty], bytes);
         if (e == hipSuccess && want_lo)
             e = hipMalloc(&p->lp_lo[ty], bytes);
         if (e == hipSuccess)
-            e = hipMalloc(&p->lp_exp[ty], sizeof(int) * (size_t)n_w);
+            e = hipMalloc(&p->lp_exp[ty], sizeof(int) * 2 * (size_t)n_w);
         if (e == hipSuccess && w_dev)
             e = bfk::launch_w_transform_lp(w_dev, n_w, f_max, ty == 1, p->lp_hi[ty], p->lp_lo[ty],
                                            p->lp_exp[ty], st);
@@ -243,6 +245,25 @@ extern "C" bf_status bf_plan_destroy(bf_plan p)
         if (p->lp_exp[ty])
             (void)hipFree(p->lp_exp[ty]);
     }
+    if (p->update_stream) {
+        (void)hipStreamSynchronize(p->update_stream);
+        (void)hipStreamDestroy(p->update_stream);
+    }
+    if (p->marker_stream) {
+        (void)hipStreamSynchronize(p->marker_stream);
+        (void)hipStreamDestroy(p->marker_stream);
+    }
+    for (hipEvent_t g : p->guard)
+        if (g)
+            (void)hipEventDestroy(g);
+    if (p->updated)
+        (void)hipEventDestroy(p->updated);
+    if (p->stage_free)
+        (void)hipEventDestroy(p->stage_free);
+    if (p->w_stage)
+        (void)hipFree(p->w_stage);
+    if (p->w_pinned)
+        (void)hipHostFree(p->w_pinned);
     if (p->copy_stream)
         (void)hipStreamDestroy(p->copy_stream);
     delete p;
@@ -259,6 +280,99 @@ extern "C" bf_status bf_plan_info(bf_plan p, int32_t *n_w, int32_t *f_max, uint3
         *f_max = p->f_max;
     if (mask)
         *mask = p->mask;
+    return BF_OK;
+}
+
+extern "C" bf_status bf_plan_update(bf_plan p, int32_t w_id, const void *w, void *hip_stream)
+{
+    if (!p)
+        return bf_fail(BF_ERR_INVALID, "plan is null");
+    if (!w)
+        return bf_fail(BF_ERR_INVALID, "w is null");
+    if (w_id < 0 || w_id >= p->n_w)
+        return bf_fail(BF_ERR_INVALID, "w_id %d outside [0, %d)", w_id, p->n_w);
+    if (p->f_max == 0)
+        return BF_OK;   // no flows: every product is the empty sum, W is never read
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    std::lock_guard<std::mutex> lk(p->mu);
+    const size_t w_bytes = (size_t)BF_M * p->f_max * sizeof(float2);
+    auto dev_fail = [&](const char *what, hipError_t e) {
+        return bf_fail(e == hipErrorOutOfMemory ? BF_ERR_OOM : BF_ERR_DEVICE, "%s: %s", what,
+                       hipGetErrorString(e));
+    };
+    hipError_t e = hipSuccess;
+    if (!p->update_stream) {
+        e = hipStreamCreateWithFlags(&p->update_stream, hipStreamNonBlocking);
+        if (e == hipSuccess)
+            e = hipStreamCreateWithFlags(&p->marker_stream, hipStreamNonBlocking);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&p->updated, hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&p->stage_free, hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipHostMalloc(&p->w_pinned, w_bytes, hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipMalloc(&p->w_stage, w_bytes);
+        if (e == hipSuccess)
+            e = hipEventRecord(p->stage_free, p->update_stream);
+        if (e != hipSuccess)
+            return dev_fail("update resources", e);
+    }
+    // The pinned buffer is free once the previous update's upload is done.
+    e = hipEventSynchronize(p->stage_free);
+    if (e != hipSuccess)
+        return dev_fail("hipEventSynchronize(update staging)", e);
+    std::memcpy(p->w_pinned, w, w_bytes);
+
+    const int next = 1 - (int)p->half[(size_t)w_id];
+    const size_t slot = (size_t)w_id + (size_t)p->n_w * next;
+    // The slot being written was current before this entry's previous update:
+    // launches issued before that update may still read it.
+    if (p->guard[(size_t)w_id])
+        e = hipStreamWaitEvent(p->update_stream, p->guard[(size_t)w_id], 0);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->w_stage, p->w_pinned, w_bytes, hipMemcpyHostToDevice, p->update_stream);
+    if (e == hipSuccess)
+        e = hipEventRecord(p->stage_free, p->update_stream);
+    if (e == hipSuccess && p->a_fp32)
+        e = bfk::launch_w_transform_fp32(p->w_stage, 1, p->f_max, p->a_fp32 + slot * p->a_fp32_stride,
+                                         p->pairs, p->update_stream);
+    if (e == hipSuccess && p->a_3m)
+        e = bfk::launch_w_transform_3m(p->w_stage, 1, p->f_max, p->a_3m + slot * p->a_3m_stride,
+                                       p->pairs, p->update_stream);
+    for (int ty = 0; ty < 2 && e == hipSuccess; ++ty) {
+        if (!p->lp_hi[ty])
+            continue;
+        const size_t off = slot * p->lp_stride * 16;
+        void *lo = p->lp_lo[ty] ? static_cast<char *>(p->lp_lo[ty]) + off : nullptr;
+        e = bfk::launch_w_transform_lp(p->w_stage, 1, p->f_max, ty == 1,
+                                       static_cast<char *>(p->lp_hi[ty]) + off, lo,
+                                       p->lp_exp[ty] + slot, p->update_stream);
+    }
+    if (e == hipSuccess)
+        e = hipEventRecord(p->updated, p->update_stream);
+    if (e == hipSuccess)
+        e = hipStreamWaitEvent(st, p->updated, 0);
+    if (e != hipSuccess)
+        return dev_fail("pool update", e);
+
+    // Guard for this entry's next update: every launch issued so far.  A
+    // staging slot is reused only after its previous launch finished, so the
+    // launches not yet known to be done are the latest one of each slot.
+    if (!p->guard[(size_t)w_id]) {
+        e = hipEventCreateWithFlags(&p->guard[(size_t)w_id], hipEventDisableTiming);
+        if (e != hipSuccess)
+            return dev_fail("hipEventCreate(guard)", e);
+    }
+    for (const StagingSlot &s : p->ring)
+        if (s.launched && e == hipSuccess)
+            e = hipStreamWaitEvent(p->marker_stream, s.ev, 0);
+    if (e == hipSuccess)
+        e = hipEventRecord(p->guard[(size_t)w_id], p->marker_stream);
+    if (e != hipSuccess)
+        return dev_fail("update guard", e);
+    p->half[(size_t)w_id] = (uint8_t)next;
+    p->any_update = true;
     return BF_OK;
 }
 
@@ -340,6 +454,8 @@ bfk::LaunchCfg choose_launch(bf_plan p, bf_prec prec, int n, int max_f, bool vec
     return cfg;
 }
 
+// Makes a staging slot ready for a block of `bytes`: waits for the launch
+// that last read it, then grows it if needed.
 static bf_status ensure_slot(StagingSlot &s, size_t bytes)
 {
     if (s.ev) {
@@ -390,6 +506,16 @@ bf_status reserve_staging(bf_plan p, int n)
     return BF_OK;
 }
 
+// Descriptors name pool entries by W id until they are ordered; the kernels
+// read the entry's current slot.  Caller holds p->mu.
+static void map_slots(bf_plan p, BfItem *items, int n)
+{
+    if (!p->any_update)
+        return;
+    for (int t = 0; t < n; ++t)
+        items[t].w_id += p->n_w * (int)p->half[(size_t)items[t].w_id];
+}
+
 // Common tail of bf_apply / bf_apply_packed / the serving batcher: items
 // are already validated and written by `fill` into host memory.
 bf_status enqueue_items(bf_plan p, bf_prec prec, int n, const FillFn &fill, hipStream_t st,
@@ -424,6 +550,7 @@ bf_status enqueue_items(bf_plan p, bf_prec prec, int n, const FillFn &fill, hipS
     bfk::LaunchCfg cfg = choose_launch(p, prec, n, max_f, vec16, &chosen);
     if (grid_out)
         *grid_out = cfg.grid;
+    map_slots(p, items, n);
 
     // The slot's previous launch has finished (ensure_slot waited for it), so
     // the upload may run on the copy stream while the caller's stream is
@@ -437,12 +564,18 @@ bf_status enqueue_items(bf_plan p, bf_prec prec, int n, const FillFn &fill, hipS
         e = hipStreamWaitEvent(st, slot.copied, 0);
     if (e != hipSuccess)
         return bf_fail(BF_ERR_DEVICE, "descriptor upload ordering: %s", hipGetErrorString(e));
+    if (p->any_update) {   // the W of updated entries must be in place
+        e = hipStreamWaitEvent(st, p->updated, 0);
+        if (e != hipSuccess)
+            return bf_fail(BF_ERR_DEVICE, "update ordering: %s", hipGetErrorString(e));
+    }
     e = launch_for_plan(p, cfg, static_cast<BfHeader *>(slot.dev), n, st);
     if (e != hipSuccess)
         return bf_fail(BF_ERR_DEVICE, "kernel launch: %s", hipGetErrorString(e));
     e = hipEventRecord(slot.ev, st);
     if (e != hipSuccess)
         return bf_fail(BF_ERR_DEVICE, "hipEventRecord: %s", hipGetErrorString(e));
+    slot.launched = true;
     return BF_OK;
 }
 
@@ -596,6 +729,15 @@ extern "C" bf_status bf_graph_create(bf_graph *out, bf_plan p, int32_t batch, co
     else
         items = raw;
     bfk::LaunchCfg cfg = choose_launch(p, prec, batch, max_f, vec16, &v);
+
+    bool after_update = false;
+    {
+        std::lock_guard<std::mutex> lk(p->mu);
+        map_slots(p, items.data(), batch);
+        after_update = p->any_update;
+    }
+    if (after_update && hipStreamWaitEvent(st, p->updated, 0) != hipSuccess)
+        return bf_fail(BF_ERR_DEVICE, "update ordering");
 
     bf_graph g = new (std::nothrow) bf_graph_s();
     if (!g)

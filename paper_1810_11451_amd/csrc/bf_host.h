@@ -26,6 +26,7 @@ struct StagingSlot {
     size_t cap = 0;
     hipEvent_t copied = nullptr;
     hipEvent_t ev = nullptr;
+    bool launched = false;   // ev has been recorded after a launch
 };
 
 struct bf_plan_s {
@@ -45,6 +46,22 @@ struct bf_plan_s {
     void *lp_lo[2] = {nullptr, nullptr};
     int *lp_exp[2] = {nullptr, nullptr};
     size_t lp_stride = 0;       // 16-byte units per W
+
+    // Pool updates.  Every entry has two device slots, w and w + n_w, in each
+    // operand layout; half[w] says which one is current.  Launches read the
+    // slot that was current when they were enqueued (descriptors carry slot
+    // numbers).  An update writes the other slot on update_stream, which
+    // first waits for guard[w]: an event on marker_stream that completes
+    // when every launch issued before the entry's previous update has.
+    std::vector<uint8_t> half;
+    std::vector<hipEvent_t> guard;
+    hipStream_t update_stream = nullptr;
+    hipStream_t marker_stream = nullptr;
+    hipEvent_t updated = nullptr;        // after the latest update's transforms
+    hipEvent_t stage_free = nullptr;     // after the latest update's upload of its W
+    void *w_pinned = nullptr;            // one W, pinned host memory
+    float2 *w_stage = nullptr;           // one W, device memory
+    bool any_update = false;
 
     hipStream_t copy_stream = nullptr;   // descriptor uploads (overlap the previous launch)
     std::mutex mu;              // guards the ring, the tables and the sort buffers

@@ -118,6 +118,12 @@ def test_calls_on_null_handles(L):
     assert L.bf_tune_save(None, b"/tmp/x") == bf.BF_ERR_INVALID
 
 
+def test_plan_update_rejects_null_arguments(L):
+    w = np.zeros((64, 4), np.complex64)
+    assert L.bf_plan_update(None, 0, w.ctypes.data, None) == bf.BF_ERR_INVALID
+    assert "plan is null" in bf.bf_last_error()
+
+
 def test_server_create_rejects_null_plan(L):
     h = ctypes.c_void_p()
     assert L.bf_server_create(ctypes.byref(h), None, None) == bf.BF_ERR_INVALID
