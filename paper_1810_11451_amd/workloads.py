@@ -7,8 +7,7 @@ their inputs from it without sharing any computation.
 Shapes follow the beamforming paragraph of Section III of the paper: W is
 64 x f (one row per antenna of the 4 x 8 x 2 array of Section II), S is
 f x 60 (one row per flow, one column per resource element), and f ranges
-from 0 to 36.  The paper gives no value distributions; the ones used here
-are the readings stated in the design notes:
+from 0 to 36.  The paper gives no value distributions; these are used:
 
 * CN(0,1): real and imaginary parts independently N(0, 1/2).
 * normalised 256-QAM: I and Q independently uniform over the odd levels
@@ -243,3 +242,33 @@ def exact_integer_batch(rng: np.random.Generator, n: int, n_w: int, f_max: int =
     f = rng.integers(0, f_max + 1, size=n).astype(np.int32)
     blocks = [qam256_levels(rng, (int(ft), B)) for ft in f]
     return _pack(f"exact-integer n={n}", W, w_ids, f, blocks)
+
+
+# ---------------------------------------------------------------------------
+# Filter stage (Section III, the filter paragraph): blocks of 2048 complex
+# samples and a filter sequence of 1..2048 taps.
+
+N_FILTER = 2048
+
+
+def filter_signals(rng: np.random.Generator, n: int) -> np.ndarray:
+    """n blocks of 2048 CN(0,1) samples, complex64 [n, 2048]."""
+    return cn01(rng, (n, N_FILTER)).astype(np.complex64)
+
+
+def random_taps(rng: np.random.Generator, n_taps: int) -> np.ndarray:
+    """n_taps CN(0, 1/n_taps) taps, complex64 (unit expected energy)."""
+    return (cn01(rng, (n_taps,)) / math.sqrt(n_taps)).astype(np.complex64)
+
+
+def lowpass_taps(n_taps: int, cutoff: float) -> np.ndarray:
+    """Real windowed-sinc lowpass taps (Hamming window), complex64.
+
+    cutoff is the passband edge as a fraction of the sample rate (0..0.5);
+    the taps are normalised to unit DC gain.  A long stopband makes |H|
+    span several orders of magnitude, the hard case for the error bar."""
+    n = np.arange(n_taps, dtype=np.float64) - (n_taps - 1) / 2.0
+    taps = 2.0 * cutoff * np.sinc(2.0 * cutoff * n)
+    taps *= 0.54 - 0.46 * np.cos(2.0 * np.pi * np.arange(n_taps) / max(n_taps - 1, 1))
+    taps /= np.sum(taps)
+    return taps.astype(np.complex64)
