@@ -76,6 +76,7 @@ typedef enum {
 typedef struct bf_plan_s *bf_plan;
 typedef struct bf_graph_s *bf_graph;
 typedef struct bf_server_s *bf_server;
+typedef struct bf_filter_s *bf_filter;
 
 /* ---- plan: the resident W pool --------------------------------------
  * W is constant across many products (Section III), so its preparation
@@ -276,7 +277,29 @@ bf_status bf_server_destroy(bf_server server);
 /* CLOCK_MONOTONIC in nanoseconds (the clock of t_arrival_ns and t_done_ns). */
 int64_t bf_now_ns(void);
 
-
+/* ---- filter stage -------------------------------------------------------
+ * The pipeline's other stage of Section III: a block s of 2048 complex
+ * samples is filtered as IFFT(MULT(FFT(s))), MULT being pointwise
+ * multiplication by H, the 2048-point FFT of the filter sequence h
+ * zero-padded to 2048 (so y is the circular convolution of s with h).
+ * Conventions: FFT(x)[k] = sum_n x[n] exp(-2 pi i k n / 2048); the inverse
+ * carries 1/2048.  Arithmetic is FP32 with twiddles rounded once from FP64.
+ *
+ * bf_filter_create: h host complex64 [n_taps], 1 <= n_taps <= 2048, may be
+ * freed on return; H is computed on the device with the filter's own
+ * transform; the call synchronises hip_stream.  Errors: BF_ERR_INVALID
+ * (null pointers, n_taps out of range), BF_ERR_OOM, BF_ERR_DEVICE. */
+bf_status bf_filter_create(bf_filter *out, const void *h, int32_t n_taps, void *hip_stream);
+/* Filters `batch` blocks: x and y device complex64 [batch][2048], 8-byte
+ * aligned; y may be the same buffer as x (in place) but must not overlap it
+ * otherwise.  Asynchronous, ordered on hip_stream; batch = 0 does nothing.
+ * Errors: BF_ERR_INVALID (null filter or buffers, batch < 0, misalignment,
+ * partial overlap), BF_ERR_DEVICE. */
+bf_status bf_filter_apply(bf_filter flt, int32_t batch, const void *x, void *y, void *hip_stream);
+/* Copies H (complex64 [2048]) to host memory. */
+bf_status bf_filter_spectrum(bf_filter flt, void *H_out);
+/* Releases the filter after the device has finished all work. */
+bf_status bf_filter_destroy(bf_filter flt);
 
 /* ---- diagnostics ------------------------------------------------------ */
 const char *bf_status_str(bf_status s);

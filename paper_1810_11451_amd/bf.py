@@ -79,6 +79,10 @@ _SIGS = {
     "bf_plan_destroy": (_i32, [_vp]),
     "bf_plan_info": (_i32, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_u32)]),
     "bf_plan_update": (_i32, [_vp, _i32, _vp, _vp]),
+    "bf_filter_create": (_i32, [ctypes.POINTER(_vp), _vp, _i32, _vp]),
+    "bf_filter_apply": (_i32, [_vp, _i32, _vp, _vp, _vp]),
+    "bf_filter_spectrum": (_i32, [_vp, _vp]),
+    "bf_filter_destroy": (_i32, [_vp]),
     "bf_apply": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _i32, _vp]),
     "bf_apply_packed": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _i32, _vp]),
     "bf_check_batch": (_i32, [_i32, _i32, _i32, _vp, _vp, _vp, _vp]),
@@ -469,3 +473,59 @@ def loadgen_replay(server: Server, reqs: np.ndarray, t_offset_ns: np.ndarray) ->
                                    reqs.shape[0], done.ctypes.data)
     _check(rc, "bf_loadgen_replay")
     return done, int(rc)
+
+
+# ---- filter stage ----------------------------------------------------------
+
+N_FILTER = 2048
+
+
+class Filter:
+    """Owns a bf_filter handle; destroyed with bf_filter_destroy on close()."""
+
+    def __init__(self, handle: int, n_taps: int):
+        self.handle = handle
+        self.n_taps = n_taps
+
+    def close(self):
+        if self.handle:
+            _check(lib().bf_filter_destroy(self.handle), "bf_filter_destroy")
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):  # pragma: no cover
+        try:
+            if self.handle:
+                lib().bf_filter_destroy(self.handle)
+        except Exception:
+            pass
+
+
+def bf_filter_create(h, stream=None) -> Filter:
+    h = np.ascontiguousarray(np.asarray(h).reshape(-1), dtype=np.complex64)
+    out = _vp()
+    _check(lib().bf_filter_create(ctypes.byref(out), h.ctypes.data, int(h.shape[0]), _stream(stream)),
+           "bf_filter_create")
+    return Filter(out.value, int(h.shape[0]))
+
+
+def bf_filter_apply(flt: Filter, batch: int, x, y, stream=None) -> None:
+    """x, y: device pointers (int) or torch tensors of complex64 [batch, 2048]."""
+    xp = x.data_ptr() if hasattr(x, "data_ptr") else int(x)
+    yp = y.data_ptr() if hasattr(y, "data_ptr") else int(y)
+    _check(lib().bf_filter_apply(flt.handle, int(batch), xp, yp, _stream(stream)), "bf_filter_apply")
+
+
+def bf_filter_spectrum(flt: Filter) -> np.ndarray:
+    H = np.zeros(N_FILTER, np.complex64)
+    _check(lib().bf_filter_spectrum(flt.handle, H.ctypes.data), "bf_filter_spectrum")
+    return H
+
+
+def bf_filter_destroy(flt: Filter) -> None:
+    flt.close()

@@ -124,6 +124,19 @@ def test_plan_update_rejects_null_arguments(L):
     assert "plan is null" in bf.bf_last_error()
 
 
+def test_filter_rejects_bad_arguments_before_device(L):
+    h = ctypes.c_void_p()
+    taps = np.ones(4, np.complex64)
+    assert L.bf_filter_create(None, taps.ctypes.data, 4, None) == bf.BF_ERR_INVALID
+    assert L.bf_filter_create(ctypes.byref(h), None, 4, None) == bf.BF_ERR_INVALID
+    assert L.bf_filter_create(ctypes.byref(h), taps.ctypes.data, 0, None) == bf.BF_ERR_INVALID
+    assert L.bf_filter_create(ctypes.byref(h), taps.ctypes.data, 2049, None) == bf.BF_ERR_INVALID
+    assert "n_taps" in bf.bf_last_error()
+    assert L.bf_filter_apply(None, 1, None, None, None) == bf.BF_ERR_INVALID
+    assert L.bf_filter_destroy(None) == bf.BF_ERR_INVALID
+    assert h.value is None
+
+
 def test_server_create_rejects_null_plan(L):
     h = ctypes.c_void_p()
     assert L.bf_server_create(ctypes.byref(h), None, None) == bf.BF_ERR_INVALID
