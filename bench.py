@@ -39,7 +39,8 @@ PEAK_FP32_TFLOPS = 157.3
 PEAK_LP_TFLOPS = 2500.0
 PRECS = {"fp32": bf.BF_FP32, "fp32_3m": bf.BF_FP32_3M, "fp16": bf.BF_FP16, "bf16": bf.BF_BF16,
          "fp16x2": bf.BF_FP16X2, "bf16x2": bf.BF_BF16X2}
-CONFIGS = {1: wl.config1, 2: wl.config2, 3: wl.config3, 4: wl.config4, 5: None}
+CONFIGS = {1: wl.config1, 2: wl.config2, 3: wl.config3, 4: wl.config4, 5: None, 6: None}
+FILTER_METRIC = "blocks/s + %roofline for the batched 2048-point FFT -> MULT -> IFFT filter stage"
 from paper_1810_11451_amd.probe.traffic import kernel_sha  # noqa: E402
 
 
@@ -112,7 +113,7 @@ def load_traffic(workload_key: str):
     except ValueError:
         return None
     entry = data.get(workload_key)
-    if not entry or entry.get("kernel_sha") != kernel_sha():
+    if not entry or entry.get("kernel_sha") != kernel_sha(workload_key):
         return None
     return entry.get("traffic_bytes_per_launch")
 
@@ -207,6 +208,77 @@ def serve_bench(args, torch) -> dict:
     return out
 
 
+def filter_cpu_baseline(s, h, target_s: float) -> dict:
+    """The filter oracle (numpy complex128 FFTs, as it stands) on seeded
+    blocks of the same workload, repeated until about target_s."""
+    from oracle import filter_oracle as fo
+    rng = np.random.default_rng(54321)
+    pick = rng.choice(s.shape[0], size=min(s.shape[0], 256), replace=False)
+    sample = s[pick]
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        fo.filter_apply(sample, h)
+        reps += 1
+        dt = time.perf_counter() - t0
+        if dt >= target_s:
+            break
+    return {"value": round(reps * len(pick) / dt, 1), "unit": "blocks/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{len(pick)} of the {s.shape[0]} blocks of the same workload (seeded choice), "
+                      f"x{reps} passes, numpy complex128 FFTs on one thread, {dt:.1f} s"}
+
+
+def filter_bench(args, torch) -> dict:
+    """Filter stage: 16384 blocks of 2048 CN(0,1) samples through a 127-tap
+    windowed-sinc lowpass (cutoff 0.1); three disjoint x/y buffer sets
+    rotate.  A step is one bf_filter_apply over all blocks."""
+    n, n_taps = 16384, 127
+    rng = np.random.default_rng(6)
+    s = wl.filter_signals(rng, n)
+    h = wl.lowpass_taps(n_taps, 0.1)
+    flt = bf.bf_filter_create(h)
+    xs = [torch.from_numpy(s).cuda() for _ in range(args.copies)]
+    ys = [torch.empty_like(xs[0]) for _ in range(args.copies)]
+    stream = torch.cuda.current_stream()
+    K, W = args.steps, args.warmup
+    for i in range(W):
+        bf.bf_filter_apply(flt, n, xs[i % args.copies], ys[i % args.copies])
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    t0 = time.perf_counter()
+    for i in range(K):
+        ev[i][0].record(stream)
+        bf.bf_filter_apply(flt, n, xs[i % args.copies], ys[i % args.copies])
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    kern_s = float(np.mean(kern_ms)) / 1e3
+    nbytes = n * wl.N_FILTER * 8 * 2                    # each block read once, written once
+    flops_conv = n * (2 * 5 * wl.N_FILTER * 11 + 6 * wl.N_FILTER)   # 5 N log2 N per FFT + complex mult
+    ach = nbytes / kern_s / 1e9
+    out = {"metric": FILTER_METRIC, "value": round(n * K / wall, 1), "unit": "blocks/s",
+           "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": round(wall / K * 1e3, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": f"filter: {n} blocks of 2048 CN(0,1) samples, {n_taps}-tap "
+                                  "windowed-sinc lowpass", "n_blocks": n, "n_taps": n_taps,
+                      "buffer_sets": args.copies},
+           "latency_us": {"p50": round(float(np.percentile(kern_ms, 50)) * 1e3, 2),
+                          "p99": round(float(np.percentile(kern_ms, 99)) * 1e3, 2)},
+           "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": load_traffic("config6-filter"),
+                        "kernel": "filter_kernel", "kernel_us_mean": round(kern_s * 1e6, 2),
+                        "kernel_timing": "HIP events around each launch on the launch stream",
+                        "algorithmic": {"bytes_per_launch": nbytes, "flops_conventional": flops_conv,
+                                        "ai_flop_per_byte": round(flops_conv / nbytes, 2)},
+                        "gflops_conventional": round(flops_conv / kern_s / 1e9, 1)}}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = filter_cpu_baseline(s, h, min(args.cpu_seconds, 10.0))
+    flt.close()
+    return out
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -232,8 +304,8 @@ def main(argv=None) -> int:
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the products are "
-              "independent and this library has no multi-GPU path (sharding is by item, see the "
-              "design notes).", file=sys.stderr)
+              "independent and this library has no multi-GPU path (a multi-GPU version would "
+              "shard the items, with no exchange between GPUs).", file=sys.stderr)
         return 2
 
     import torch
@@ -243,6 +315,9 @@ def main(argv=None) -> int:
     from paper_1810_11451_amd.device import DeviceBatch
 
     torch.cuda.set_device(0)
+    if args.config == 6:
+        print(json.dumps(filter_bench(args, torch)), flush=True)
+        return 0
     if args.config == 5:
         res = serve_bench(args, torch)
         fp = res["fp32"]

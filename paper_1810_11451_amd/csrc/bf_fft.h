@@ -23,9 +23,20 @@ namespace bff {
 constexpr int kN = 2048;
 constexpr int kThreads = 256;
 constexpr int kPts = 8;                   // points per thread
-constexpr int kLdsPad = kN + kN / 8;      // one pad entry per 8 (bank spread)
+constexpr int kLdsPad = kN;               // LDS entries per buffer (swizzled, no padding)
 
-__host__ __device__ inline int pad(int j) { return j + (j >> 3); }
+// LDS position of entry j: its row of 16 entries (128 bytes) stays, the
+// position inside the row is XORed with h(row) = (row & 7) ^ (bit 2 of row
+// << 3).  With 8-byte accesses checked for bank conflicts over groups of 16
+// lanes, every access pattern of the passes then touches 16 different
+// positions per group: the stride-8 writes of pass 1 (rows differ in their
+// low 3 bits), the group-of-8 writes of pass 2 (bit 3 set apart by bit 2
+// of the row) and all unit-stride accesses (one row, a bijection within it).
+__host__ __device__ inline int pad(int j)
+{
+    const int row = j >> 4;
+    return j ^ ((row & 7) ^ (((row >> 2) & 1) << 3));
+}
 
 __host__ __device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __host__ __device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }

@@ -3,8 +3,8 @@
 // filter sequence, computed once per filter with the same transform.
 //
 // One workgroup of 256 threads transforms a block with the Stockham passes
-// of bf_fft.h, the intermediate results going through two padded LDS
-// buffers.  The inverse transform is the forward one applied to the
+// of bf_fft.h, the intermediate results going through two swizzled LDS
+// buffers (no bank conflicts).  The inverse transform is the forward one applied to the
 // conjugate: IFFT(Z) = conj(FFT(conj(Z))) / 2048.  The forward transform
 // leaves thread t with X[t + 256 q], which is exactly the input pattern of
 // the next forward transform, so the multiply by H, the conjugation and the

@@ -25,12 +25,16 @@ from pathlib import Path
 ROOT = Path(__file__).resolve().parents[2]
 KERNEL_SOURCES = ["paper_1810_11451_amd/csrc/bf_kernels.hip",
                   "paper_1810_11451_amd/csrc/bf_internal.h"]
+FILTER_SOURCES = ["paper_1810_11451_amd/csrc/bf_filter.hip",
+                  "paper_1810_11451_amd/csrc/bf_fft.h"]
 TRAFFIC_JSON = ROOT / "profiles" / "traffic.json"
 
 
-def kernel_sha() -> str:
+def kernel_sha(key: str = "") -> str:
+    """Hash of the kernel sources a traffic entry depends on (the filter
+    stage's for keys naming it, else the beamforming kernels')."""
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in (FILTER_SOURCES if "filter" in key else KERNEL_SOURCES):
         h.update((ROOT / p).read_bytes())
     return h.hexdigest()[:16]
 
@@ -80,7 +84,7 @@ def main(argv=None) -> int:
     fetch_b = f_kib * 1024.0 * k_fetch
     write_b = w_kib * 1024.0 * k_write
     entry = {
-        "kernel_sha": kernel_sha(),
+        "kernel_sha": kernel_sha(a.key),
         "kernel": a.kernel,
         "fetch_kib_per_dispatch": round(f_kib, 1), "write_kib_per_dispatch": round(w_kib, 1),
         "dispatches": [nf, nw],
