@@ -190,7 +190,8 @@ typedef struct {
                               schedule 3 (always staged): producer waves per
                               workgroup and products prefetched in their
                               registers, 0 = (4, 1), 1 = (8, 1), 2 = (8, 2),
-                              3 = (8, 3), 4 = (12, 1), 5 = (12, 2) */
+                              3 = (8, 3), 4 = (12, 1), 5 = (12, 2); the
+                              three-product form uses at most 8 producers */
 } bf_variant;
 
 bf_status bf_set_variant(bf_plan plan, bf_prec prec, int32_t f_bucket, const bf_variant *v);

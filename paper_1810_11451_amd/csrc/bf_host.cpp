@@ -95,7 +95,9 @@ static bf_status default_variants(bf_plan p)
             bf_variant v{};
             const bool full = b == kBucketCount - 1;
             const bool fp32 = pr == BF_FP32 || pr == BF_FP32_3M;
-            if (full && fp32)
+            if (full && pr == BF_FP32_3M)
+                v = bf_variant{3, 0, 0, 1};   // wave-specialised, 8 producers, depth 1, as given
+            else if (full && fp32)
                 v = bf_variant{3, 0, 0, 5};   // wave-specialised, 12 producers, depth 2, as given
             else if (full)
                 v = bf_variant{2, 2, 0, 0};   // 16-bit forms: streaming, 2 per CU
@@ -443,6 +445,8 @@ bfk::LaunchCfg choose_launch(bf_plan p, bf_prec prec, int n, int max_f, bool vec
     const int ws = (cfg.schedule == 3 && v.store >= 0 && v.store <= 5) ? v.store : 0;
     cfg.producers = kProducers[ws];
     cfg.depth = kDepths[ws];
+    if (prec == BF_FP32_3M && cfg.producers > 8)
+        cfg.producers = 8;   // its two accumulator sets leave registers for 12 waves only
     if (v.schedule == 0) {
         cfg.grid = n;
     } else {

@@ -499,17 +499,34 @@ __device__ __forceinline__ void contract_stage_3m(const f2v *__restrict__ lds,
     }
 }
 
-// contract_stage_3m for the wave-specialised schedule, with the operands of
-// W staged in LDS by the producer waves (component planes, as in the plan:
-// [2 halves][pairs][3][64 lanes] floats).  The A and B values of each pair
-// are read ahead of its products in batches of 6 pairs: batch k is issued
-// once pair 6k - 4 is, so at most 10 pairs occupy registers and each wait
-// covers only the oldest reads.  Rows past f and pairs past the plan's hold
-// older data and feed no product.
-__device__ __forceinline__ void contract_stage_3m_lds(const f2v *__restrict__ lds,
-                                                      const float *__restrict__ lds_a, int pairs,
-                                                      int f, int wave, int lane,
-                                                      f2v *__restrict__ tile)
+// Row r of a wave's 32 x 32 quadrant of R (staged in LDS, 64 x 60
+// row-major) from the three products: Re = T1 - T2, Im = (T3 - T1) - T2.
+__device__ __forceinline__ void stage_row_3m(const floatx16 &t1, const floatx16 &t2, const floatx16 &t3,
+                                             int r, int wave, int lane, f2v *__restrict__ tile)
+{
+    const int h = lane >> 5;
+    const int i = 32 * (wave >> 1) + 8 * (r >> 2) + 4 * h + (r & 3);
+    const int j = 32 * (wave & 1) + (lane & 31);
+    if (j < kB)
+        tile[i * kB + j] = f2v{t1[r] - t2[r], (t3[r] - t1[r]) - t2[r]};
+}
+
+// The three-product chain of one product for the wave-specialised schedule,
+// with the operands of W staged in LDS by the producer waves (component
+// planes, as in the plan: [2 halves][pairs][3][64 lanes] floats).  The A
+// and B values of each pair are read ahead of its products in batches of 6
+// pairs: batch k is issued once pair 6k - 4 is, so at most 10 pairs occupy
+// registers and each wait covers only the oldest reads.  Rows past f and
+// pairs past the plan's hold older data and feed no product.
+// With kEpi, the previous product's accumulators (p1, p2, p3) are staged to
+// `prev_tile` one row per pair during the chain, so the epilogue runs while
+// the matrix cores are busy instead of after they drain.
+template <bool kEpi>
+__device__ __forceinline__ void chain_3m_lds(const f2v *__restrict__ lds, const float *__restrict__ lds_a,
+                                             int pairs, int f, int wave, int lane, floatx16 &t1,
+                                             floatx16 &t2, floatx16 &t3, const floatx16 &p1,
+                                             const floatx16 &p2, const floatx16 &p3,
+                                             f2v *__restrict__ prev_tile)
 {
     const int h = lane >> 5;
     const int n = lane & 31;
@@ -519,7 +536,9 @@ __device__ __forceinline__ void contract_stage_3m_lds(const f2v *__restrict__ ld
     constexpr int kBatch = 6, kLead = 4;
     const f2v *col = lds + h * kLdsCols + 32 * nt + n;
     const float *ab = lds_a + mt * pairs * 192 + lane;
-    floatx16 t1 = {}, t2 = {}, t3 = {};
+    t1 = floatx16{};
+    t2 = floatx16{};
+    t3 = floatx16{};
     f3v a[kPairsMax];
     f2v b[kPairsMax];
 #pragma unroll
@@ -539,15 +558,20 @@ __device__ __forceinline__ void contract_stage_3m_lds(const f2v *__restrict__ ld
         }
         if (p < np)
             mfma3(a[p], b[p], t1, t2, t3);
+        if constexpr (kEpi) {
+            if (p < 16)
+                stage_row_3m(p1, p2, p3, p, wave, lane, prev_tile);
+        }
         __builtin_amdgcn_sched_barrier(0);
     }
-    const int j = 32 * nt + n;
+}
+
+__device__ __forceinline__ void stage_3m(const floatx16 &t1, const floatx16 &t2, const floatx16 &t3,
+                                         int wave, int lane, f2v *__restrict__ tile)
+{
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-        const int i = 32 * mt + 8 * (r >> 2) + 4 * h + (r & 3);
-        if (j < kB)
-            tile[i * kB + j] = f2v{t1[r] - t2[r], (t3[r] - t1[r]) - t2[r]};
-    }
+    for (int r = 0; r < 16; ++r)
+        stage_row_3m(t1, t2, t3, r, wave, lane, tile);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (block b runs on
@@ -918,19 +942,20 @@ struct WBuf<false> {
     float v[2][1];
 };
 
-// One producer iteration for product t >= 1 of the share: R(t-1) out, the
-// data of product t+1 into LDS from register set kPut, the loads for product
-// t+1+kDepth into that set.  Past the end of the share the descriptor index
-// is clamped and the S loads read the sink, so every memory instruction is
-// unconditional; a put past the end fills LDS buffers nobody reads any more.
-template <int kProd, int kDepth, int kPut, bool k3M>
+// One producer iteration t >= kLag: R(t - kLag) out (the consumers staged it
+// by the end of iteration t - 1), the data of product t+1 into LDS from
+// register set kPut, the loads for product t+1+kDepth into that set.  Past
+// the end of the share the descriptor index is clamped and the S loads read
+// the sink, so every memory instruction is unconditional; a put past the
+// end fills LDS buffers nobody reads any more.
+template <int kProd, int kDepth, int kPut, bool k3M, int kLag>
 __device__ __forceinline__ void ws_produce_step(PRegs<kProd, k3M> (&sr)[kDepth], c_item *my, int stride,
                                                 int t, int n_my, float2 *sink,
                                                 f2v (*s_buf)[kFMax * kLdsCols], WBuf<k3M> &a_buf,
                                                 const f2v (*r_buf)[kM * kB], const void *apool,
                                                 int a_w_stride, int pairs, int ptid)
 {
-    p_store_r<kProd>(item_at(my, t - 1, stride).R, r_buf[(t - 1) & 1], ptid);
+    p_store_r<kProd>(item_at(my, t - kLag, stride).R, r_buf[(t - kLag) & 1], ptid);
     const BfItem d1 = item_at(my, min(t + 1, n_my - 1), stride);
     p_put_item<kProd, k3M>(s_buf[(t + 1) & 1], a_buf.v[(t + 1) & 1], sr[kPut], d1.f, pairs, ptid);
     const int tn = t + 1 + kDepth;
@@ -979,12 +1004,42 @@ __global__ __launch_bounds__(64 * (kWaves + kProd)) void apply_fp32_ws(
         const int wave = wave8;
         int f = item_at(my, 0, stride).f;
         if constexpr (k3M) {
+            // Product k's chain runs with product k - 1's epilogue folded in
+            // (two accumulator sets, A for even k, B for odd k); the last
+            // product's epilogue gets an iteration of its own, so the R of
+            // product k is staged during iteration k + 1 and drained by the
+            // producers in iteration k + 2.
+            floatx16 a1, a2, a3, b1, b2, b3;
             __syncthreads();
-            for (int t = 0; t < n_my; ++t) {
-                contract_stage_3m_lds(s_buf[t & 1], a_buf.v[t & 1], pairs, f, wave, lane, r_buf[t & 1]);
+            chain_3m_lds<false>(s_buf[0], a_buf.v[0], pairs, f, wave, lane, a1, a2, a3, a1, a2, a3,
+                                nullptr);
+            __builtin_amdgcn_sched_barrier(0);
+            f = item_at(my, min(1, n_my - 1), stride).f;
+            __syncthreads();
+            int k = 1;
+            while (true) {
+                if (k >= n_my) {
+                    stage_3m(a1, a2, a3, wave, lane, r_buf[(k - 1) & 1]);
+                    __syncthreads();
+                    break;
+                }
+                chain_3m_lds<true>(s_buf[k & 1], a_buf.v[k & 1], pairs, f, wave, lane, b1, b2, b3, a1,
+                                   a2, a3, r_buf[(k - 1) & 1]);
                 __builtin_amdgcn_sched_barrier(0);
-                f = item_at(my, min(t + 1, n_my - 1), stride).f;
+                f = item_at(my, min(k + 1, n_my - 1), stride).f;
                 __syncthreads();
+                ++k;
+                if (k >= n_my) {
+                    stage_3m(b1, b2, b3, wave, lane, r_buf[(k - 1) & 1]);
+                    __syncthreads();
+                    break;
+                }
+                chain_3m_lds<true>(s_buf[k & 1], a_buf.v[k & 1], pairs, f, wave, lane, a1, a2, a3, b1,
+                                   b2, b3, r_buf[(k - 1) & 1]);
+                __builtin_amdgcn_sched_barrier(0);
+                f = item_at(my, min(k + 1, n_my - 1), stride).f;
+                __syncthreads();
+                ++k;
             }
         } else {
             // W of product t is in registers when t starts; the chain of t
@@ -1028,53 +1083,61 @@ __global__ __launch_bounds__(64 * (kWaves + kProd)) void apply_fp32_ws(
             p_load_item<kProd, k3M>(sr[u % kDepth], d, u < n_my, sink, apool, a_w_stride, pairs, ptid);
         }
         __syncthreads();
-        // product 0
-        {
+        // The consumers stage R(t) during iteration t (four-product form) or
+        // t + 1 (three-product form, epilogue folded into the next chain), so
+        // iteration t writes R(t - kLag).  The first kLag iterations have no R
+        // to write and issue sink stores instead.
+        constexpr int kLag = k3M ? 2 : 1;
+#pragma unroll
+        for (int t0 = 0; t0 < kLag; ++t0) {
             prime_store_count<kPStoreRounds<kProd>>(sink, plane);
-            const BfItem d1 = item_at(my, min(1, n_my - 1), stride);
-            p_put_item<kProd, k3M>(s_buf[1], a_buf.v[1], sr[1 % kDepth], d1.f, pairs, ptid);
-            const int tn = 1 + kDepth;
+            const BfItem d1 = item_at(my, min(t0 + 1, n_my - 1), stride);
+            p_put_item<kProd, k3M>(s_buf[(t0 + 1) & 1], a_buf.v[(t0 + 1) & 1], sr[(t0 + 1) % kDepth], d1.f,
+                                   pairs, ptid);
+            const int tn = t0 + 1 + kDepth;
             const BfItem dn = item_at(my, min(tn, n_my - 1), stride);
-            p_load_item<kProd, k3M>(sr[1 % kDepth], dn, tn < n_my, sink, apool, a_w_stride, pairs, ptid);
+            p_load_item<kProd, k3M>(sr[(t0 + 1) % kDepth], dn, tn < n_my, sink, apool, a_w_stride, pairs,
+                                    ptid);
             __syncthreads();
         }
-        // Products 1.. in groups of kDepth, so that every register set index
-        // is a constant: product t puts product t+1 from set (t+1) % kDepth.
-        // The loop has a single exit at its end (a break in the middle becomes
-        // a flow block inside the loop, whose pessimistic memory-count state
-        // would then reach the loop's first put); the remaining products
-        // follow it.
+        // Iterations kLag .. n_my + kLag - 2 in groups of kDepth, so that every
+        // register set index is a constant: iteration t puts product t+1 from
+        // set (t+1) % kDepth.  The loop has a single exit at its end (a break
+        // in the middle becomes a flow block inside the loop, whose pessimistic
+        // memory-count state would then reach the loop's first put); the
+        // remaining iterations follow it.
         static_assert(kDepth >= 1 && kDepth <= 3, "prefetch depth");
         const int groups = (n_my - 1) / kDepth;
         const int rest = (n_my - 1) - groups * kDepth;
-        int t = 1;
+        constexpr int kP0 = (kLag + 1) % kDepth, kP1 = (kLag + 2) % kDepth, kP2 = (kLag + 3) % kDepth;
+        int t = kLag;
         for (int g = 0; g < groups; ++g) {
-            ws_produce_step<kProd, kDepth, 2 % kDepth, k3M>(sr, my, stride, t, n_my, sink, s_buf, a_buf,
-                                                            r_buf, apool, a_w_stride, pairs, ptid);
+            ws_produce_step<kProd, kDepth, kP0, k3M, kLag>(sr, my, stride, t, n_my, sink, s_buf, a_buf,
+                                                           r_buf, apool, a_w_stride, pairs, ptid);
             __syncthreads();
             if constexpr (kDepth >= 2) {
-                ws_produce_step<kProd, kDepth, 3 % kDepth, k3M>(sr, my, stride, t + 1, n_my, sink, s_buf,
-                                                                a_buf, r_buf, apool, a_w_stride, pairs, ptid);
+                ws_produce_step<kProd, kDepth, kP1, k3M, kLag>(sr, my, stride, t + 1, n_my, sink, s_buf,
+                                                               a_buf, r_buf, apool, a_w_stride, pairs, ptid);
                 __syncthreads();
             }
             if constexpr (kDepth >= 3) {
-                ws_produce_step<kProd, kDepth, 4 % kDepth, k3M>(sr, my, stride, t + 2, n_my, sink, s_buf,
-                                                                a_buf, r_buf, apool, a_w_stride, pairs, ptid);
+                ws_produce_step<kProd, kDepth, kP2, k3M, kLag>(sr, my, stride, t + 2, n_my, sink, s_buf,
+                                                               a_buf, r_buf, apool, a_w_stride, pairs, ptid);
                 __syncthreads();
             }
             t += kDepth;
         }
         if constexpr (kDepth >= 2) {
             if (rest >= 1) {
-                ws_produce_step<kProd, kDepth, 2 % kDepth, k3M>(sr, my, stride, t, n_my, sink, s_buf, a_buf,
-                                                                r_buf, apool, a_w_stride, pairs, ptid);
+                ws_produce_step<kProd, kDepth, kP0, k3M, kLag>(sr, my, stride, t, n_my, sink, s_buf, a_buf,
+                                                               r_buf, apool, a_w_stride, pairs, ptid);
                 __syncthreads();
             }
         }
         if constexpr (kDepth >= 3) {
             if (rest >= 2) {
-                ws_produce_step<kProd, kDepth, 3 % kDepth, k3M>(sr, my, stride, t + 1, n_my, sink, s_buf,
-                                                                a_buf, r_buf, apool, a_w_stride, pairs, ptid);
+                ws_produce_step<kProd, kDepth, kP1, k3M, kLag>(sr, my, stride, t + 1, n_my, sink, s_buf,
+                                                               a_buf, r_buf, apool, a_w_stride, pairs, ptid);
                 __syncthreads();
             }
         }
@@ -1513,11 +1576,13 @@ static hipError_t launch_ws(const LaunchCfg &cfg, BfHeader *blk, int n_items, co
     if (cfg.producers == 4)
         hipLaunchKernelGGL((apply_fp32_ws<k3M, 4, 1>), grid, dim3(64 * 8), 0, st, blk, items,
                            n_items, apool, a_stride, pairs);
-    else if (cfg.producers == 12 && cfg.depth == 2)
-        hipLaunchKernelGGL((apply_fp32_ws<k3M, 12, 2>), grid, dim3(64 * 16), 0, st, blk, items,
+    else if (!k3M && cfg.producers == 12 && cfg.depth == 2)
+        // (the three-product form's two accumulator sets do not fit 16 waves'
+        // register share; the host gives it at most 8 producers)
+        hipLaunchKernelGGL((apply_fp32_ws<false, 12, 2>), grid, dim3(64 * 16), 0, st, blk, items,
                            n_items, apool, a_stride, pairs);
-    else if (cfg.producers == 12)
-        hipLaunchKernelGGL((apply_fp32_ws<k3M, 12, 1>), grid, dim3(64 * 16), 0, st, blk, items,
+    else if (!k3M && cfg.producers == 12)
+        hipLaunchKernelGGL((apply_fp32_ws<false, 12, 1>), grid, dim3(64 * 16), 0, st, blk, items,
                            n_items, apool, a_stride, pairs);
     else if (cfg.depth == 3)
         hipLaunchKernelGGL((apply_fp32_ws<k3M, 8, 3>), grid, dim3(64 * 12), 0, st, blk, items,
