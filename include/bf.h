@@ -202,8 +202,24 @@ int32_t bf_f_bucket(int32_t f);
 bf_status bf_autotune(bf_plan plan, int32_t batch, const int32_t *w_ids, const int32_t *f,
                       const void *const *S, void *const *R, bf_prec prec, int32_t reps,
                       void *hip_stream, bf_variant *best, float *best_us);
+/* The tuning table as a database in the manner of the optimizer tool of
+ * Section IV, which picks the most efficient version of a building block for
+ * a given matrix size and target architecture.  Key: (architecture, CU
+ * count, precision form, f bucket); value: the variant and its measured
+ * kernel time in microseconds (0 for untuned defaults).  Text lines
+ *   arch cus prec bucket schedule wg_per_cu order store us
+ * e.g. "gfx950 256 5 4 3 0 0 1 177.20"; '#' starts a comment.
+ * bf_tune_save writes this device's entries, keeping the file's entries of
+ * other architectures or CU counts.  bf_tune_load applies the entries of
+ * this device's architecture and CU count (lines of the older form
+ * "prec bucket schedule wg_per_cu order store" apply to any device) and
+ * ignores the rest.  Errors: BF_ERR_INVALID (null arguments, unreadable or
+ * malformed file: nothing is applied). */
 bf_status bf_tune_save(bf_plan plan, const char *path);
 bf_status bf_tune_load(bf_plan plan, const char *path);
+/* The variant the plan uses for batches of precision form prec and mean f
+ * (0..36), and its recorded time (0: default, not measured). */
+bf_status bf_tune_query(bf_plan plan, bf_prec prec, int32_t f, bf_variant *v, float *tuned_us);
 
 /* ---- serving: continuous batching of arriving requests ----------------
  * The pipeline of Section II runs its stages continuously on arriving

@@ -96,6 +96,7 @@ _SIGS = {
                            ctypes.POINTER(bf_variant), ctypes.POINTER(ctypes.c_float)]),
     "bf_tune_save": (_i32, [_vp, ctypes.c_char_p]),
     "bf_tune_load": (_i32, [_vp, ctypes.c_char_p]),
+    "bf_tune_query": (_i32, [_vp, _i32, _i32, ctypes.POINTER(bf_variant), ctypes.POINTER(ctypes.c_float)]),
     "bf_status_str": (ctypes.c_char_p, [_i32]),
     "bf_last_error": (ctypes.c_char_p, []),
     "bf_build_info": (ctypes.c_char_p, []),
@@ -529,3 +530,12 @@ def bf_filter_spectrum(flt: Filter) -> np.ndarray:
 
 def bf_filter_destroy(flt: Filter) -> None:
     flt.close()
+
+
+def bf_tune_query(plan: Plan, prec: int, f: int):
+    """(variant tuple, recorded kernel us or 0) the plan uses for mean f."""
+    v = bf_variant()
+    us = ctypes.c_float()
+    _check(lib().bf_tune_query(plan.handle, int(prec), int(f), ctypes.byref(v), ctypes.byref(us)),
+           "bf_tune_query")
+    return v.as_tuple(), float(us.value)

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cstdarg>
+#include <cctype>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -925,6 +926,7 @@ extern "C" bf_status bf_autotune(bf_plan p, int32_t batch, const int32_t *w_ids,
     {
         std::lock_guard<std::mutex> lk(p->mu);
         p->table[prec][batch_bucket(sum_f, batch)] = best_v;
+        p->tuned_us[prec][batch_bucket(sum_f, batch)] = best_t;
     }
     if (best)
         *best = best_v;
@@ -933,29 +935,100 @@ extern "C" bf_status bf_autotune(bf_plan p, int32_t batch, const int32_t *w_ids,
     return BF_OK;
 }
 
+// Architecture key of the tuning database: the device's gfx name without
+// feature suffixes (e.g. "gfx950").
 static std::string arch_name()
 {
     int dev = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
         return "unknown";
-    return prop.gcnArchName;
+    std::string a = prop.gcnArchName;
+    const size_t colon = a.find(':');
+    return colon == std::string::npos ? a : a.substr(0, colon);
 }
+
+namespace {
+// One database entry: the best variant of a (precision form, f bucket) on
+// one architecture and CU count, with its measured time (0: not measured).
+struct TuneRow {
+    std::string arch;
+    int cus, prec, bucket;
+    bf_variant v;
+    float us;
+};
+
+// Parses a tuning file: v2 lines "arch cus prec bucket schedule wg_per_cu
+// order store us", or v1 lines "prec bucket schedule wg_per_cu order store"
+// (no architecture: they apply anywhere).  Returns false on a malformed line.
+bool read_tune_file(const char *path, std::vector<TuneRow> &rows)
+{
+    FILE *fp = fopen(path, "r");
+    if (!fp)
+        return false;
+    char line[256];
+    bool ok = true;
+    while (fgets(line, sizeof line, fp)) {
+        if (line[0] == '#' || line[0] == '\n')
+            continue;
+        TuneRow r{};
+        char arch[64] = {0};
+        int sc = 0, w = 0, o = 0, st = 0;
+        float us = 0.f;
+        if (std::isalpha((unsigned char)line[0])) {
+            if (sscanf(line, "%63s %d %d %d %d %d %d %d %f", arch, &r.cus, &r.prec, &r.bucket, &sc, &w, &o,
+                       &st, &us) != 9) {
+                ok = false;
+                break;
+            }
+            r.arch = arch;
+        } else {
+            const int got = sscanf(line, "%d %d %d %d %d %d", &r.prec, &r.bucket, &sc, &w, &o, &st);
+            if (got < 5) {
+                ok = false;
+                break;
+            }
+            r.cus = -1;   // v1: any device
+        }
+        r.v = bf_variant{sc, w, o, st};
+        r.us = us;
+        if (r.prec < 0 || r.prec >= kPrecCount || r.bucket < 0 || r.bucket >= kBucketCount ||
+            !valid_variant(r.v)) {
+            ok = false;
+            break;
+        }
+        rows.push_back(r);
+    }
+    fclose(fp);
+    return ok;
+}
+}  // namespace
 
 extern "C" bf_status bf_tune_save(bf_plan p, const char *path)
 {
     if (!p || !path)
         return bf_fail(BF_ERR_INVALID, "null argument");
+    const std::string arch = arch_name();
+    // Entries of other architectures or CU counts already in the file stay.
+    std::vector<TuneRow> keep, old;
+    if (read_tune_file(path, old))
+        for (const TuneRow &r : old)
+            if (r.cus >= 0 && !(r.arch == arch && r.cus == p->n_cu))
+                keep.push_back(r);
     FILE *fp = fopen(path, "w");
     if (!fp)
         return bf_fail(BF_ERR_INVALID, "cannot open %s for writing", path);
     std::lock_guard<std::mutex> lk(p->mu);
-    fprintf(fp, "# bf tune v1 arch=%s\n", arch_name().c_str());
-    fprintf(fp, "# prec bucket schedule wg_per_cu order store\n");
+    fprintf(fp, "# bf tune v2: the best variant per (architecture, CUs, precision form, f bucket)\n");
+    fprintf(fp, "# arch cus prec bucket schedule wg_per_cu order store us\n");
+    for (const TuneRow &r : keep)
+        fprintf(fp, "%s %d %d %d %d %d %d %d %.2f\n", r.arch.c_str(), r.cus, r.prec, r.bucket,
+                r.v.schedule, r.v.wg_per_cu, r.v.order, r.v.store, r.us);
     for (int pr = 0; pr < kPrecCount; ++pr)
         for (int b = 0; b < kBucketCount; ++b) {
             const bf_variant &v = p->table[pr][b];
-            fprintf(fp, "%d %d %d %d %d %d\n", pr, b, v.schedule, v.wg_per_cu, v.order, v.store);
+            fprintf(fp, "%s %d %d %d %d %d %d %d %.2f\n", arch.c_str(), p->n_cu, pr, b, v.schedule,
+                    v.wg_per_cu, v.order, v.store, p->tuned_us[pr][b]);
         }
     fclose(fp);
     return BF_OK;
@@ -965,34 +1038,30 @@ extern "C" bf_status bf_tune_load(bf_plan p, const char *path)
 {
     if (!p || !path)
         return bf_fail(BF_ERR_INVALID, "null argument");
-    FILE *fp = fopen(path, "r");
-    if (!fp)
-        return bf_fail(BF_ERR_INVALID, "cannot open %s", path);
-    char line[256];
-    std::vector<std::pair<std::pair<int, int>, bf_variant>> rows;
-    bool ok = true;
-    while (fgets(line, sizeof line, fp)) {
-        if (line[0] == '#' || line[0] == '\n')
-            continue;
-        int pr, b, sc, w, o, st = 0;
-        const int got = sscanf(line, "%d %d %d %d %d %d", &pr, &b, &sc, &w, &o, &st);
-        if (got < 5 || pr < 0 || pr >= kPrecCount || b < 0 || b >= kBucketCount) {
-            ok = false;
-            break;
-        }
-        bf_variant v{sc, w, o, st};
-        if (!valid_variant(v)) {
-            ok = false;
-            break;
-        }
-        rows.push_back({{pr, b}, v});
-    }
-    fclose(fp);
-    if (!ok)
-        return bf_fail(BF_ERR_INVALID, "malformed tune file %s", path);
+    std::vector<TuneRow> rows;
+    if (!read_tune_file(path, rows))
+        return bf_fail(BF_ERR_INVALID, "cannot read or malformed tune file %s", path);
+    const std::string arch = arch_name();
     std::lock_guard<std::mutex> lk(p->mu);
-    for (auto &r : rows)
-        p->table[r.first.first][r.first.second] = r.second;
+    for (const TuneRow &r : rows)
+        if (r.cus < 0 || (r.arch == arch && r.cus == p->n_cu)) {
+            p->table[r.prec][r.bucket] = r.v;
+            p->tuned_us[r.prec][r.bucket] = r.us;
+        }
+    return BF_OK;
+}
+
+extern "C" bf_status bf_tune_query(bf_plan p, bf_prec prec, int32_t f, bf_variant *v, float *tuned_us)
+{
+    if (!p || !v)
+        return bf_fail(BF_ERR_INVALID, "null argument");
+    if ((int)prec < 0 || (int)prec >= kPrecCount || f < 0 || f > BF_FMAX)
+        return bf_fail(BF_ERR_INVALID, "precision %d or f %d out of range", (int)prec, f);
+    std::lock_guard<std::mutex> lk(p->mu);
+    const int b = bf_f_bucket(f);
+    *v = p->table[prec][b];
+    if (tuned_us)
+        *tuned_us = p->tuned_us[prec][b];
     return BF_OK;
 }
 

@@ -68,6 +68,7 @@ struct bf_plan_s {
     std::vector<StagingSlot> ring;
     size_t ring_next = 0;
     bf_variant table[kPrecCount][kBucketCount];
+    float tuned_us[kPrecCount][kBucketCount] = {};   // measured by autotune or loaded; 0: default
     std::vector<BfItem> sort_tmp;
     std::vector<int> sort_scratch;
 };

@@ -116,6 +116,8 @@ def test_calls_on_null_handles(L):
     assert L.bf_graph_launch(None, None) == bf.BF_ERR_INVALID
     assert L.bf_graph_destroy(None) == bf.BF_ERR_INVALID
     assert L.bf_tune_save(None, b"/tmp/x") == bf.BF_ERR_INVALID
+    assert L.bf_tune_load(None, b"/tmp/x") == bf.BF_ERR_INVALID
+    assert L.bf_tune_query(None, 0, 36, None, None) == bf.BF_ERR_INVALID
 
 
 def test_plan_update_rejects_null_arguments(L):

@@ -214,6 +214,9 @@ def test_autotune_and_cache(tmp_path):
     assert us > 0
     bucket = bf.batch_bucket(b.f)
     assert bf.bf_get_variant(plan, bf.BF_FP32, bucket) == best
+    f_mean = int(round(float(np.mean(b.f))))
+    q_v, q_us = bf.bf_tune_query(plan, bf.BF_FP32, f_mean)
+    assert q_v == best and abs(q_us - us) < 1e-3
     path = tmp_path / "tune.txt"
     bf.bf_tune_save(plan, path)
     plan2 = bf.bf_plan_create(b.W)
@@ -265,3 +268,46 @@ def test_ws_long_shares(vname, per_wg):
     nz = b.f > 0
     assert np.max(err[nz]) <= FP32_TOL, f"max rel err {np.max(err[nz]):.3g}"
     assert np.all(R[~nz] == 0)
+
+
+def test_tune_database(tmp_path):
+    """The tuning table as a database keyed by (architecture, CUs, form, f
+    bucket): loads only this device's entries (and architecture-free ones),
+    keeps other devices' entries when saving, rejects malformed files."""
+    torch = require_gpu()
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    cus = bf.bf_device_cu_count()
+    rng = np.random.default_rng(131)
+    b = wl.random_batch(rng, 80, 3, dist="qam")
+    plan = bf.bf_plan_create(b.W, bf.BF_PREC_ALL)
+    default4 = bf.bf_tune_query(plan, bf.BF_FP32, 36)
+    path = tmp_path / "db.txt"
+    path.write_text("# hand-written entries\n"
+                    f"gfx942 304 {bf.BF_FP32} 2 1 2 1 0 99.00\n"
+                    f"{arch} {cus} {bf.BF_FP32} 2 2 1 0 1 12.50\n"
+                    f"{arch} {cus + 1} {bf.BF_FP32} 3 1 1 1 0 7.00\n"
+                    f"{bf.BF_BF16} 1 2 3 0 0\n")
+    announce("tune database")
+    bf.bf_tune_load(plan, path)
+    assert bf.bf_tune_query(plan, bf.BF_FP32, 20) == ((2, 1, 0, 1), 12.5)
+    assert bf.bf_tune_query(plan, bf.BF_BF16, 10) == ((2, 3, 0, 0), 0.0)
+    assert bf.bf_tune_query(plan, bf.BF_FP32, 27)[0] != (1, 1, 1, 0)   # other CU count: ignored
+    assert bf.bf_tune_query(plan, bf.BF_FP32, 36) == default4
+    bf.bf_tune_save(plan, path)
+    text = path.read_text()
+    assert "gfx942 304" in text and f"{arch} {cus + 1}" in text
+    plan2 = bf.bf_plan_create(b.W, bf.BF_PREC_ALL)
+    bf.bf_tune_load(plan2, path)
+    assert bf.bf_tune_query(plan2, bf.BF_FP32, 20) == ((2, 1, 0, 1), 12.5)
+    db = DeviceBatch(b)
+    db.apply(plan2, bf.BF_FP32)
+    err, _ = rel_errors(b, db.result())
+    assert np.max(err) <= FP32_TOL
+    bad = tmp_path / "bad.txt"
+    bad.write_text(f"{arch} {cus} 0 2 9 0 0 0 1.0\n")   # schedule 9 does not exist
+    with pytest.raises(bf.BfError) as ei:
+        bf.bf_tune_load(plan2, bad)
+    assert ei.value.status == bf.BF_ERR_INVALID
+    assert bf.bf_tune_query(plan2, bf.BF_FP32, 20) == ((2, 1, 0, 1), 12.5)
+    plan.close()
+    plan2.close()
