@@ -25,7 +25,7 @@ BF_ERR_BUSY, BF_ERR_TIMEOUT, BF_ERR_UNSUPPORTED = -4, -5, -6
 BF_FP32, BF_FP16, BF_BF16, BF_FP16X2, BF_BF16X2, BF_FP32_3M = 0, 1, 2, 3, 4, 5
 PREC_NAMES = {BF_FP32: "fp32", BF_FP16: "fp16", BF_BF16: "bf16",
               BF_FP16X2: "fp16x2", BF_BF16X2: "bf16x2", BF_FP32_3M: "fp32_3m"}
-PREC_ALL = 0x3F
+PREC_ALL = BF_PREC_ALL = 0x3F
 
 
 def BF_PREC_BIT(p: int) -> int:

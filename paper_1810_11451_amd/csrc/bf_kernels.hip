@@ -439,14 +439,19 @@ __device__ __forceinline__ void contract_fp32_reload(const f2v *__restrict__ lds
 // Operands of pool entry w for antenna half mt: 3 registers per pair, read
 // from the plan's component planes; entries past `pairs` repeat the last
 // one and are never used.
+// `need` (>= 1) pairs are used by the product; loads of later pairs repeat
+// the last needed one, so they hit in cache instead of fetching W columns
+// the product does not use.
 __device__ __forceinline__ void load_a_3m(f3v (&a)[kPairsMax], const float *__restrict__ apool,
-                                          int w, int a_w_stride, int pairs, int mt, int lane)
+                                          int w, int a_w_stride, int pairs, int mt, int lane,
+                                          int need)
 {
     typedef __attribute__((address_space(1))) const float g_cf;
     const g_cf *ap = (const g_cf *)(apool + (size_t)w * a_w_stride + (size_t)mt * pairs * 192 + lane);
+    const int last = min(pairs, need) - 1;
 #pragma unroll
     for (int p = 0; p < kPairsMax; ++p) {
-        const int q = min(p, pairs - 1);
+        const int q = min(p, last);
         a[p] = f3v{ap[(3 * q) * 64], ap[(3 * q + 1) * 64], ap[(3 * q + 2) * 64]};
     }
 }
@@ -611,7 +616,7 @@ __global__ __launch_bounds__(kThreads) void apply_fp32_3m_single(BfHeader *__res
     SRegs<kVec16> sr;
     load_s<kVec16>(sr, d.f > 0 ? d.S : sink, d.f);
     if (pairs > 0)
-        load_a_3m(a, apool, d.w_id, a_w_stride, pairs, wave >> 1, lane);
+        load_a_3m(a, apool, d.w_id, a_w_stride, pairs, wave >> 1, lane, max((d.f + 1) >> 1, 1));
     put_s<kVec16>(lds_s, sr, d.f);
     __syncthreads();
     contract_stage_3m(lds_s, a, d.f, wave, lane, tile);
@@ -848,16 +853,30 @@ __device__ __forceinline__ void p_load_s(PRegs<kProd, kW> &r, const float2 *__re
         r.v[u] = __builtin_nontemporal_load(src + min(ptid + u * 64 * kProd, last));
 }
 
-// W operands (L2-resident pool: plain loads, no streaming hint).
+// W operands (L2-resident pool: plain loads, no streaming hint).  Each
+// antenna half holds pairs * 48 chunks; only the first `need` (>= 1) pairs
+// of each half are used by the product, and chunks of later pairs
+// load the last used chunk of their half again (a cache hit; the LDS slots
+// they fill feed no product).
 template <int kProd>
 __device__ __forceinline__ void p_load_w(PRegs<kProd, true> &r, const float *__restrict__ wsrc, int pairs,
-                                         int ptid)
+                                         int need, int ptid)
 {
     g_cf4v *src = (g_cf4v *)wsrc;
-    const int last = pairs * 96 - 1;
+    const int half = pairs * 48;
+    if (need >= pairs) {   // uniform: every pair is used
 #pragma unroll
-    for (int u = 0; u < PRegs<kProd, true>::kNW; ++u)
-        r.w[u] = src[min(ptid + u * 64 * kProd, last)];
+        for (int u = 0; u < PRegs<kProd, true>::kNW; ++u)
+            r.w[u] = src[min(ptid + u * 64 * kProd, 2 * half - 1)];
+        return;
+    }
+    const int used = need * 48 - 1;
+#pragma unroll
+    for (int u = 0; u < PRegs<kProd, true>::kNW; ++u) {
+        const int c = min(ptid + u * 64 * kProd, 2 * half - 1);
+        const int h = c >= half ? half : 0;
+        r.w[u] = src[h + min(c - h, used)];
+    }
 }
 
 template <int kProd>
@@ -920,7 +939,8 @@ __device__ __forceinline__ void p_load_item(PRegs<kProd, k3M> &r, const BfItem &
 {
     p_load_s<kProd, k3M>(r, real && d.f > 0 ? d.S : sink, real ? d.f : 0, ptid);
     if constexpr (k3M)
-        p_load_w<kProd>(r, static_cast<const float *>(apool) + (size_t)d.w_id * a_w_stride, pairs, ptid);
+        p_load_w<kProd>(r, static_cast<const float *>(apool) + (size_t)d.w_id * a_w_stride, pairs,
+                        max((d.f + 1) >> 1, 1), ptid);
 }
 
 template <int kProd, bool k3M>
