@@ -181,7 +181,9 @@ typedef struct {
     int32_t schedule;      /* 0: one product per workgroup; 1: persistent, atomic claim;
                               2: persistent, static share per XCD, next S prefetched;
                               3: persistent, wave-specialised (matrix-core waves and
-                              data-movement waves), FP32 forms only */
+                              data-movement waves); needs every S 16-byte aligned
+                              (other batches run schedule 0 for the three-product
+                              form, 2 otherwise) */
     int32_t wg_per_cu;     /* persistent grid = wg_per_cu * CU count (ignored for 0) */
     int32_t order;         /* 0: as given; 1: longest f first, then by W id */
     int32_t store;         /* schedules 0 and 2: 0 = lanes write their accumulators
@@ -191,7 +193,9 @@ typedef struct {
                               workgroup and products prefetched in their
                               registers, 0 = (4, 1), 1 = (8, 1), 2 = (8, 2),
                               3 = (8, 3), 4 = (12, 1), 5 = (12, 2); the
-                              three-product form uses at most 8 producers */
+                              three-product form uses at most 8 producers; the
+                              16-bit forms prefetch at least 2 products, and 3
+                              only with 8 producers */
 } bf_variant;
 
 bf_status bf_set_variant(bf_plan plan, bf_prec prec, int32_t f_bucket, const bf_variant *v);

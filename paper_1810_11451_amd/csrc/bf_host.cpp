@@ -86,9 +86,10 @@ static void release_slot(StagingSlot &s)
     s = StagingSlot{};
 }
 
-// Defaults measured on MI355X: full-width batches (mean f 36) run persistent
-// workgroups (FP32 forms wave-specialised), batches of mixed or small f one
-// product per workgroup, all in the order given.
+// Defaults measured on MI355X: full-width batches (mean f 36) run the
+// wave-specialised schedule, so do the 16-bit forms' batches of mixed f;
+// the FP32 forms' mixed batches and every batch of small mean f run one
+// product per workgroup; all in the order given.
 static bf_status default_variants(bf_plan p)
 {
     for (int pr = 0; pr < kPrecCount; ++pr)
@@ -100,10 +101,10 @@ static bf_status default_variants(bf_plan p)
                 v = bf_variant{3, 0, 0, 1};   // wave-specialised, 8 producers, depth 1, as given
             else if (full && fp32)
                 v = bf_variant{3, 0, 0, 5};   // wave-specialised, 12 producers, depth 2, as given
-            else if (full)
-                v = bf_variant{2, 2, 0, 0};   // 16-bit forms: streaming, 2 per CU
+            else if (!fp32 && b > 0)
+                v = bf_variant{3, 0, 0, 4};   // 16-bit forms: wave-specialised, 12 producers
             else
-                v = bf_variant{0, 0, 0, 0};   // mixed or small f: one per workgroup
+                v = bf_variant{0, 0, 0, 0};   // one per workgroup
             p->table[pr][b] = v;
         }
     return BF_OK;
@@ -209,9 +210,12 @@ extern "C" bf_status bf_plan_create(bf_plan *out, const void *w_pool, int32_t n_
             e = hipMalloc(&p->lp_lo[ty], bytes);
         if (e == hipSuccess)
             e = hipMalloc(&p->lp_exp[ty], sizeof(int) * 2 * (size_t)n_w);
+        p->lp_wc_stride[ty] = bfk::lp_wc_stride(want_lo);
+        if (e == hipSuccess)
+            e = hipMalloc(&p->lp_wc[ty], sizeof(uint32_t) * 2 * (size_t)n_w * p->lp_wc_stride[ty]);
         if (e == hipSuccess && w_dev)
             e = bfk::launch_w_transform_lp(w_dev, n_w, f_max, ty == 1, p->lp_hi[ty], p->lp_lo[ty],
-                                           p->lp_exp[ty], st);
+                                           p->lp_exp[ty], p->lp_wc[ty], st);
         if (e != hipSuccess) {
             if (w_dev)
                 (void)hipFree(w_dev);
@@ -247,6 +251,8 @@ extern "C" bf_status bf_plan_destroy(bf_plan p)
             (void)hipFree(p->lp_lo[ty]);
         if (p->lp_exp[ty])
             (void)hipFree(p->lp_exp[ty]);
+        if (p->lp_wc[ty])
+            (void)hipFree(p->lp_wc[ty]);
     }
     if (p->update_stream) {
         (void)hipStreamSynchronize(p->update_stream);
@@ -350,7 +356,8 @@ extern "C" bf_status bf_plan_update(bf_plan p, int32_t w_id, const void *w, void
         void *lo = p->lp_lo[ty] ? static_cast<char *>(p->lp_lo[ty]) + off : nullptr;
         e = bfk::launch_w_transform_lp(p->w_stage, 1, p->f_max, ty == 1,
                                        static_cast<char *>(p->lp_hi[ty]) + off, lo,
-                                       p->lp_exp[ty] + slot, p->update_stream);
+                                       p->lp_exp[ty] + slot, p->lp_wc[ty] + slot * p->lp_wc_stride[ty],
+                                       p->update_stream);
     }
     if (e == hipSuccess)
         e = hipEventRecord(p->updated, p->update_stream);
@@ -430,13 +437,16 @@ bfk::LaunchCfg choose_launch(bf_plan p, bf_prec prec, int n, int max_f, bool vec
     bfk::LaunchCfg cfg{};
     cfg.prec = prec;
     cfg.schedule = v.schedule;
+    const bool lp = prec != BF_FP32 && prec != BF_FP32_3M;
     if (prec == BF_FP32_3M && cfg.schedule != 0)
         cfg.schedule = 3;   // the three-product form runs one-per-workgroup or wave-specialised
-    else if (prec != BF_FP32 && prec != BF_FP32_3M && (cfg.schedule == 1 || cfg.schedule == 3))
-        cfg.schedule = 2;   // the 16-bit forms have no claim or wave-specialised schedule
+    else if (lp && cfg.schedule == 1)
+        cfg.schedule = 2;   // the 16-bit forms have no claim schedule
     cfg.vec16 = vec16;
     if (cfg.schedule == 3 && !vec16)   // its producers move S in 16-byte chunks only
         cfg.schedule = prec == BF_FP32_3M ? 0 : 2;
+    if (cfg.schedule == 3 && lp && p->f_max < 1)   // no 16-bit operands to load
+        cfg.schedule = 2;
     cfg.stage = cfg.schedule == 3 || prec == BF_FP32_3M || (v.store >= 1 && cfg.schedule != 1);
     // For schedule 3 the store field selects producer waves and prefetch
     // depth: 0 -> (4, 1), 1 -> (8, 1), 2 -> (8, 2), 3 -> (8, 3), 4 -> (12, 1),
@@ -599,6 +609,8 @@ hipError_t launch_for_plan(bf_plan p, const bfk::LaunchCfg &cfg, BfHeader *blk, 
     pd.lp_exp = p->lp_exp[ty];
     pd.lp_stride = (int)p->lp_stride;
     pd.lp_chunks = bfk::lp_chunks(p->f_max);
+    pd.lp_wc = p->lp_wc[ty];
+    pd.lp_wc_stride = (int)p->lp_wc_stride[ty];
     return bfk::launch_apply(cfg, blk, n, pd, st);
 }
 
@@ -871,10 +883,9 @@ extern "C" bf_status bf_autotune(bf_plan p, int32_t batch, const int32_t *w_ids,
         for (int w : per_cu)
             for (int o = 0; o < 2; ++o)
                 cands.push_back(bf_variant{2, w, o, st});
-    if (prec == BF_FP32 || prec == BF_FP32_3M)
-        for (int o = 0; o < 2; ++o)
-            for (int st = 0; st < 6; ++st)
-                cands.push_back(bf_variant{3, 0, o, st});
+    for (int o = 0; o < 2; ++o)
+        for (int st = 0; st < 6; ++st)
+            cands.push_back(bf_variant{3, 0, o, st});
 
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)

@@ -45,6 +45,8 @@ struct bf_plan_s {
     void *lp_hi[2] = {nullptr, nullptr};
     void *lp_lo[2] = {nullptr, nullptr};
     int *lp_exp[2] = {nullptr, nullptr};
+    uint32_t *lp_wc[2] = {nullptr, nullptr};   // compact 16-bit W (wave-specialised schedule)
+    size_t lp_wc_stride[2] = {0, 0};           // dwords per W
     size_t lp_stride = 0;       // 16-byte units per W
 
     // Pool updates.  Every entry has two device slots, w and w + n_w, in each

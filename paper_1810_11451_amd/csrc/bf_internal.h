@@ -63,19 +63,28 @@ struct PlanDev {
     const int *lp_exp;        // per-W power-of-two exponent of the 16-bit operands
     int lp_stride;            // 16-byte units per W
     int lp_chunks;            // ceil(f_max / 8)
+    const uint32_t *lp_wc;    // 16-bit forms, compact: parts x 64 antennas x 40 flows dwords per W
+    int lp_wc_stride;         // dwords per W
 };
 
 constexpr int kLpFlows = 8;   // flows per 16-bit matrix-core step (K = 16 real)
 inline int lp_chunks(int f_max) { return (f_max + kLpFlows - 1) / kLpFlows; }
 inline size_t lp_w_units(int f_max) { return (size_t)kWaves * lp_chunks(f_max) * 64; }
+// Compact 16-bit W (wave-specialised schedule): per part (hi, then lo for
+// the split forms) one dword per (antenna, flow < 40), (re, im) codes of the
+// scaled entry, flows past f_max zero.
+constexpr int kLpWcFlows = 40;
+constexpr size_t kLpWcPart = (size_t)BF_M * kLpWcFlows;
+inline size_t lp_wc_stride(bool split) { return (split ? 2 : 1) * kLpWcPart; }
 
 hipError_t launch_w_transform_fp32(const float2 *w_dev, int n_w, int f_max, float2 *a_out,
                                    int pairs, hipStream_t st);
 hipError_t launch_w_transform_3m(const float2 *w_dev, int n_w, int f_max, float *a_out,
                                  int pairs, hipStream_t st);
-// bf16 selects BF16 (else FP16); lo may be null (plain forms only).
+// bf16 selects BF16 (else FP16); lo may be null (plain forms only); wc
+// (compact layout, lp_wc_stride(lo != null) dwords per W) may be null.
 hipError_t launch_w_transform_lp(const float2 *w_dev, int n_w, int f_max, bool bf16, void *hi,
-                                 void *lo, int *w_exp, hipStream_t st);
+                                 void *lo, int *w_exp, uint32_t *wc, hipStream_t st);
 
 struct LaunchCfg {
     int prec;        // bf_prec

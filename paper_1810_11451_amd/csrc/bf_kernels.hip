@@ -829,6 +829,24 @@ __global__ __launch_bounds__(kThreads) void apply_fp32_stream(BfHeader *__restri
 // accumulators, so they come through LDS, copied once per workgroup instead
 // of once per wave.
 
+// Exponent e with 2^e <= m < 2^(e+1) for the bit pattern m of a positive
+// float (0 for m == 0), clamped so that 2^-e is a normal float.
+__device__ __forceinline__ int exp_of_bits(uint32_t m)
+{
+    if (m == 0)
+        return 0;
+    const int e = (int)(m >> 23) - 127;
+    return e < -126 ? -126 : (e > 126 ? 126 : e);
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    return v;
+}
+
 // Producer-side staging over kProd waves, in 16-byte chunks with clamped
 // indices: S of one product and, for the three-product form (kW), the
 // operands of its W (the plan's 2 x pairs x 3 x 64 floats, 96 pairs chunks).
@@ -943,13 +961,39 @@ __device__ __forceinline__ void p_load_item(PRegs<kProd, k3M> &r, const BfItem &
                         max((d.f + 1) >> 1, 1), ptid);
 }
 
-template <int kProd, bool k3M>
+// Largest |Re|, |Im| (as float bits) over the valid chunks of a staged S.
+template <int kProd, bool kW>
+__device__ __forceinline__ uint32_t p_absmax(const PRegs<kProd, kW> &r, int f, int ptid)
+{
+    const int chunks = f * (kB / 2);
+    uint32_t m = 0;
+#pragma unroll
+    for (int u = 0; u < PRegs<kProd, kW>::kN; ++u) {
+        if (ptid + u * 64 * kProd < chunks) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                m = max(m, __float_as_uint(r.v[u][e]) & 0x7fffffffu);
+        }
+    }
+    return m;
+}
+
+// Puts one product's data into LDS.  kMax (16-bit forms): each producer wave
+// also leaves the largest |Re|, |Im| of its part of S in smax[wave], from
+// which the consumers take the product's power-of-two scale.
+template <int kProd, bool k3M, bool kMax>
 __device__ __forceinline__ void p_put_item(f2v *__restrict__ s_lds, float *__restrict__ a_lds,
-                                           const PRegs<kProd, k3M> &r, int f, int pairs, int ptid)
+                                           uint32_t *__restrict__ smax, const PRegs<kProd, k3M> &r,
+                                           int f, int pairs, int ptid)
 {
     p_put_s<kProd, k3M>(s_lds, r, f, ptid);
     if constexpr (k3M)
         p_put_w<kProd>(a_lds, r, pairs, ptid);
+    if constexpr (kMax) {
+        const uint32_t m = wave_max_u32(p_absmax<kProd, k3M>(r, f, ptid));
+        if ((ptid & 63) == 0)
+            smax[ptid >> 6] = m;
+    }
 }
 
 // Staged W operands of the workgroup (three-product form only).
@@ -962,25 +1006,222 @@ struct WBuf<false> {
     float v[2][1];
 };
 
+// LDS shared by the two roles of the wave-specialised kernels: S of two
+// products, R of two products, the three-product form's W operands and the
+// 16-bit forms' per-wave S maxima (kProd entries per product).  The member
+// order sets which buffers the 16-bit offset field of LDS instructions can
+// reach from one base register; the orders below are the ones that keep
+// each form's kernel free of register spills.
+template <bool k3M, int kProd>
+struct WsLds {
+    alignas(16) f2v s_buf[2][kFMax * kLdsCols];
+    alignas(16) f2v r_buf[2][kM * kB];
+    alignas(16) WBuf<k3M> a_buf;
+    alignas(16) uint32_t smax[2][kProd];
+};
+template <int kProd>
+struct WsLds<true, kProd> {
+    alignas(16) f2v r_buf[2][kM * kB];
+    alignas(16) f2v s_buf[2][kFMax * kLdsCols];
+    alignas(16) WBuf<true> a_buf;
+    alignas(16) uint32_t smax[2][kProd];
+};
+
 // One producer iteration t >= kLag: R(t - kLag) out (the consumers staged it
 // by the end of iteration t - 1), the data of product t+1 into LDS from
 // register set kPut, the loads for product t+1+kDepth into that set.  Past
 // the end of the share the descriptor index is clamped and the S loads read
 // the sink, so every memory instruction is unconditional; a put past the
 // end fills LDS buffers nobody reads any more.
-template <int kProd, int kDepth, int kPut, bool k3M, int kLag>
+template <int kProd, int kDepth, int kPut, bool k3M, bool kMax, int kLag>
 __device__ __forceinline__ void ws_produce_step(PRegs<kProd, k3M> (&sr)[kDepth], c_item *my, int stride,
-                                                int t, int n_my, float2 *sink,
-                                                f2v (*s_buf)[kFMax * kLdsCols], WBuf<k3M> &a_buf,
-                                                const f2v (*r_buf)[kM * kB], const void *apool,
-                                                int a_w_stride, int pairs, int ptid)
+                                                int t, int n_my, float2 *sink, WsLds<k3M, kProd> &L,
+                                                const void *apool, int a_w_stride, int pairs, int ptid)
 {
-    p_store_r<kProd>(item_at(my, t - kLag, stride).R, r_buf[(t - kLag) & 1], ptid);
+    p_store_r<kProd>(item_at(my, t - kLag, stride).R, L.r_buf[(t - kLag) & 1], ptid);
     const BfItem d1 = item_at(my, min(t + 1, n_my - 1), stride);
-    p_put_item<kProd, k3M>(s_buf[(t + 1) & 1], a_buf.v[(t + 1) & 1], sr[kPut], d1.f, pairs, ptid);
+    p_put_item<kProd, k3M, kMax>(L.s_buf[(t + 1) & 1], L.a_buf.v[(t + 1) & 1], L.smax[(t + 1) & 1],
+                                 sr[kPut], d1.f, pairs, ptid);
     const int tn = t + 1 + kDepth;
     const BfItem dn = item_at(my, min(tn, n_my - 1), stride);
     p_load_item<kProd, k3M>(sr[kPut], dn, tn < n_my, sink, apool, a_w_stride, pairs, ptid);
+}
+
+// The producer role of the wave-specialised kernels (threads 64 kWaves ..):
+// product 0 straight to LDS, products u = 1..kDepth into register set
+// u % kDepth, then one iteration per barrier of the consumers.  The
+// consumers stage R(t) during iteration t (four-product and 16-bit forms)
+// or t + 1 (three-product form, epilogue folded into the next chain), so
+// iteration t writes R(t - kLag).
+template <int kProd, int kDepth, bool k3M, bool kMax>
+__device__ __forceinline__ void ws_producer(c_item *my, int stride, int n_my, float2 *sink,
+                                            WsLds<k3M, kProd> &L, const void *apool, int a_w_stride,
+                                            int pairs)
+{
+    constexpr int kLag = k3M ? 2 : 1;
+    const int ptid = threadIdx.x - 64 * kWaves;
+    PRegs<kProd, k3M> sr[kDepth];
+    {
+        const BfItem d0 = item_at(my, 0, stride);
+        p_load_item<kProd, k3M>(sr[0], d0, true, sink, apool, a_w_stride, pairs, ptid);
+        p_put_item<kProd, k3M, kMax>(L.s_buf[0], L.a_buf.v[0], L.smax[0], sr[0], d0.f, pairs, ptid);
+    }
+    // Each load group is preceded by as many sink stores as an iteration
+    // issues R stores, and so is product 0, which has no R to write: the
+    // outstanding memory operations at the loop's entry then follow the
+    // same pattern as at its back edge, and the compiler's wait before
+    // each put counts only the loads that put needs.
+    const int plane = ptid & 63;
+#pragma unroll
+    for (int u = 1; u <= kDepth; ++u) {
+        prime_store_count<kPStoreRounds<kProd>>(sink, plane);
+        const BfItem d = item_at(my, min(u, n_my - 1), stride);
+        p_load_item<kProd, k3M>(sr[u % kDepth], d, u < n_my, sink, apool, a_w_stride, pairs, ptid);
+    }
+    __syncthreads();
+    // The first kLag iterations have no R to write and issue sink stores
+    // instead.
+#pragma unroll
+    for (int t0 = 0; t0 < kLag; ++t0) {
+        prime_store_count<kPStoreRounds<kProd>>(sink, plane);
+        const BfItem d1 = item_at(my, min(t0 + 1, n_my - 1), stride);
+        p_put_item<kProd, k3M, kMax>(L.s_buf[(t0 + 1) & 1], L.a_buf.v[(t0 + 1) & 1], L.smax[(t0 + 1) & 1],
+                                     sr[(t0 + 1) % kDepth], d1.f, pairs, ptid);
+        const int tn = t0 + 1 + kDepth;
+        const BfItem dn = item_at(my, min(tn, n_my - 1), stride);
+        p_load_item<kProd, k3M>(sr[(t0 + 1) % kDepth], dn, tn < n_my, sink, apool, a_w_stride, pairs,
+                                ptid);
+        __syncthreads();
+    }
+    // Iterations kLag .. n_my + kLag - 2 in groups of kDepth, so that every
+    // register set index is a constant: iteration t puts product t+1 from
+    // set (t+1) % kDepth.  The loop has a single exit at its end (a break
+    // in the middle becomes a flow block inside the loop, whose pessimistic
+    // memory-count state would then reach the loop's first put); the
+    // remaining iterations follow it.
+    static_assert(kDepth >= 1 && kDepth <= 3, "prefetch depth");
+    const int groups = (n_my - 1) / kDepth;
+    const int rest = (n_my - 1) - groups * kDepth;
+    constexpr int kP0 = (kLag + 1) % kDepth, kP1 = (kLag + 2) % kDepth, kP2 = (kLag + 3) % kDepth;
+    int t = kLag;
+    for (int g = 0; g < groups; ++g) {
+        ws_produce_step<kProd, kDepth, kP0, k3M, kMax, kLag>(sr, my, stride, t, n_my, sink, L, apool,
+                                                             a_w_stride, pairs, ptid);
+        __syncthreads();
+        if constexpr (kDepth >= 2) {
+            ws_produce_step<kProd, kDepth, kP1, k3M, kMax, kLag>(sr, my, stride, t + 1, n_my, sink, L,
+                                                                 apool, a_w_stride, pairs, ptid);
+            __syncthreads();
+        }
+        if constexpr (kDepth >= 3) {
+            ws_produce_step<kProd, kDepth, kP2, k3M, kMax, kLag>(sr, my, stride, t + 2, n_my, sink, L,
+                                                                 apool, a_w_stride, pairs, ptid);
+            __syncthreads();
+        }
+        t += kDepth;
+    }
+    if constexpr (kDepth >= 2) {
+        if (rest >= 1) {
+            ws_produce_step<kProd, kDepth, kP0, k3M, kMax, kLag>(sr, my, stride, t, n_my, sink, L, apool,
+                                                                 a_w_stride, pairs, ptid);
+            __syncthreads();
+        }
+    }
+    if constexpr (kDepth >= 3) {
+        if (rest >= 2) {
+            ws_produce_step<kProd, kDepth, kP1, k3M, kMax, kLag>(sr, my, stride, t + 1, n_my, sink, L,
+                                                                 apool, a_w_stride, pairs, ptid);
+            __syncthreads();
+        }
+    }
+    p_store_r<kProd>(item_at(my, n_my - 1, stride).R, L.r_buf[(n_my - 1) & 1], ptid);
+}
+
+// The share of a workgroup of the wave-specialised kernels: the nb
+// workgroups of an XCD take its items round-robin (item lo + j + k nb is
+// product k of workgroup j), so at any moment they work on one contiguous
+// window of the item list: R is written as one advancing front per XCD,
+// which keeps HBM pages open far better than nb separate fronts would.
+// Returns the number of products; *start and *stride locate them.
+__device__ __forceinline__ int ws_share(int n_items, int *start, int *stride)
+{
+    const int G = gridDim.x;
+    const int X = G < 8 ? G : 8;
+    const int x = blockIdx.x % X;
+    const int j = blockIdx.x / X;
+    const int nb = G / X + (x < G % X ? 1 : 0);
+    const int q = n_items / X, r = n_items % X;
+    const int lo = x * q + (x < r ? x : r);
+    const int cnt = q + (x < r ? 1 : 0);
+    *start = lo + j;
+    *stride = nb;
+    return j < cnt ? (cnt - j + nb - 1) / nb : 0;
+}
+
+// The consumer role of apply_fp32_ws (threads 0 .. 64 kWaves - 1).
+template <bool k3M, int kProd>
+__device__ __forceinline__ void ws_fp32_consumer(c_item *my, int stride, int n_my, WsLds<k3M, kProd> &L,
+                                                 const void *apool, int a_w_stride, int pairs, int wave,
+                                                 int lane)
+{
+    int f = item_at(my, 0, stride).f;
+    if constexpr (k3M) {
+        // Product k's chain runs with product k - 1's epilogue folded in
+        // (two accumulator sets, A for even k, B for odd k); the last
+        // product's epilogue gets an iteration of its own, so the R of
+        // product k is staged during iteration k + 1 and drained by the
+        // producers in iteration k + 2.
+        floatx16 a1, a2, a3, b1, b2, b3;
+        __syncthreads();
+        chain_3m_lds<false>(L.s_buf[0], L.a_buf.v[0], pairs, f, wave, lane, a1, a2, a3, a1, a2, a3,
+                            nullptr);
+        __builtin_amdgcn_sched_barrier(0);
+        f = item_at(my, min(1, n_my - 1), stride).f;
+        __syncthreads();
+        int k = 1;
+        while (true) {
+            if (k >= n_my) {
+                stage_3m(a1, a2, a3, wave, lane, L.r_buf[(k - 1) & 1]);
+                __syncthreads();
+                break;
+            }
+            chain_3m_lds<true>(L.s_buf[k & 1], L.a_buf.v[k & 1], pairs, f, wave, lane, b1, b2, b3, a1,
+                               a2, a3, L.r_buf[(k - 1) & 1]);
+            __builtin_amdgcn_sched_barrier(0);
+            f = item_at(my, min(k + 1, n_my - 1), stride).f;
+            __syncthreads();
+            ++k;
+            if (k >= n_my) {
+                stage_3m(b1, b2, b3, wave, lane, L.r_buf[(k - 1) & 1]);
+                __syncthreads();
+                break;
+            }
+            chain_3m_lds<true>(L.s_buf[k & 1], L.a_buf.v[k & 1], pairs, f, wave, lane, a1, a2, a3, b1,
+                               b2, b3, L.r_buf[(k - 1) & 1]);
+            __builtin_amdgcn_sched_barrier(0);
+            f = item_at(my, min(k + 1, n_my - 1), stride).f;
+            __syncthreads();
+            ++k;
+        }
+    } else {
+        // W of product t is in registers when t starts; the chain of t
+        // reloads them with W of t + 1 (the last product reloads its own).
+        f2v a[kPairsMax];
+        load_a_fp32(a, static_cast<const float2 *>(apool), item_at(my, 0, stride).w_id, a_w_stride,
+                    pairs, wave, lane);
+        int w_next = item_at(my, min(1, n_my - 1), stride).w_id;
+        __syncthreads();
+        for (int t = 0; t < n_my; ++t) {
+            floatx16 acc0, acc1;
+            contract_fp32_reload(L.s_buf[t & 1], a, f, lane, acc0, acc1,
+                                 static_cast<const float2 *>(apool), w_next, a_w_stride, pairs, wave);
+            stage_acc(L.r_buf[t & 1] + wave * kWaveOut, lane, acc0, acc1);
+            __builtin_amdgcn_sched_barrier(0);
+            f = item_at(my, min(t + 1, n_my - 1), stride).f;
+            w_next = item_at(my, min(t + 2, n_my - 1), stride).w_id;
+            __syncthreads();
+        }
+    }
 }
 
 // kSched 3: wave-specialised persistent kernel (FP32 forms).  S must be
@@ -990,29 +1231,12 @@ __global__ __launch_bounds__(64 * (kWaves + kProd)) void apply_fp32_ws(
     BfHeader *__restrict__ blk, const BfItem *__restrict__ items, int n_items,
     const void *__restrict__ apool, int a_w_stride, int pairs)
 {
-    __shared__ f2v s_buf[2][kFMax * kLdsCols];
-    __shared__ f2v r_buf[2][kM * kB];
-    __shared__ WBuf<k3M> a_buf;
+    __shared__ WsLds<k3M, kProd> L;
     const int wave8 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     float2 *sink = sink_of(blk);
-
-    const int G = gridDim.x;
-    const int X = G < 8 ? G : 8;
-    const int x = blockIdx.x % X;
-    const int j = blockIdx.x / X;
-    const int nb = G / X + (x < G % X ? 1 : 0);
-    const int q = n_items / X, r = n_items % X;
-    const int lo = x * q + (x < r ? x : r);
-    const int cnt = q + (x < r ? 1 : 0);
-    // The nb workgroups of an XCD take its items round-robin (item lo + j +
-    // k nb is product k of workgroup j), so at any moment they work on one
-    // contiguous window of the item list: R is written as one advancing
-    // front per XCD, which keeps HBM pages open far better than nb separate
-    // fronts would.
-    const int start = lo + j;
-    const int stride = nb;
-    const int n_my = j < cnt ? (cnt - j + nb - 1) / nb : 0;
+    int start, stride;
+    const int n_my = ws_share(n_items, &start, &stride);
     if (n_my <= 0)
         return;
 
@@ -1021,147 +1245,9 @@ __global__ __launch_bounds__(64 * (kWaves + kProd)) void apply_fp32_ws(
         // consumer.  f of product t is read at the end of product t - 1,
         // where the barrier waits for it: a wait for a scalar read also waits
         // for every LDS read, so it must not fall among the chain's.
-        const int wave = wave8;
-        int f = item_at(my, 0, stride).f;
-        if constexpr (k3M) {
-            // Product k's chain runs with product k - 1's epilogue folded in
-            // (two accumulator sets, A for even k, B for odd k); the last
-            // product's epilogue gets an iteration of its own, so the R of
-            // product k is staged during iteration k + 1 and drained by the
-            // producers in iteration k + 2.
-            floatx16 a1, a2, a3, b1, b2, b3;
-            __syncthreads();
-            chain_3m_lds<false>(s_buf[0], a_buf.v[0], pairs, f, wave, lane, a1, a2, a3, a1, a2, a3,
-                                nullptr);
-            __builtin_amdgcn_sched_barrier(0);
-            f = item_at(my, min(1, n_my - 1), stride).f;
-            __syncthreads();
-            int k = 1;
-            while (true) {
-                if (k >= n_my) {
-                    stage_3m(a1, a2, a3, wave, lane, r_buf[(k - 1) & 1]);
-                    __syncthreads();
-                    break;
-                }
-                chain_3m_lds<true>(s_buf[k & 1], a_buf.v[k & 1], pairs, f, wave, lane, b1, b2, b3, a1,
-                                   a2, a3, r_buf[(k - 1) & 1]);
-                __builtin_amdgcn_sched_barrier(0);
-                f = item_at(my, min(k + 1, n_my - 1), stride).f;
-                __syncthreads();
-                ++k;
-                if (k >= n_my) {
-                    stage_3m(b1, b2, b3, wave, lane, r_buf[(k - 1) & 1]);
-                    __syncthreads();
-                    break;
-                }
-                chain_3m_lds<true>(s_buf[k & 1], a_buf.v[k & 1], pairs, f, wave, lane, a1, a2, a3, b1,
-                                   b2, b3, r_buf[(k - 1) & 1]);
-                __builtin_amdgcn_sched_barrier(0);
-                f = item_at(my, min(k + 1, n_my - 1), stride).f;
-                __syncthreads();
-                ++k;
-            }
-        } else {
-            // W of product t is in registers when t starts; the chain of t
-            // reloads them with W of t + 1 (the last product reloads its own).
-            f2v a[kPairsMax];
-            load_a_fp32(a, static_cast<const float2 *>(apool), item_at(my, 0, stride).w_id, a_w_stride,
-                        pairs, wave, lane);
-            int w_next = item_at(my, min(1, n_my - 1), stride).w_id;
-            __syncthreads();
-            for (int t = 0; t < n_my; ++t) {
-                floatx16 acc0, acc1;
-                contract_fp32_reload(s_buf[t & 1], a, f, lane, acc0, acc1,
-                                     static_cast<const float2 *>(apool), w_next, a_w_stride, pairs, wave);
-                stage_acc(r_buf[t & 1] + wave * kWaveOut, lane, acc0, acc1);
-                __builtin_amdgcn_sched_barrier(0);
-                f = item_at(my, min(t + 1, n_my - 1), stride).f;
-                w_next = item_at(my, min(t + 2, n_my - 1), stride).w_id;
-                __syncthreads();
-            }
-        }
+        ws_fp32_consumer<k3M, kProd>(my, stride, n_my, L, apool, a_w_stride, pairs, wave8, lane);
     } else {
-        // producer: product 0 straight to LDS; products u = 1..kDepth into
-        // register set u % kDepth
-        const int ptid = threadIdx.x - 64 * kWaves;
-        PRegs<kProd, k3M> sr[kDepth];
-        {
-            const BfItem d0 = item_at(my, 0, stride);
-            p_load_item<kProd, k3M>(sr[0], d0, true, sink, apool, a_w_stride, pairs, ptid);
-            p_put_item<kProd, k3M>(s_buf[0], a_buf.v[0], sr[0], d0.f, pairs, ptid);
-        }
-        // Each load group is preceded by as many sink stores as an iteration
-        // issues R stores, and so is product 0, which has no R to write: the
-        // outstanding memory operations at the loop's entry then follow the
-        // same pattern as at its back edge, and the compiler's wait before
-        // each put counts only the loads that put needs.
-        const int plane = ptid & 63;
-#pragma unroll
-        for (int u = 1; u <= kDepth; ++u) {
-            prime_store_count<kPStoreRounds<kProd>>(sink, plane);
-            const BfItem d = item_at(my, min(u, n_my - 1), stride);
-            p_load_item<kProd, k3M>(sr[u % kDepth], d, u < n_my, sink, apool, a_w_stride, pairs, ptid);
-        }
-        __syncthreads();
-        // The consumers stage R(t) during iteration t (four-product form) or
-        // t + 1 (three-product form, epilogue folded into the next chain), so
-        // iteration t writes R(t - kLag).  The first kLag iterations have no R
-        // to write and issue sink stores instead.
-        constexpr int kLag = k3M ? 2 : 1;
-#pragma unroll
-        for (int t0 = 0; t0 < kLag; ++t0) {
-            prime_store_count<kPStoreRounds<kProd>>(sink, plane);
-            const BfItem d1 = item_at(my, min(t0 + 1, n_my - 1), stride);
-            p_put_item<kProd, k3M>(s_buf[(t0 + 1) & 1], a_buf.v[(t0 + 1) & 1], sr[(t0 + 1) % kDepth], d1.f,
-                                   pairs, ptid);
-            const int tn = t0 + 1 + kDepth;
-            const BfItem dn = item_at(my, min(tn, n_my - 1), stride);
-            p_load_item<kProd, k3M>(sr[(t0 + 1) % kDepth], dn, tn < n_my, sink, apool, a_w_stride, pairs,
-                                    ptid);
-            __syncthreads();
-        }
-        // Iterations kLag .. n_my + kLag - 2 in groups of kDepth, so that every
-        // register set index is a constant: iteration t puts product t+1 from
-        // set (t+1) % kDepth.  The loop has a single exit at its end (a break
-        // in the middle becomes a flow block inside the loop, whose pessimistic
-        // memory-count state would then reach the loop's first put); the
-        // remaining iterations follow it.
-        static_assert(kDepth >= 1 && kDepth <= 3, "prefetch depth");
-        const int groups = (n_my - 1) / kDepth;
-        const int rest = (n_my - 1) - groups * kDepth;
-        constexpr int kP0 = (kLag + 1) % kDepth, kP1 = (kLag + 2) % kDepth, kP2 = (kLag + 3) % kDepth;
-        int t = kLag;
-        for (int g = 0; g < groups; ++g) {
-            ws_produce_step<kProd, kDepth, kP0, k3M, kLag>(sr, my, stride, t, n_my, sink, s_buf, a_buf,
-                                                           r_buf, apool, a_w_stride, pairs, ptid);
-            __syncthreads();
-            if constexpr (kDepth >= 2) {
-                ws_produce_step<kProd, kDepth, kP1, k3M, kLag>(sr, my, stride, t + 1, n_my, sink, s_buf,
-                                                               a_buf, r_buf, apool, a_w_stride, pairs, ptid);
-                __syncthreads();
-            }
-            if constexpr (kDepth >= 3) {
-                ws_produce_step<kProd, kDepth, kP2, k3M, kLag>(sr, my, stride, t + 2, n_my, sink, s_buf,
-                                                               a_buf, r_buf, apool, a_w_stride, pairs, ptid);
-                __syncthreads();
-            }
-            t += kDepth;
-        }
-        if constexpr (kDepth >= 2) {
-            if (rest >= 1) {
-                ws_produce_step<kProd, kDepth, kP0, k3M, kLag>(sr, my, stride, t, n_my, sink, s_buf, a_buf,
-                                                               r_buf, apool, a_w_stride, pairs, ptid);
-                __syncthreads();
-            }
-        }
-        if constexpr (kDepth >= 3) {
-            if (rest >= 2) {
-                ws_produce_step<kProd, kDepth, kP1, k3M, kLag>(sr, my, stride, t + 1, n_my, sink, s_buf,
-                                                               a_buf, r_buf, apool, a_w_stride, pairs, ptid);
-                __syncthreads();
-            }
-        }
-        p_store_r<kProd>(item_at(my, n_my - 1, stride).R, r_buf[(n_my - 1) & 1], ptid);
+        ws_producer<kProd, kDepth, k3M, false>(my, stride, n_my, sink, L, apool, a_w_stride, pairs);
     }
 }
 
@@ -1197,6 +1283,7 @@ struct Lp;
 template <>
 struct Lp<false> {
     typedef _Float16 T;
+    typedef _Float16 T2 __attribute__((ext_vector_type(2)));
     static constexpr int kShift = 11;
     __device__ static floatx16 mfma(u4v a, u4v b, floatx16 c)
     {
@@ -1207,6 +1294,7 @@ struct Lp<false> {
 template <>
 struct Lp<true> {
     typedef __bf16 T;
+    typedef __bf16 T2 __attribute__((ext_vector_type(2)));
     static constexpr int kShift = 8;
     __device__ static floatx16 mfma(u4v a, u4v b, floatx16 c)
     {
@@ -1233,35 +1321,23 @@ __device__ __forceinline__ void split16(float x, unsigned short &hi, unsigned sh
     lo = to16<kBf16>((x - from16<kBf16>(hi)) * (float)(1 << Lp<kBf16>::kShift));
 }
 
-// Exponent e with 2^e <= m < 2^(e+1) for the bit pattern m of a positive
-// float (0 for m == 0), clamped so that 2^-e is a normal float.
-__device__ __forceinline__ int exp_of_bits(uint32_t m)
-{
-    if (m == 0)
-        return 0;
-    const int e = (int)(m >> 23) - 127;
-    return e < -126 ? -126 : (e > 126 ? 126 : e);
-}
-
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-        v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
-    return v;
-}
-
 // Plan time: one block per W.  Layout per W and part (hi, lo):
 // [kWaves][chunks][64 lanes][8 x 16-bit], slot s of lane l in step t being
 // real row m = l % 32 of the wave (antenna 16 wave + m / 2, c = m % 2) and
 // K index (flow 8t + 4(l / 32) + s / 2, part q = s % 2):
 //   (c, q) = (0, 0): Wr   (0, 1): -Wi   (1, 0): Wi   (1, 1): Wr.
+//
+// Compact layout (wc, when given): per part (hi, then lo if `lo` is given)
+// dword 40 i + k holds the (re, im) codes of entry (antenna i, flow k < 40)
+// of the scaled W, zero past f_max; the same codes as the operand layout,
+// whose -Wi entries are the negated (sign-flipped) codes.
 template <bool kBf16>
 __global__ __launch_bounds__(256) void w_transform_lp_kernel(const float2 *__restrict__ w, int f_max,
                                                              int chunks,
                                                              unsigned short *__restrict__ hi,
                                                              unsigned short *__restrict__ lo,
-                                                             int *__restrict__ w_exp)
+                                                             int *__restrict__ w_exp,
+                                                             uint32_t *__restrict__ wc)
 {
     __shared__ uint32_t wmax[kThreads / 64];
     const size_t wi = blockIdx.x;
@@ -1302,10 +1378,25 @@ __global__ __launch_bounds__(256) void w_transform_lp_kernel(const float2 *__res
         if (lo)
             lo[wi * per_w + idx] = l;
     }
+    if (!wc)
+        return;
+    const size_t part = (size_t)kM * kLpWcFlows;
+    uint32_t *dst = wc + wi * part * (lo ? 2 : 1);
+    for (int idx = threadIdx.x; idx < (int)part; idx += blockDim.x) {
+        const int i = idx / kLpWcFlows;
+        const int k = idx - i * kLpWcFlows;
+        const float2 v = k < f_max ? W[(size_t)i * f_max + k] : make_float2(0.f, 0.f);
+        unsigned short rh, rl, ih, il;
+        split16<kBf16>(v.x * scale, rh, rl);
+        split16<kBf16>(v.y * scale, ih, il);
+        dst[idx] = (uint32_t)rh | ((uint32_t)ih << 16);
+        if (lo)
+            dst[part + idx] = (uint32_t)rl | ((uint32_t)il << 16);
+    }
 }
 
 hipError_t launch_w_transform_lp(const float2 *w_dev, int n_w, int f_max, bool bf16, void *hi,
-                                 void *lo, int *w_exp, hipStream_t st)
+                                 void *lo, int *w_exp, uint32_t *wc, hipStream_t st)
 {
     const int chunks = lp_chunks(f_max);
     if (n_w <= 0 || chunks == 0)
@@ -1313,11 +1404,11 @@ hipError_t launch_w_transform_lp(const float2 *w_dev, int n_w, int f_max, bool b
     if (bf16)
         hipLaunchKernelGGL(w_transform_lp_kernel<true>, dim3(n_w), dim3(256), 0, st, w_dev, f_max,
                            chunks, static_cast<unsigned short *>(hi),
-                           static_cast<unsigned short *>(lo), w_exp);
+                           static_cast<unsigned short *>(lo), w_exp, wc);
     else
         hipLaunchKernelGGL(w_transform_lp_kernel<false>, dim3(n_w), dim3(256), 0, st, w_dev, f_max,
                            chunks, static_cast<unsigned short *>(hi),
-                           static_cast<unsigned short *>(lo), w_exp);
+                           static_cast<unsigned short *>(lo), w_exp, wc);
     return hipGetLastError();
 }
 
@@ -1469,6 +1560,338 @@ __device__ __forceinline__ void contract_lp(const uint32_t *__restrict__ bhi,
         }
         o0[r] = __builtin_amdgcn_ldexpf(v0, eo);
         o1[r] = __builtin_amdgcn_ldexpf(v1, eo);
+    }
+}
+
+// kSched 3 for the 16-bit forms: wave-specialised, with the producers
+// splitting S into 16-bit operands as they put it into LDS, so each value
+// is converted once and the consumers only read operands and issue
+// matrix-core steps.  The producers also stage each product's W, in the
+// plan's compact layout (one dword of (re, im) codes per entry and part),
+// from which the consumers form their operands; the consumers then issue
+// no memory loads at all.  A product's power-of-two scale must be known
+// before its conversion: the producers publish the largest |Re|, |Im| of
+// their part of product t + 2 in iteration t (smax, per wave) and convert
+// product t + 1 with the scale published for it in iteration t - 1.  This
+// needs S in producer registers two products ahead of its put (depth >= 2);
+// the loads of a product have kDepth - 1 iterations to arrive.
+//
+// LDS operand layout of S (per part, hi and lo): dword ((k / 4) 64 + c) 4 +
+// k % 4 holds (re, im) of flow k, column c as two 16-bit codes, so the
+// operand of lane (column n, half h) in chunk t is the 16 bytes at group
+// 2t + h.
+constexpr int kLpB = (kLpFlowsMax / 4) * 64 * 4;   // dwords per part: 40 flows x 64 columns
+constexpr int kLpWcP = kM * kLpWcFlows;            // dwords per part of a compact W
+static_assert(kLpWcFlows == kLpFlowsMax, "compact W covers the padded flows");
+
+// Every member starts on a 16-byte boundary (its 16-byte accesses would
+// otherwise be split).
+template <int kProd, bool kSplit>
+struct WsLdsLp {
+    alignas(16) uint32_t b_hi[2][kLpB];
+    alignas(16) uint32_t b_lo[2][kSplit ? kLpB : 4];
+    alignas(16) uint32_t w[2][(kSplit ? 2 : 1) * kLpWcP];
+    alignas(16) f2v r_buf[2][kM * kB];
+    alignas(16) uint32_t smax[2][kProd];
+    int es[2];
+};
+
+// One product's S and compact W in producer registers.
+template <int kProd, bool kSplit>
+struct PRegsLp {
+    static constexpr int kWChunks = (kSplit ? 2 : 1) * kLpWcP / 4;
+    static constexpr int kNW = (kWChunks + 64 * kProd - 1) / (64 * kProd);
+    PRegs<kProd, false> s;
+    f4v w[kNW];
+};
+
+// hi and lo (scaled by 2^kShift) 16-bit codes of a complex value, packed as
+// (re, im) pairs; the same rounding as split16, two values per instruction.
+template <bool kBf16, bool kSplit>
+__device__ __forceinline__ void split_pair(f2v v, uint32_t &hi, uint32_t &lo)
+{
+    typedef typename Lp<kBf16>::T2 T2;
+    const T2 h = __builtin_convertvector(v, T2);
+    hi = __builtin_bit_cast(uint32_t, h);
+    if constexpr (kSplit) {
+        const f2v r = (v - __builtin_convertvector(h, f2v)) * (float)(1 << Lp<kBf16>::kShift);
+        lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, T2));
+    }
+}
+
+// Every producer wave leaves the largest |Re|, |Im| of its part of a staged S.
+template <int kProd>
+__device__ __forceinline__ void p_publish_max(uint32_t *__restrict__ smax, const PRegs<kProd, false> &r,
+                                              int f, int ptid)
+{
+    const uint32_t m = wave_max_u32(p_absmax<kProd, false>(r, f, ptid));
+    if ((ptid & 63) == 0)
+        smax[ptid >> 6] = m;
+}
+
+// Converts a staged S (scale 2^-es, es from the published maxima) into the
+// 16-bit operand layout, flows f .. 8 ceil(f / 8) - 1 cleared, and copies
+// the staged W.  One lane leaves es for the consumers.
+template <bool kBf16, bool kSplit, int kProd>
+__device__ __forceinline__ void p_put_lp(uint32_t *__restrict__ bhi, uint32_t *__restrict__ blo,
+                                         uint32_t *__restrict__ wl, const uint32_t *__restrict__ smax,
+                                         int *__restrict__ es_out, const PRegsLp<kProd, kSplit> &r, int f,
+                                         int ptid)
+{
+    uint32_t m = 0;
+#pragma unroll
+    for (int i = 0; i < kProd; ++i)
+        m = max(m, smax[i]);
+    const int es = exp_of_bits(m);
+    const float sc = __builtin_amdgcn_ldexpf(1.0f, -es);
+    if (ptid == 0)
+        *es_out = es;
+    const int chunks = f * (kB / 2);
+#pragma unroll
+    for (int u = 0; u < PRegs<kProd, false>::kN; ++u) {
+        const int c = ptid + u * 64 * kProd;
+        if (c < chunks) {
+            const int row = c / (kB / 2);
+            const int col = 2 * (c - row * (kB / 2));
+            const int d = ((row >> 2) * 64 + col) * 4 + (row & 3);
+            uint32_t h0, l0 = 0, h1, l1 = 0;
+            split_pair<kBf16, kSplit>(f2v{r.s.v[u][0], r.s.v[u][1]} * sc, h0, l0);
+            split_pair<kBf16, kSplit>(f2v{r.s.v[u][2], r.s.v[u][3]} * sc, h1, l1);
+            bhi[d] = h0;
+            bhi[d + 4] = h1;
+            if constexpr (kSplit) {
+                blo[d] = l0;
+                blo[d + 4] = l1;
+            }
+        }
+    }
+    const int fpad = (f + kLpFlows - 1) & ~(kLpFlows - 1);
+    const int gap = fpad - f;
+    for (int e = ptid; e < 64 * gap; e += 64 * kProd) {
+        const int col = e / gap;
+        const int k = f + (e - col * gap);
+        const int d = ((k >> 2) * 64 + col) * 4 + (k & 3);
+        bhi[d] = 0u;
+        if constexpr (kSplit)
+            blo[d] = 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < PRegsLp<kProd, kSplit>::kNW; ++u) {
+        const int c = ptid + u * 64 * kProd;
+        if (c < PRegsLp<kProd, kSplit>::kWChunks)
+            reinterpret_cast<f4v *>(wl)[c] = r.w[u];
+    }
+}
+
+// Loads of product u (S and compact W) into a register set; past the end
+// the S loads read the sink (f = 0) and W is the last product's.
+template <int kProd, bool kSplit>
+__device__ __forceinline__ void p_load_lp(PRegsLp<kProd, kSplit> &r, c_item *my, int stride, int u, int n_my,
+                                          float2 *sink, const PlanDev &pd, int ptid)
+{
+    const BfItem d = item_at(my, min(u, n_my - 1), stride);
+    const bool real = u < n_my;
+    p_load_s<kProd, false>(r.s, real && d.f > 0 ? d.S : sink, real ? d.f : 0, ptid);
+    g_cf4v *src = (g_cf4v *)(pd.lp_wc + (size_t)d.w_id * pd.lp_wc_stride);
+    constexpr int kLast = PRegsLp<kProd, kSplit>::kWChunks - 1;
+#pragma unroll
+    for (int q = 0; q < PRegsLp<kProd, kSplit>::kNW; ++q)
+        r.w[q] = src[min(ptid + q * 64 * kProd, kLast)];
+}
+
+// One producer iteration t >= 1: R(t - 1) out, product t + 1 converted from
+// set kPut, the maxima of product t + 2 (set kMax) published, the loads of
+// product t + 1 + kDepth into set kPut.
+template <bool kBf16, bool kSplit, int kProd, int kDepth, int kPut, int kMax>
+__device__ __forceinline__ void ws_lp_step(PRegsLp<kProd, kSplit> (&sr)[kDepth], c_item *my, int stride,
+                                           int t, int n_my, float2 *sink, WsLdsLp<kProd, kSplit> &L,
+                                           const PlanDev &pd, int ptid)
+{
+    p_store_r<kProd>(item_at(my, t - 1, stride).R, L.r_buf[(t - 1) & 1], ptid);
+    const int f1 = item_at(my, min(t + 1, n_my - 1), stride).f;
+    const int f2 = t + 2 < n_my ? item_at(my, t + 2, stride).f : 0;
+    p_put_lp<kBf16, kSplit, kProd>(L.b_hi[(t + 1) & 1], L.b_lo[kSplit ? (t + 1) & 1 : 0], L.w[(t + 1) & 1],
+                                   L.smax[(t + 1) & 1], &L.es[(t + 1) & 1], sr[kPut], f1, ptid);
+    p_publish_max<kProd>(L.smax[t & 1], sr[kMax].s, f2, ptid);
+    p_load_lp<kProd, kSplit>(sr[kPut], my, stride, t + 1 + kDepth, n_my, sink, pd, ptid);
+}
+
+// The producer role (threads 64 kWaves ..).  Barriers: one before product
+// 0's conversion, then as the consumers: one before product 0 is used and
+// one after each product.
+template <bool kBf16, bool kSplit, int kProd, int kDepth>
+__device__ __forceinline__ void ws_producer_lp(c_item *my, int stride, int n_my, float2 *sink,
+                                               WsLdsLp<kProd, kSplit> &L, const PlanDev &pd)
+{
+    static_assert(kDepth >= 2 && kDepth <= 3, "prefetch depth");
+    const int ptid = threadIdx.x - 64 * kWaves;
+    const int plane = ptid & 63;
+    PRegsLp<kProd, kSplit> sr[kDepth];
+    // Each load group is preceded by as many sink stores as an iteration
+    // issues R stores, so that the outstanding memory operations at the
+    // loop's entry follow the pattern of its back edge.
+#pragma unroll
+    for (int u = 0; u < kDepth; ++u) {
+        prime_store_count<kPStoreRounds<kProd>>(sink, plane);
+        p_load_lp<kProd, kSplit>(sr[u], my, stride, u, n_my, sink, pd, ptid);
+    }
+    p_publish_max<kProd>(L.smax[0], sr[0].s, item_at(my, 0, stride).f, ptid);
+    __syncthreads();
+    p_put_lp<kBf16, kSplit, kProd>(L.b_hi[0], L.b_lo[0], L.w[0], L.smax[0], &L.es[0], sr[0],
+                                   item_at(my, 0, stride).f, ptid);
+    p_publish_max<kProd>(L.smax[1], sr[1].s, 1 < n_my ? item_at(my, 1, stride).f : 0, ptid);
+    prime_store_count<kPStoreRounds<kProd>>(sink, plane);
+    p_load_lp<kProd, kSplit>(sr[0], my, stride, kDepth, n_my, sink, pd, ptid);
+    __syncthreads();
+    // iteration 0: no R to write yet
+    {
+        prime_store_count<kPStoreRounds<kProd>>(sink, plane);
+        const int f1 = item_at(my, min(1, n_my - 1), stride).f;
+        const int f2 = 2 < n_my ? item_at(my, 2, stride).f : 0;
+        p_put_lp<kBf16, kSplit, kProd>(L.b_hi[1], L.b_lo[kSplit ? 1 : 0], L.w[1], L.smax[1], &L.es[1], sr[1],
+                                       f1, ptid);
+        p_publish_max<kProd>(L.smax[0], sr[2 % kDepth].s, f2, ptid);
+        p_load_lp<kProd, kSplit>(sr[1], my, stride, 1 + kDepth, n_my, sink, pd, ptid);
+        __syncthreads();
+    }
+    // Iterations 1 .. n_my - 1 in groups of kDepth (constant register set
+    // indices; a single exit at the loop's end), then the remainder.
+    const int groups = (n_my - 1) / kDepth;
+    const int rest = (n_my - 1) - groups * kDepth;
+    constexpr int kA0 = 2 % kDepth, kB0 = 3 % kDepth;
+    constexpr int kA1 = 3 % kDepth, kB1 = 4 % kDepth;
+    constexpr int kA2 = 4 % kDepth, kB2 = 5 % kDepth;
+    int t = 1;
+    for (int g = 0; g < groups; ++g) {
+        ws_lp_step<kBf16, kSplit, kProd, kDepth, kA0, kB0>(sr, my, stride, t, n_my, sink, L, pd, ptid);
+        __syncthreads();
+        ws_lp_step<kBf16, kSplit, kProd, kDepth, kA1, kB1>(sr, my, stride, t + 1, n_my, sink, L, pd, ptid);
+        __syncthreads();
+        if constexpr (kDepth >= 3) {
+            ws_lp_step<kBf16, kSplit, kProd, kDepth, kA2, kB2>(sr, my, stride, t + 2, n_my, sink, L, pd,
+                                                               ptid);
+            __syncthreads();
+        }
+        t += kDepth;
+    }
+    if (rest >= 1) {
+        ws_lp_step<kBf16, kSplit, kProd, kDepth, kA0, kB0>(sr, my, stride, t, n_my, sink, L, pd, ptid);
+        __syncthreads();
+    }
+    if constexpr (kDepth >= 3) {
+        if (rest >= 2) {
+            ws_lp_step<kBf16, kSplit, kProd, kDepth, kA1, kB1>(sr, my, stride, t + 1, n_my, sink, L, pd,
+                                                               ptid);
+            __syncthreads();
+        }
+    }
+    p_store_r<kProd>(item_at(my, n_my - 1, stride).R, L.r_buf[(n_my - 1) & 1], ptid);
+}
+
+// Matrix-core steps of one chunk for one 32-column tile.
+template <bool kBf16, bool kSplit>
+__device__ __forceinline__ void lp_mma(const u4v &ahi, const u4v &alo, const u4v &bh, const u4v &bl,
+                                       floatx16 &hh, floatx16 &cr)
+{
+    hh = Lp<kBf16>::mfma(ahi, bh, hh);
+    if constexpr (kSplit) {
+        cr = Lp<kBf16>::mfma(ahi, bl, cr);
+        cr = Lp<kBf16>::mfma(alo, bh, cr);
+    }
+}
+
+// Operand of a lane from four compact dwords (flows k .. k + 3 of its
+// antenna): real rows (c = 0) take (Wr, -Wi), i.e. the sign of the high
+// half flipped; imaginary rows (c = 1) take (Wi, Wr), the halves swapped.
+__device__ __forceinline__ u4v lp_a_of(u4v x, uint32_t rot, uint32_t flip)
+{
+    u4v a;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        a[j] = __builtin_amdgcn_alignbit(x[j], x[j], rot) ^ flip;
+    return a;
+}
+
+// One product from the 16-bit operands in LDS (result scaled by 2^eo),
+// staged into `stage`: both 32-column tiles, chunk by chunk, W operands
+// formed from the staged compact W.
+template <bool kBf16, bool kSplit>
+__device__ __forceinline__ void lp_chain_ws(const uint32_t *__restrict__ bhi, const uint32_t *__restrict__ blo,
+                                            const uint32_t *__restrict__ wl, int f, int eo, int wave, int lane,
+                                            f2v *__restrict__ stage)
+{
+    const int h = lane >> 5;
+    const int n = lane & 31;
+    const int tc = (f + kLpFlows - 1) / kLpFlows;
+    const u4v *ph = reinterpret_cast<const u4v *>(bhi) + h * 64 + n;
+    const u4v *pl = reinterpret_cast<const u4v *>(blo) + h * 64 + n;
+    // this lane's real row: antenna 16 wave + n / 2, component n % 2
+    const u4v *pw = reinterpret_cast<const u4v *>(wl + (16 * wave + (n >> 1)) * kLpWcFlows + 4 * h);
+    const uint32_t rot = (n & 1) ? 16u : 0u;
+    const uint32_t flip = (n & 1) ? 0u : 0x80000000u;
+    floatx16 hh0 = {}, hh1 = {}, cr0 = {}, cr1 = {};
+    const u4v zero = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int t = 0; t < kLpChunksMax; ++t) {
+        if (tc == kLpChunksMax || t < tc) {
+            const int g = 2 * t * 64;
+            const u4v ahi = lp_a_of(pw[2 * t], rot, flip);
+            const u4v alo = kSplit ? lp_a_of(pw[kLpWcP / 4 + 2 * t], rot, flip) : zero;
+            lp_mma<kBf16, kSplit>(ahi, alo, ph[g], kSplit ? pl[g] : zero, hh0, cr0);
+            lp_mma<kBf16, kSplit>(ahi, alo, ph[g + 32], kSplit ? pl[g + 32] : zero, hh1, cr1);
+        }
+    }
+    const float back = __builtin_amdgcn_ldexpf(1.0f, -Lp<kBf16>::kShift);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        float v0 = hh0[r], v1 = hh1[r];
+        if constexpr (kSplit) {
+            v0 = __builtin_fmaf(cr0[r], back, v0);
+            v1 = __builtin_fmaf(cr1[r], back, v1);
+        }
+        hh0[r] = __builtin_amdgcn_ldexpf(v0, eo);
+        hh1[r] = __builtin_amdgcn_ldexpf(v1, eo);
+    }
+    stage_acc(stage, lane, hh0, hh1);
+}
+
+// S must be 16-byte aligned and the plan's f_max at least 1 (the host routes
+// other batches elsewhere).
+template <bool kBf16, bool kSplit, int kProd, int kDepth>
+__global__ __launch_bounds__(64 * (kWaves + kProd)) void apply_lp_ws(BfHeader *__restrict__ blk,
+                                                                     const BfItem *__restrict__ items,
+                                                                     int n_items, PlanDev pd)
+{
+    __shared__ WsLdsLp<kProd, kSplit> L;
+    const int wave8 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    float2 *sink = sink_of(blk);
+    int start, stride;
+    const int n_my = ws_share(n_items, &start, &stride);
+    if (n_my <= 0)
+        return;
+
+    c_item *my = (c_item *)items + start;
+    if (wave8 < kWaves) {
+        // consumer.  The scalar reads for later products (f of t + 1, the W
+        // exponent of t + 1) are issued at the end of product t, where the
+        // barrier waits for them anyway.
+        const int wave = wave8;
+        int f = item_at(my, 0, stride).f;
+        int ew = pd.lp_exp[item_at(my, 0, stride).w_id];
+        __syncthreads();
+        __syncthreads();
+        for (int t = 0; t < n_my; ++t) {
+            lp_chain_ws<kBf16, kSplit>(L.b_hi[t & 1], L.b_lo[kSplit ? t & 1 : 0], L.w[t & 1], f,
+                                       ew + L.es[t & 1], wave, lane, L.r_buf[t & 1] + wave * kWaveOut);
+            __builtin_amdgcn_sched_barrier(0);
+            const BfItem dn = item_at(my, min(t + 1, n_my - 1), stride);
+            f = dn.f;
+            ew = pd.lp_exp[dn.w_id];
+            __syncthreads();
+        }
+    } else {
+        ws_producer_lp<kBf16, kSplit, kProd, kDepth>(my, stride, n_my, sink, L, pd);
     }
 }
 
@@ -1667,10 +2090,35 @@ static hipError_t launch_lp_t(const LaunchCfg &cfg, BfHeader *blk, int n_items, 
     return hipGetLastError();
 }
 
+// Schedule 3 for the 16-bit forms: producer waves and S prefetch depth from
+// the variant.
+template <bool kBf16, bool kSplit>
+static hipError_t launch_lp_ws(const LaunchCfg &cfg, BfHeader *blk, int n_items, const PlanDev &pd,
+                               hipStream_t st)
+{
+    const BfItem *items = items_of(blk);
+    const dim3 grid(cfg.grid);
+    if (cfg.producers == 4)
+        hipLaunchKernelGGL((apply_lp_ws<kBf16, kSplit, 4, 2>), grid, dim3(64 * 8), 0, st, blk, items,
+                           n_items, pd);
+    else if (cfg.producers == 12)
+        hipLaunchKernelGGL((apply_lp_ws<kBf16, kSplit, 12, 2>), grid, dim3(64 * 16), 0, st, blk, items,
+                           n_items, pd);
+    else if (cfg.depth >= 3)
+        hipLaunchKernelGGL((apply_lp_ws<kBf16, kSplit, 8, 3>), grid, dim3(64 * 12), 0, st, blk, items,
+                           n_items, pd);
+    else
+        hipLaunchKernelGGL((apply_lp_ws<kBf16, kSplit, 8, 2>), grid, dim3(64 * 12), 0, st, blk, items,
+                           n_items, pd);
+    return hipGetLastError();
+}
+
 template <bool kBf16, bool kSplit>
 static hipError_t launch_lp_v(const LaunchCfg &cfg, BfHeader *blk, int n_items, const PlanDev &pd,
                               hipStream_t st)
 {
+    if (cfg.schedule == 3)
+        return launch_lp_ws<kBf16, kSplit>(cfg, blk, n_items, pd, st);
     if (cfg.stage)
         return cfg.vec16 ? launch_lp_t<kBf16, kSplit, true, true>(cfg, blk, n_items, pd, st)
                          : launch_lp_t<kBf16, kSplit, false, true>(cfg, blk, n_items, pd, st);
@@ -1712,6 +2160,8 @@ static int occ_of(K kernel, int threads = kThreads)
 template <bool kBf16, bool kSplit, bool kStage>
 static int occ_lp(int schedule, bool vec16)
 {
+    if (schedule == 3)
+        return occ_of(apply_lp_ws<kBf16, kSplit, 4, 2>, 512);
     if (schedule == 0)
         return vec16 ? occ_of(apply_lp_single<kBf16, kSplit, true, kStage>)
                      : occ_of(apply_lp_single<kBf16, kSplit, false, kStage>);

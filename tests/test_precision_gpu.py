@@ -28,15 +28,20 @@ U = {"fp16": 2.0 ** -11, "bf16": 2.0 ** -8}
 BAR = {"fp16x2": 2e-5, "bf16x2": 2e-5,
        "fp16": 4 * U["fp16"] * math.sqrt(2), "bf16": 4 * U["bf16"] * math.sqrt(2)}
 VARIANTS = {"one-per-wg": (0, 0, 0), "stream": (2, 0, 1), "stream-2-asgiven": (2, 2, 0),
-            "single-staged": (0, 0, 0, 1), "stream-staged": (2, 0, 1, 1)}
+            "single-staged": (0, 0, 0, 1), "stream-staged": (2, 0, 1, 1),
+            "ws-4-producers": (3, 0, 0, 0), "ws-8-sorted": (3, 0, 1, 1),
+            "ws-8-depth-2": (3, 0, 0, 2), "ws-8-depth-3": (3, 0, 1, 3),
+            "ws-12-producers": (3, 0, 0, 4), "ws-2-per-cu": (3, 2, 0, 1)}
+WS_VARIANTS = ["ws-4-producers", "ws-8-sorted", "ws-8-depth-3", "ws-12-producers"]
 
 
+@pytest.mark.parametrize("vname", ["default", "ws-8-sorted"])
 @pytest.mark.parametrize("form", sorted(LP))
-def test_exact_integers_bitwise(form):
+def test_exact_integers_bitwise(form, vname):
     rng = np.random.default_rng(601)
     b = wl.exact_integer_batch(rng, 150, 4)
-    announce(f"exact integers form={form}")
-    R = run_batch(b, prec=LP[form])
+    announce(f"exact integers form={form} variant={vname}")
+    R = run_batch(b, prec=LP[form], variant=VARIANTS.get(vname))
     ref = orc.apply(b)
     assert np.array_equal(R.astype(np.complex128), ref)
 
@@ -55,18 +60,20 @@ def test_ragged_random(form, vname):
     assert np.max(err[nz]) <= BAR[form], f"{form}: max rel err {np.max(err[nz]):.3g}"
 
 
+@pytest.mark.parametrize("vname", ["default", "stream", "ws-8-sorted"])
 @pytest.mark.parametrize("form", sorted(LP))
-def test_gains_do_not_change_accuracy(form):
-    """S scaled by gains 1e-3 .. 1e3: the per-product power-of-two scaling
-    keeps every 16-bit operand in range, so the error stays at the bar."""
+def test_gains_do_not_change_accuracy(form, vname):
+    """S scaled by gains 1e-3 .. 1e3 (and far beyond FP16's range): the
+    per-product power-of-two scaling keeps every 16-bit operand in range, so
+    the error stays at the bar."""
     rng = np.random.default_rng(603)
     base = wl.qam256(rng, (36, wl.B))
-    gains = np.array([1e-3, 3.7e-2, 1.0, 29.0, 1e3])
+    gains = np.array([1e-3, 3.7e-2, 1.0, 29.0, 1e3, 1e-9, 1e9])
     W = wl.unit_norm_pool(rng, 1, 36)
     blocks = [base * g for g in gains]
     b = wl._pack("gains", W, np.zeros(len(gains), np.int32), np.full(len(gains), 36), blocks)
-    announce(f"gains form={form}")
-    R = run_batch(b, prec=LP[form])
+    announce(f"gains form={form} variant={vname}")
+    R = run_batch(b, prec=LP[form], variant=VARIANTS.get(vname))
     err, _ = rel_errors(b, R)
     assert np.max(err) <= BAR[form], f"{form}: {err}"
 
@@ -101,3 +108,41 @@ def test_gain_workload_sampled(form):
     print(f"[{form}] rel err min {err.min():.3g} p50 {np.median(err):.3g} "
           f"p99 {np.percentile(err, 99):.3g} max {err.max():.3g}", flush=True)
     assert np.max(err) <= BAR[form]
+
+
+@pytest.mark.parametrize("vname", WS_VARIANTS)
+@pytest.mark.parametrize("per_wg", [5, 7])
+@pytest.mark.parametrize("form", sorted(LP))
+def test_ws_long_shares(form, vname, per_wg):
+    """Wave-specialised schedule with 5-8 products per workgroup, so that the
+    producers' prefetch ring wraps and every remainder of its unrolled loop
+    occurs; ragged f in random order, gains 10^U(-3,3) per product (each
+    product's scale comes from the producers' maxima)."""
+    require_gpu()
+    n_cu = bf.bf_device_cu_count()
+    n = n_cu * per_wg + (37 * per_wg) % n_cu
+    rng = np.random.default_rng(620 + per_wg)
+    b = wl.random_batch(rng, n, 9, f_values=np.arange(0, 37), dist="qam")
+    gains = 10.0 ** rng.uniform(-3, 3, size=n)
+    b = wl._pack("gains", b.W, b.w_ids, b.f,
+                 [b.s_block(t) * g for t, g in enumerate(gains)])
+    announce(f"ws long shares form={form} variant={vname} n={n}")
+    R = run_batch(b, prec=LP[form], variant=VARIANTS[vname])
+    err, _ = rel_errors(b, R)
+    nz = b.f > 0
+    assert np.all(R[~nz] == 0)
+    assert np.max(err[nz]) <= BAR[form], f"{form}: max rel err {np.max(err[nz]):.3g}"
+
+
+@pytest.mark.parametrize("f_max", [1, 7, 9])
+@pytest.mark.parametrize("form", sorted(LP))
+def test_ws_small_pools(form, f_max):
+    """Pools narrower than one 8-flow chunk (and just over one)."""
+    rng = np.random.default_rng(630 + f_max)
+    b = wl.random_batch(rng, 300, 3, f_max=f_max, f_values=np.arange(0, f_max + 1), dist="qam")
+    announce(f"ws small pool form={form} f_max={f_max}")
+    R = run_batch(b, prec=LP[form], variant=VARIANTS["ws-8-sorted"])
+    err, _ = rel_errors(b, R)
+    nz = b.f > 0
+    assert np.all(R[~nz] == 0)
+    assert np.max(err[nz]) <= BAR[form], f"{form}: max rel err {np.max(err[nz]):.3g}"
