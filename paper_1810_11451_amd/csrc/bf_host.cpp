@@ -87,9 +87,8 @@ static void release_slot(StagingSlot &s)
 }
 
 // Defaults measured on MI355X: full-width batches (mean f 36) run the
-// wave-specialised schedule, so do the 16-bit forms' batches of mixed f;
-// the FP32 forms' mixed batches and every batch of small mean f run one
-// product per workgroup; all in the order given.
+// wave-specialised schedule, batches of mixed or small f one product per
+// workgroup, all in the order given.
 static bf_status default_variants(bf_plan p)
 {
     for (int pr = 0; pr < kPrecCount; ++pr)
@@ -101,10 +100,10 @@ static bf_status default_variants(bf_plan p)
                 v = bf_variant{3, 0, 0, 1};   // wave-specialised, 8 producers, depth 1, as given
             else if (full && fp32)
                 v = bf_variant{3, 0, 0, 5};   // wave-specialised, 12 producers, depth 2, as given
-            else if (!fp32 && b > 0)
+            else if (full)
                 v = bf_variant{3, 0, 0, 4};   // 16-bit forms: wave-specialised, 12 producers
             else
-                v = bf_variant{0, 0, 0, 0};   // one per workgroup
+                v = bf_variant{0, 0, 0, 0};   // mixed or small f: one per workgroup
             p->table[pr][b] = v;
         }
     return BF_OK;
