@@ -71,6 +71,26 @@ def test_update_then_apply(form):
     plan.close()
 
 
+@pytest.mark.parametrize("form", sorted(FORMS))
+def test_update_then_apply_wave_specialised(form):
+    """The same through the wave-specialised schedule, which reads the
+    16-bit forms' compact W layout (rewritten by the update too)."""
+    require_gpu()
+    rng = np.random.default_rng(907)
+    b = wl.random_batch(rng, 700, 5, f_values=np.arange(0, 37), dist="qam")
+    plan = bf.bf_plan_create(b.W, bf.BF_PREC_BIT(FORMS[form]))
+    for bk in range(5):
+        bf.bf_set_variant(plan, FORMS[form], bk, 3, 0, 0, 1)
+    W2 = b.W.copy()
+    W2[2] = wl.unit_norm_pool(rng, 1, wl.F_MAX)[0] * 3.0   # a new scale exponent as well
+    announce(f"update then apply, wave-specialised, form={form}")
+    bf.bf_plan_update(plan, 2, W2[2])
+    db = DeviceBatch(b)
+    db.apply(plan, FORMS[form])
+    check(b, W2, db.result(), BAR[form], form)
+    plan.close()
+
+
 def test_before_and_after_on_one_stream():
     """apply(old) ; update ; apply(new) issued back to back on one stream."""
     torch = require_gpu()
