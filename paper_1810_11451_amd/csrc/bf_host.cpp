@@ -87,8 +87,9 @@ static void release_slot(StagingSlot &s)
 }
 
 // Defaults measured on MI355X: full-width batches (mean f 36) run the
-// wave-specialised schedule, batches of mixed or small f one product per
-// workgroup, all in the order given.
+// wave-specialised schedule, and so do the three-product form's batches of
+// mixed f; other batches of mixed or small f run one product per
+// workgroup; all in the order given.
 static bf_status default_variants(bf_plan p)
 {
     for (int pr = 0; pr < kPrecCount; ++pr)
@@ -96,7 +97,7 @@ static bf_status default_variants(bf_plan p)
             bf_variant v{};
             const bool full = b == kBucketCount - 1;
             const bool fp32 = pr == BF_FP32 || pr == BF_FP32_3M;
-            if (full && pr == BF_FP32_3M)
+            if (pr == BF_FP32_3M && b > 0)
                 v = bf_variant{3, 0, 0, 1};   // wave-specialised, 8 producers, depth 1, as given
             else if (full && fp32)
                 v = bf_variant{3, 0, 0, 5};   // wave-specialised, 12 producers, depth 2, as given
