@@ -434,14 +434,11 @@ __device__ __forceinline__ void contract_fp32_reload(const f2v *__restrict__ lds
 // nt = w % 2, and accumulates T1 = Wr Sr, T2 = Wi Si, T3 = (Wr + Wi)(Sr + Si)
 // over the flows; then Re R = T1 - T2 and Im R = (T3 - T1) - T2.
 
-// Loads the wave's operands of pool entry w: pairs >= 1, entries past
-// `pairs` repeat the last one and are never used.
 // Operands of pool entry w for antenna half mt: 3 registers per pair, read
-// from the plan's component planes; entries past `pairs` repeat the last
-// one and are never used.
-// `need` (>= 1) pairs are used by the product; loads of later pairs repeat
-// the last needed one, so they hit in cache instead of fetching W columns
-// the product does not use.
+// from the plan's component planes (pairs >= 1).  The product uses `need`
+// (>= 1) pairs; the loads of later pairs repeat the last used one, so they
+// hit in cache instead of fetching W columns the product does not use, and
+// those registers feed no matrix-core step.
 __device__ __forceinline__ void load_a_3m(f3v (&a)[kPairsMax], const float *__restrict__ apool,
                                           int w, int a_w_stride, int pairs, int mt, int lane,
                                           int need)
@@ -813,9 +810,11 @@ __global__ __launch_bounds__(kThreads) void apply_fp32_stream(BfHeader *__restri
 // from LDS; the kProd producer waves only move data.  Per product t of the
 // workgroup's share (every nb-th item of its XCD's range):
 //   consumers: contract S(t) from s_buf[t % 2] (three-product form: with the
-//              W operands from a_buf[t % 2]), results -> r_buf[t % 2];
-//   producers: write R(t-1) from r_buf[(t-1) % 2] with contiguous 16-byte
-//              stores; move S(t+1) (and W(t+1)) from registers to LDS; issue
+//              W operands from a_buf[t % 2]), results -> r_buf[t % 2] (the
+//              three-product form stages them during product t + 1);
+//   producers: write R(t-1) (three-product form: R(t-2)) from LDS with
+//              contiguous 16-byte stores; move S(t+1) (and W(t+1)) from
+//              registers to LDS; issue
 //              the loads for product t+1+kDepth into the register set that
 //              product t+1 has just left;
 //   one barrier.

@@ -30,12 +30,26 @@ FILTER_SOURCES = ["paper_1810_11451_amd/csrc/bf_filter.hip",
 TRAFFIC_JSON = ROOT / "profiles" / "traffic.json"
 
 
+def _code_only(text: str) -> str:
+    """Source text without comments and blank lines, each line stripped, so
+    that edits to comments alone do not change a kernel's hash.  (Only line
+    comments are used in these sources; a "//" inside a string literal would
+    be cut too, which only makes the hash stricter.)"""
+    out = []
+    for line in text.splitlines():
+        code = line.split("//", 1)[0].strip()
+        if code:
+            out.append(code)
+    return "\n".join(out)
+
+
 def kernel_sha(key: str = "") -> str:
-    """Hash of the kernel sources a traffic entry depends on (the filter
-    stage's for keys naming it, else the beamforming kernels')."""
+    """Hash of the code (comments left out) of the kernel sources a traffic
+    entry depends on: the filter stage's for keys naming it, else the
+    beamforming kernels'."""
     h = hashlib.sha256()
     for p in (FILTER_SOURCES if "filter" in key else KERNEL_SOURCES):
-        h.update((ROOT / p).read_bytes())
+        h.update(_code_only((ROOT / p).read_text()).encode())
     return h.hexdigest()[:16]
 
 
