@@ -146,3 +146,75 @@ def test_ws_small_pools(form, f_max):
     nz = b.f > 0
     assert np.all(R[~nz] == 0)
     assert np.max(err[nz]) <= BAR[form], f"{form}: max rel err {np.max(err[nz]):.3g}"
+
+
+@pytest.mark.parametrize("form", ["fp16x2", "bf16"])
+def test_ws_graph_replay_matches_direct(form):
+    """The wave-specialised 16-bit kernel captured in a graph: every replay
+    (with eager work between replays) equals the direct launch bitwise."""
+    torch = require_gpu()
+    rng = np.random.default_rng(640)
+    b = wl.random_batch(rng, 900, 6, f_values=np.arange(0, 37), dist="qam")
+    plan = bf.bf_plan_create(b.W, bf.BF_PREC_BIT(LP[form]))
+    for bk in range(5):
+        bf.bf_set_variant(plan, LP[form], bk, *VARIANTS["ws-8-depth-3"])
+    direct = DeviceBatch(b)
+    direct.apply(plan, LP[form])
+    Rd = direct.result()
+    db = DeviceBatch(b)
+    announce(f"ws graph replay x3 form={form}")
+    g = bf.bf_graph_create(plan, b.w_ids, b.f, db.s_ptrs[0], db.r_ptrs[0], LP[form])
+    for rep in range(3):
+        db.R[0].view(torch.float32).fill_(float("nan"))
+        bf.bf_graph_launch(g)
+        torch.cuda.synchronize()
+        assert np.array_equal(db.result().view(np.uint32), Rd.view(np.uint32)), f"replay {rep}"
+        direct.apply(plan, LP[form])
+        torch.cuda.synchronize()
+    g.close()
+    err, _ = rel_errors(b, Rd)
+    nz = b.f > 0
+    assert np.max(err[nz]) <= BAR[form]
+    plan.close()
+
+
+def test_autotune_split_form():
+    """The autotuner over every schedule of a split form (the wave-specialised
+    one included) picks a variant whose results meet the bar."""
+    require_gpu()
+    rng = np.random.default_rng(641)
+    b = wl.random_batch(rng, 1500, 8, f_values=np.arange(20, 37), dist="qam")
+    plan = bf.bf_plan_create(b.W, bf.BF_PREC_BIT(bf.BF_FP16X2))
+    db = DeviceBatch(b)
+    announce("autotune fp16x2")
+    best, us = bf.bf_autotune(plan, b.w_ids, b.f, db.s_ptrs[0], db.r_ptrs[0], prec=bf.BF_FP16X2, reps=2)
+    assert us > 0
+    assert bf.bf_get_variant(plan, bf.BF_FP16X2, bf.batch_bucket(b.f)) == best
+    db.R[0].fill_(float("nan"))
+    db.apply(plan, bf.BF_FP16X2)
+    err, _ = rel_errors(b, db.result())
+    assert np.max(err) <= BAR["fp16x2"]
+    plan.close()
+
+
+@pytest.mark.parametrize("form", sorted(LP))
+def test_ws_variant_with_unaligned_s(form):
+    """S blocks only 8-byte aligned: a wave-specialised variant falls back to
+    a schedule that reads 8-byte elements, with the same results."""
+    rng = np.random.default_rng(642)
+    f = np.array([3, 1, 36, 5, 0, 2, 35, 17, 9], np.int32)
+    W = wl.unit_norm_pool(rng, 2, wl.F_MAX)
+    w_ids = rng.integers(0, 2, len(f)).astype(np.int32)
+    blocks = [wl.qam256(rng, (int(x), wl.B)) for x in f]
+    b = wl._pack("aligned", W, w_ids, f, blocks)
+    S2 = np.zeros(b.S.size + len(f), np.complex64)
+    off2 = b.s_off + np.arange(len(f)) + 1
+    for t in range(len(f)):
+        S2[off2[t]: off2[t] + f[t] * wl.B] = b.s_block(t).reshape(-1)
+    b2 = wl.Batch("unaligned", W, w_ids, f, S2, off2)
+    announce(f"ws variant, 8-byte aligned S, form={form}")
+    R = run_batch(b2, prec=LP[form], variant=VARIANTS["ws-8-sorted"])
+    err, _ = rel_errors(b2, R)
+    nz = f > 0
+    assert np.all(R[~nz] == 0)
+    assert np.max(err[nz]) <= BAR[form]
