@@ -81,6 +81,41 @@ def cpu_baseline(batch, target_s: float) -> dict:
                       f"x{reps} passes, C FP64 triple loop, {dt:.1f} s"}
 
 
+def cpu_extra(batch, target_s: float) -> dict:
+    """Second CPU data points on bounded samples: the C oracle on one core
+    and the oracle's numpy rendering (complex128), each about target_s."""
+    from oracle import oracle as orc
+    rng = np.random.default_rng(54321)
+    out = {}
+    for name, fn in (("c_oracle_one_core", lambda it: orc.apply(batch, items=it, threads=1)),
+                     ("numpy_oracle_one_core", lambda it: [orc.apply_numpy(batch.w_block(int(t)),
+                                                                           batch.s_block(int(t)))
+                                                          for t in it])):
+        items = rng.choice(batch.n, size=min(batch.n, 64), replace=False)
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            fn(items)
+            reps += 1
+            dt = time.perf_counter() - t0
+            if dt >= target_s:
+                break
+        flops = reps * 8 * wl.M * wl.B * int(np.sum(batch.f[items].astype(np.int64)))
+        out[name] = {"value": round(flops / dt / 1e9, 3), "unit": "complex GFLOP/s", "cores": 1,
+                     "sample": f"{len(items)} seeded products, x{reps} passes, {dt:.1f} s"}
+    return out
+
+
+def probe_copy(mib: int = 1024) -> dict | None:
+    """Measured HBM copy bandwidth on this device (the probe's streaming
+    copy), as a second denominator for HBM-bound rooflines."""
+    try:
+        from paper_1810_11451_amd.probe import hbm
+        return hbm.measure(mib=mib, iters=10)
+    except (RuntimeError, OSError) as e:   # probe library not built
+        print(f"[bench] copy probe unavailable: {e}", file=sys.stderr, flush=True)
+        return None
+
+
 GROUP = 10   # launches per event pair in the kernel timing
 
 
@@ -446,17 +481,26 @@ def main(argv=None) -> int:
         ("3m_" if prec == bf.BF_FP32_3M else "") + \
         {0: "single", 1: "claim", 2: "stream", 3: "ws"}[sched]
     roof["kernel_us_mean"] = round(kern_s * 1e6, 2)
+    roof["kernel_us_p50"] = round(float(np.median(kern_ms)) * 1e3, 2)
+    roof["kernel_us_min"] = round(float(np.min(kern_ms)) * 1e3, 2)
     roof["kernel_timing"] = ("HIP events on the launch stream around groups of 10 back-to-back graph "
                              "launches of the same kernel and grid")
     roof["step_us_mean"] = round(float(np.mean(step_ms)) * 1e3, 2)
     roof["algorithmic"] = {"flops_per_launch": flops, "bytes_per_launch": nbytes,
                            "ai_flop_per_byte": round(ai, 2)}
     roof["hbm_gbs_equiv"] = round(nbytes / kern_s / 1e9, 1)
+    if roof["bound"] == "hbm":
+        pc = probe_copy()
+        if pc is not None:
+            roof["measured_probe"] = {"kind": "streaming copy, 1 GiB read + 1 GiB written",
+                                      "GBps": pc["GBps"],
+                                      "frac": round(roof["hbm_gbs_equiv"] / pc["GBps"], 4)}
 
     out = {
         "metric": METRIC,
         "value": round(value, 2),
         "unit": "complex GFLOP/s",
+        "complex_gmac_per_s": round(value / 8, 2),
         "n_gpus": 1,
         "steps": K,
         "warmup": args.warmup,
@@ -485,6 +529,7 @@ def main(argv=None) -> int:
         out["compare_fp32_four_product"] = compare
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(batch, args.cpu_seconds)
+        out["cpu_other"] = cpu_extra(batch, min(3.0, args.cpu_seconds))
     plan.close()
     print(json.dumps(out), flush=True)
     return 0

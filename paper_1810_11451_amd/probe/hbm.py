@@ -24,8 +24,48 @@ def build() -> Path:
     from paper_1810_11451_amd.build import ARCH, COMMON, hipcc
     cmd = [hipcc(), *COMMON, "-x", "hip", "-shared", "-fPIC", str(HERE / "hbm_probe.hip"),
            "-o", str(LIB)]
-    subprocess.run(cmd, check=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"probe build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     return LIB
+
+
+def measure(mib: int = 1024, iters: int = 20, mode: str = "copy", grid: int = 0,
+            variant: int = 1) -> dict:
+    """Times the streaming kernel on `mib` MiB (read, written or both) with
+    HIP events; returns its figures as a dict (GBps counts read + written)."""
+    import torch
+    if not LIB.exists():
+        raise RuntimeError(f"{LIB} not built")
+    L = ctypes.CDLL(str(LIB))
+    L.bfprobe_stream.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
+                                 ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+    m = {"copy": 0, "read": 1, "write": 2}[mode]
+    nbytes = mib << 20
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    grid = grid or 256 * 8
+    st = torch.cuda.current_stream()
+    for _ in range(3):
+        if L.bfprobe_stream(src.data_ptr(), dst.data_ptr(), nbytes, grid, variant, m,
+                            st.cuda_stream) != 0:
+            raise RuntimeError("probe launch failed")
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(iters):
+        L.bfprobe_stream(src.data_ptr(), dst.data_ptr(), nbytes, grid, variant, m, st.cuda_stream)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / iters
+    rd = nbytes if m != 2 else 0
+    wr = nbytes if m != 1 else 0
+    if m == 0 and not bool(torch.equal(src[:1024], dst[:1024])):
+        raise RuntimeError("probe copy is wrong")
+    del src, dst
+    return {"probe": "hbm_" + mode, "bytes_read": rd, "bytes_written": wr,
+            "us": round(ms * 1e3, 2), "GBps": round((rd + wr) / ms / 1e6, 1), "grid": grid,
+            "variant": variant}
 
 
 def main(argv=None) -> int:
@@ -37,36 +77,7 @@ def main(argv=None) -> int:
                     help="bit 0 non-temporal, bits 1-2 log2 unroll (default 1: plain nt copy)")
     ap.add_argument("--mode", default="copy", choices=["copy", "read", "write"])
     a = ap.parse_args(argv)
-    import torch
-    if not LIB.exists():
-        raise RuntimeError(f"{LIB} not built")
-    L = ctypes.CDLL(str(LIB))
-    L.bfprobe_stream.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
-                                 ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
-    mode = {"copy": 0, "read": 1, "write": 2}[a.mode]
-    nbytes = a.mib << 20
-    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
-    dst = torch.empty_like(src)
-    grid = a.grid or 256 * 8
-    st = torch.cuda.current_stream()
-    for _ in range(3):
-        assert L.bfprobe_stream(src.data_ptr(), dst.data_ptr(), nbytes, grid, a.variant, mode,
-                                st.cuda_stream) == 0
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(st)
-    for _ in range(a.iters):
-        L.bfprobe_stream(src.data_ptr(), dst.data_ptr(), nbytes, grid, a.variant, mode, st.cuda_stream)
-    e1.record(st)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / a.iters
-    rd = nbytes if mode != 2 else 0
-    wr = nbytes if mode != 1 else 0
-    if mode == 0:
-        assert bool(torch.equal(src[:1024], dst[:1024]))
-    print(json.dumps({"probe": "hbm_" + a.mode, "bytes_read": rd, "bytes_written": wr,
-                      "us": round(ms * 1e3, 2), "GBps": round((rd + wr) / ms / 1e6, 1),
-                      "grid": grid, "variant": a.variant}), flush=True)
+    print(json.dumps(measure(a.mib, a.iters, a.mode, a.grid, a.variant)), flush=True)
     return 0
 
 
