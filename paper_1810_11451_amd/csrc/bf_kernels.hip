@@ -518,23 +518,24 @@ __device__ __forceinline__ void stage_row_3m(const floatx16 &t1, const floatx16 
 // planes, as in the plan: [2 halves][pairs][3][64 lanes] floats).  The A
 // and B values of each pair are read ahead of its products in batches of 6
 // pairs: batch k is issued once pair 6k - 4 is, so at most 10 pairs occupy
-// registers and each wait covers only the oldest reads.  Rows past f and
-// pairs past the plan's hold older data and feed no product.
+// registers and each wait covers only the oldest reads.  kFull (f > 34):
+// every batch is read, in straight-line code; otherwise only the batches
+// holding pairs below ceil(f / 2).  Rows past f and pairs past the plan's
+// hold older data and feed no product.
 // With kEpi, the previous product's accumulators (p1, p2, p3) are staged to
 // `prev_tile` one row per pair during the chain, so the epilogue runs while
 // the matrix cores are busy instead of after they drain.
-template <bool kEpi>
-__device__ __forceinline__ void chain_3m_lds(const f2v *__restrict__ lds, const float *__restrict__ lds_a,
-                                             int pairs, int f, int wave, int lane, floatx16 &t1,
-                                             floatx16 &t2, floatx16 &t3, const floatx16 &p1,
-                                             const floatx16 &p2, const floatx16 &p3,
-                                             f2v *__restrict__ prev_tile)
+template <bool kEpi, bool kFull>
+__device__ __forceinline__ void chain_3m_body(const f2v *__restrict__ lds, const float *__restrict__ lds_a,
+                                              int pairs, int np, int wave, int lane, floatx16 &t1,
+                                              floatx16 &t2, floatx16 &t3, const floatx16 &p1,
+                                              const floatx16 &p2, const floatx16 &p3,
+                                              f2v *__restrict__ prev_tile)
 {
     const int h = lane >> 5;
     const int n = lane & 31;
     const int mt = wave >> 1;
     const int nt = wave & 1;
-    const int np = (f + 1) >> 1;
     constexpr int kBatch = 6, kLead = 4;
     const f2v *col = lds + h * kLdsCols + 32 * nt + n;
     const float *ab = lds_a + mt * pairs * 192 + lane;
@@ -543,22 +544,24 @@ __device__ __forceinline__ void chain_3m_lds(const f2v *__restrict__ lds, const 
     t3 = floatx16{};
     f3v a[kPairsMax];
     f2v b[kPairsMax];
+    if (kFull || np > 0) {
 #pragma unroll
-    for (int q = 0; q < kBatch; ++q) {
-        b[q] = col[2 * q * kLdsCols];
-        a[q] = f3v{ab[(3 * q) * 64], ab[(3 * q + 1) * 64], ab[(3 * q + 2) * 64]};
+        for (int q = 0; q < kBatch; ++q) {
+            b[q] = col[2 * q * kLdsCols];
+            a[q] = f3v{ab[(3 * q) * 64], ab[(3 * q + 1) * 64], ab[(3 * q + 2) * 64]};
+        }
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int p = 0; p < kPairsMax; ++p) {
-        if (p + kLead < kPairsMax && (p + kLead) % kBatch == 0) {
+        if (p + kLead < kPairsMax && (p + kLead) % kBatch == 0 && (kFull || p + kLead < np)) {
 #pragma unroll
             for (int q = p + kLead; q < p + kLead + kBatch; ++q) {
                 b[q] = col[2 * q * kLdsCols];
                 a[q] = f3v{ab[(3 * q) * 64], ab[(3 * q + 1) * 64], ab[(3 * q + 2) * 64]};
             }
         }
-        if (p < np)
+        if (kFull || p < np)
             mfma3(a[p], b[p], t1, t2, t3);
         if constexpr (kEpi) {
             if (p < 16)
@@ -566,6 +569,20 @@ __device__ __forceinline__ void chain_3m_lds(const f2v *__restrict__ lds, const 
         }
         __builtin_amdgcn_sched_barrier(0);
     }
+}
+
+template <bool kEpi>
+__device__ __forceinline__ void chain_3m_lds(const f2v *__restrict__ lds, const float *__restrict__ lds_a,
+                                             int pairs, int f, int wave, int lane, floatx16 &t1,
+                                             floatx16 &t2, floatx16 &t3, const floatx16 &p1,
+                                             const floatx16 &p2, const floatx16 &p3,
+                                             f2v *__restrict__ prev_tile)
+{
+    const int np = (f + 1) >> 1;
+    if (np == kPairsMax)
+        chain_3m_body<kEpi, true>(lds, lds_a, pairs, np, wave, lane, t1, t2, t3, p1, p2, p3, prev_tile);
+    else
+        chain_3m_body<kEpi, false>(lds, lds_a, pairs, np, wave, lane, t1, t2, t3, p1, p2, p3, prev_tile);
 }
 
 __device__ __forceinline__ void stage_3m(const floatx16 &t1, const floatx16 &t2, const floatx16 &t3,
@@ -896,15 +913,18 @@ __device__ __forceinline__ void p_load_w(PRegs<kProd, true> &r, const float *__r
     }
 }
 
+// Puts the chunks of the first `need` pairs of each antenna half (the
+// only ones the product's chain reads).
 template <int kProd>
 __device__ __forceinline__ void p_put_w(float *__restrict__ lds_a, const PRegs<kProd, true> &r, int pairs,
-                                        int ptid)
+                                        int need, int ptid)
 {
-    const int chunks = pairs * 96;
+    const int half = pairs * 48;
+    const int used = min(pairs, need) * 48;
 #pragma unroll
     for (int u = 0; u < PRegs<kProd, true>::kNW; ++u) {
         const int c = ptid + u * 64 * kProd;
-        if (c < chunks)
+        if (c < 2 * half && (c < half ? c : c - half) < used)
             reinterpret_cast<f4v *>(lds_a)[c] = r.w[u];
     }
 }
@@ -987,7 +1007,7 @@ __device__ __forceinline__ void p_put_item(f2v *__restrict__ s_lds, float *__res
 {
     p_put_s<kProd, k3M>(s_lds, r, f, ptid);
     if constexpr (k3M)
-        p_put_w<kProd>(a_lds, r, pairs, ptid);
+        p_put_w<kProd>(a_lds, r, pairs, max((f + 1) >> 1, 1), ptid);
     if constexpr (kMax) {
         const uint32_t m = wave_max_u32(p_absmax<kProd, k3M>(r, f, ptid));
         if ((ptid & 63) == 0)
