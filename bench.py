@@ -105,6 +105,18 @@ def cpu_extra(batch, target_s: float) -> dict:
     return out
 
 
+def probe_mfma() -> dict | None:
+    """Measured sustained FP32 matrix-core rate on this device (the probe's
+    register-only MFMA loop), as a second denominator for MFMA-bound
+    rooflines."""
+    try:
+        from paper_1810_11451_amd.probe import hbm
+        return hbm.measure_mfma()
+    except (RuntimeError, OSError) as e:   # probe library not built
+        print(f"[bench] matrix-core probe unavailable: {e}", file=sys.stderr, flush=True)
+        return None
+
+
 def probe_copy(mib: int = 1024) -> dict | None:
     """Measured HBM copy bandwidth on this device (the probe's streaming
     copy), as a second denominator for HBM-bound rooflines."""
@@ -495,6 +507,13 @@ def main(argv=None) -> int:
             roof["measured_probe"] = {"kind": "streaming copy, 1 GiB read + 1 GiB written",
                                       "GBps": pc["GBps"],
                                       "frac": round(roof["hbm_gbs_equiv"] / pc["GBps"], 4)}
+    elif not lp:
+        pm = probe_mfma()
+        if pm is not None:
+            roof["measured_probe"] = {"kind": "FP32 matrix-core loop from registers "
+                                              "(v_mfma_f32_32x32x2_f32)",
+                                      "TFLOPs": pm["TFLOPs"],
+                                      "frac": round(roof["achieved"] / pm["TFLOPs"], 4)}
 
     out = {
         "metric": METRIC,

@@ -1,6 +1,7 @@
-"""Achievable HBM bandwidth: time a plain streaming copy of known size.
+"""Achievable HBM bandwidth: time a plain streaming copy of known size
+(and, with --mode mfma, the sustained FP32 matrix-core rate).
 
-    python -m paper_1810_11451_amd.probe.hbm [--mib 1024] [--iters 20] [--grid G]
+    python -m paper_1810_11451_amd.probe.hbm [--mib 1024] [--iters 20] [--grid G] [--mode M]
 
 Prints one JSON line with the copy's read+write GB/s.  Under a counter run
 (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE) the same command gives the bytes
@@ -68,6 +69,34 @@ def measure(mib: int = 1024, iters: int = 20, mode: str = "copy", grid: int = 0,
             "variant": variant}
 
 
+def measure_mfma(iters: int = 20000, grid: int = 0, reps: int = 3) -> dict:
+    """Times the FP32 matrix-core loop (v_mfma_f32_32x32x2_f32, four
+    independent chains per wave, two waves per SIMD) with HIP events;
+    returns its sustained TFLOP/s."""
+    import torch
+    if not LIB.exists():
+        raise RuntimeError(f"{LIB} not built")
+    L = ctypes.CDLL(str(LIB))
+    L.bfprobe_mfma.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+    grid = grid or 256 * 2
+    out = torch.empty(grid * 256, dtype=torch.float32, device="cuda")
+    st = torch.cuda.current_stream()
+    if L.bfprobe_mfma(out.data_ptr(), grid, 100, st.cuda_stream) != 0:
+        raise RuntimeError("mfma probe launch failed")
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        L.bfprobe_mfma(out.data_ptr(), grid, iters, st.cuda_stream)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    flops = grid * 4 * iters * 4 * 4096
+    del out
+    return {"probe": "mfma_fp32_32x32x2", "us": round(ms * 1e3, 2),
+            "TFLOPs": round(flops / ms / 1e9, 2), "grid": grid, "iters": iters}
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--mib", type=int, default=1024)
@@ -75,9 +104,12 @@ def main(argv=None) -> int:
     ap.add_argument("--grid", type=int, default=0, help="workgroups (0: 256 CUs x 8)")
     ap.add_argument("--variant", type=int, default=1,
                     help="bit 0 non-temporal, bits 1-2 log2 unroll (default 1: plain nt copy)")
-    ap.add_argument("--mode", default="copy", choices=["copy", "read", "write"])
+    ap.add_argument("--mode", default="copy", choices=["copy", "read", "write", "mfma"])
     a = ap.parse_args(argv)
-    print(json.dumps(measure(a.mib, a.iters, a.mode, a.grid, a.variant)), flush=True)
+    if a.mode == "mfma":
+        print(json.dumps(measure_mfma(grid=a.grid)), flush=True)
+    else:
+        print(json.dumps(measure(a.mib, a.iters, a.mode, a.grid, a.variant)), flush=True)
     return 0
 
 

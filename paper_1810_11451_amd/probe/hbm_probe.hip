@@ -107,3 +107,38 @@ extern "C" int bfprobe_copy(const void *src, void *dst, uint64_t bytes, int grid
 {
     return bfprobe_stream(src, dst, bytes, grid, variant, 0, stream);
 }
+
+// Matrix-core reference: each wave runs `iters` steps of four independent
+// v_mfma_f32_32x32x2_f32 chains from registers (no memory traffic inside
+// the loop), so the measured rate is what the FP32 matrix cores sustain at
+// the clock the chip runs under that load.  Each thread writes one value
+// (out needs grid * 256 floats) so nothing is dropped.
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+__global__ __launch_bounds__(256) void mfma_kernel(float *__restrict__ out, int iters)
+{
+    floatx16 c0 = {}, c1 = {}, c2 = {}, c3 = {};
+    const float a = 1.0f + 1e-7f * (float)threadIdx.x;
+    const float b = 1.0f - 1e-7f * (float)blockIdx.x;
+    for (int i = 0; i < iters; ++i) {
+        c0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c0, 0, 0, 0);
+        c1 = __builtin_amdgcn_mfma_f32_32x32x2f32(b, a, c1, 0, 0, 0);
+        c2 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, a, c2, 0, 0, 0);
+        c3 = __builtin_amdgcn_mfma_f32_32x32x2f32(b, b, c3, 0, 0, 0);
+    }
+    float s = 0.f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+        s += c0[r] + c1[r] + c2[r] + c3[r];
+    out[(size_t)blockIdx.x * 256 + threadIdx.x] = s;
+}
+
+// Flops per call: grid * 4 waves * iters * 4 MFMAs * 4096.
+extern "C" int bfprobe_mfma(float *out, int grid, int iters, void *stream)
+{
+    if (!out || grid <= 0 || iters <= 0)
+        return -1;
+    hipLaunchKernelGGL(mfma_kernel, dim3(grid), dim3(256), 0, static_cast<hipStream_t>(stream), out,
+                       iters);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
