@@ -272,6 +272,16 @@ def bf_apply_packed(plan: Plan, w_ids, f, S_base, s_off, R_base, prec: int = BF_
     s_off = np.ascontiguousarray(np.asarray(s_off), dtype=np.int64)
     if s_off.shape != (n,):
         raise ValueError("s_off must have one entry per item")
+    # Tensors are checked for size: the library sees only addresses.
+    if hasattr(S_base, "numel"):
+        live = f > 0
+        need = int(np.max(s_off[live] + f[live].astype(np.int64) * BF_B)) if np.any(live) else 0
+        if not S_base.is_contiguous() or S_base.numel() * S_base.element_size() < need * 8:
+            raise ValueError(f"S_base must be contiguous and hold {need} complex64 values")
+    if hasattr(R_base, "numel"):
+        need = n * BF_M * BF_B
+        if not R_base.is_contiguous() or R_base.numel() * R_base.element_size() < need * 8:
+            raise ValueError(f"R_base must be contiguous and hold {need} complex64 values")
     _check(lib().bf_apply_packed(plan.handle, n, w_ids.ctypes.data, f.ctypes.data, _ptr(S_base),
                                  s_off.ctypes.data, _ptr(R_base), int(prec), _stream(stream)),
            "bf_apply_packed")
@@ -515,10 +525,27 @@ def bf_filter_create(h, stream=None) -> Filter:
     return Filter(out.value, int(h.shape[0]))
 
 
+def _filter_buffer(a, batch: int, name: str) -> int:
+    """Device address of a filter buffer: an int, or a tensor, which must be
+    contiguous and hold at least batch x 2048 complex64 values."""
+    if not hasattr(a, "data_ptr"):
+        return int(a)
+    need = int(batch) * N_FILTER * 8
+    if not a.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if str(a.dtype) not in ("torch.complex64", "torch.float32"):
+        raise ValueError(f"{name} must be complex64 (or float32 pairs), got {a.dtype}")
+    have = a.numel() * a.element_size()
+    if have < need:
+        raise ValueError(f"{name} holds {have} bytes, {need} needed for {batch} blocks")
+    return a.data_ptr()
+
+
 def bf_filter_apply(flt: Filter, batch: int, x, y, stream=None) -> None:
-    """x, y: device pointers (int) or torch tensors of complex64 [batch, 2048]."""
-    xp = x.data_ptr() if hasattr(x, "data_ptr") else int(x)
-    yp = y.data_ptr() if hasattr(y, "data_ptr") else int(y)
+    """x, y: device pointers (int) or contiguous torch tensors of complex64
+    [batch, 2048] (checked for size)."""
+    xp = _filter_buffer(x, batch, "x")
+    yp = _filter_buffer(y, batch, "y")
     _check(lib().bf_filter_apply(flt.handle, int(batch), xp, yp, _stream(stream)), "bf_filter_apply")
 
 

@@ -168,3 +168,39 @@ def test_python_wrapper_raises_with_detail(L):
     with pytest.raises(bf.BfError) as ei:
         bf.bf_plan_create(np.zeros((1, 64, 40), np.complex64))
     assert ei.value.status == bf.BF_ERR_INVALID and "f_max" in ei.value.detail
+
+
+def test_filter_binding_checks_tensor_sizes():
+    """The binding refuses tensors that cannot hold the batch (CPU tensors
+    stand in: the check happens before anything reaches the library)."""
+    import torch
+    small = torch.zeros((2, bf.N_FILTER), dtype=torch.complex64)
+    ok = torch.zeros((3, bf.N_FILTER), dtype=torch.complex64)
+    with pytest.raises(ValueError, match="bytes"):
+        bf._filter_buffer(small, 3, "x")
+    assert bf._filter_buffer(ok, 3, "x") == ok.data_ptr()
+    with pytest.raises(ValueError, match="contiguous"):
+        bf._filter_buffer(ok.t(), 1, "x")
+    with pytest.raises(ValueError, match="complex64"):
+        bf._filter_buffer(torch.zeros((3, bf.N_FILTER), dtype=torch.float64), 1, "x")
+    assert bf._filter_buffer(12345, 7, "x") == 12345
+
+
+def test_packed_binding_checks_tensor_sizes():
+    """bf_apply_packed refuses S or R tensors too small for the batch before
+    the library is called (plan handle unused: the check comes first)."""
+    import torch
+
+    class NoPlan:
+        handle = None
+
+    f = np.array([2, 0, 3], np.int32)
+    s_off = np.array([0, 0, 120], np.int64)      # last item ends at 120 + 180 = 300
+    w = np.zeros(3, np.int32)
+    S_small = torch.zeros(299, dtype=torch.complex64)
+    R_ok = torch.zeros((3, bf.BF_M, bf.BF_B), dtype=torch.complex64)
+    with pytest.raises(ValueError, match="S_base"):
+        bf.bf_apply_packed(NoPlan(), w, f, S_small, s_off, R_ok)
+    S_ok = torch.zeros(300, dtype=torch.complex64)
+    with pytest.raises(ValueError, match="R_base"):
+        bf.bf_apply_packed(NoPlan(), w, f, S_ok, s_off, R_ok[:2])
