@@ -101,8 +101,10 @@ static bf_status default_variants(bf_plan p)
                 v = bf_variant{3, 0, 0, 2};   // wave-specialised, 8 producers, depth 2, as given
             else if (full && fp32)
                 v = bf_variant{3, 0, 0, 5};   // wave-specialised, 12 producers, depth 2, as given
+            else if (full && (pr == BF_FP16 || pr == BF_BF16))
+                v = bf_variant{3, 0, 0, 4};   // plain 16-bit: wave-specialised, 12 producers
             else if (full)
-                v = bf_variant{3, 0, 0, 4};   // 16-bit forms: wave-specialised, 12 producers
+                v = bf_variant{2, 2, 0, 0};   // split 16-bit: streaming, 2 workgroups per CU
             else
                 v = bf_variant{0, 0, 0, 0};   // mixed or small f: one per workgroup
             p->table[pr][b] = v;
