@@ -188,10 +188,10 @@ def kernel_symbol(prec: int, schedule: int) -> str:
     return {0: "apply_lp_single", 2: "apply_lp_stream", 3: "apply_lp_ws"}[schedule]
 
 
-def load_traffic(workload_key: str, symbol: str | None = None):
+def load_traffic(workload_key: str, symbol: str | None = None, variant=None):
     """HBM traffic per launch from committed rocprofv3 counter runs, if they
-    were taken on the current kernel source (and, given `symbol`, on that
-    kernel); else None."""
+    were taken on the current kernel source (and, given `symbol` and
+    `variant`, on that kernel in that launch variant); else None."""
     path = ROOT / "profiles" / "traffic.json"
     if not path.exists():
         return None
@@ -203,6 +203,8 @@ def load_traffic(workload_key: str, symbol: str | None = None):
     if not entry or entry.get("kernel_sha") != kernel_sha(workload_key):
         return None
     if symbol is not None and entry.get("kernel") != symbol:
+        return None
+    if variant is not None and entry.get("variant") != ":".join(str(int(x)) for x in variant):
         return None
     return entry.get("traffic_bytes_per_launch")
 
@@ -482,7 +484,7 @@ def main(argv=None) -> int:
     ridge = peak_flops / (PEAK_HBM_GBS * 1e9)
     key = f"config{args.config}-{args.prec}"
     sched = launched_schedule(prec, variant[0])
-    traffic = load_traffic(key, kernel_symbol(prec, sched))
+    traffic = load_traffic(key, kernel_symbol(prec, sched), variant)
     if ai >= ridge:
         ach = flops / kern_s / 1e12
         roof = {"bound": "mfma", "achieved": round(ach, 2), "peak": peak_flops / 1e12,
@@ -492,9 +494,7 @@ def main(argv=None) -> int:
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(ach / PEAK_HBM_GBS, 4)}
     roof["traffic"] = traffic
-    roof["kernel"] = ("apply_fp32_" if not lp else "apply_lp_") + \
-        ("3m_" if prec == bf.BF_FP32_3M else "") + \
-        {0: "single", 1: "claim", 2: "stream", 3: "ws"}[sched]
+    roof["kernel"] = kernel_symbol(prec, sched)
     roof["kernel_us_mean"] = round(kern_s * 1e6, 2)
     roof["kernel_us_p50"] = round(float(np.median(kern_ms)) * 1e3, 2)
     roof["kernel_us_min"] = round(float(np.min(kern_ms)) * 1e3, 2)

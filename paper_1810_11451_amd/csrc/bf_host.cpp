@@ -86,10 +86,11 @@ static void release_slot(StagingSlot &s)
     s = StagingSlot{};
 }
 
-// Defaults measured on MI355X: full-width batches (mean f 36) run the
-// wave-specialised schedule, and so do the three-product form's batches of
-// mixed f; other batches of mixed or small f run one product per
-// workgroup; all in the order given.
+// Defaults measured on MI355X at steady state: full-width batches (mean f
+// 36) run the wave-specialised schedule, except the split 16-bit forms,
+// which stream; the three-product form's batches of mixed f are
+// wave-specialised too; other batches of mixed or small f run one product
+// per workgroup; all in the order given.
 static bf_status default_variants(bf_plan p)
 {
     for (int pr = 0; pr < kPrecCount; ++pr)

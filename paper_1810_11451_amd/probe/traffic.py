@@ -10,8 +10,9 @@ FETCH_SIZE and WRITE_SIZE (KiB per dispatch, from `rocprofv3 --pmc ...
 --kernel, then each is scaled by the factor that makes the same counter
 read the known traffic of the plain copy probe (`probe/hbm.py`, which
 reads and writes --copy-bytes per dispatch).  The result is stored in
-profiles/traffic.json under --key, with the hash of the kernel sources, so
-that bench.py reports it only while the kernels are unchanged.
+profiles/traffic.json under --key, with the hash of the kernel sources and
+the launch variant (--variant), so that bench.py reports it only while the
+kernels and the variant it launches are unchanged.
 """
 from __future__ import annotations
 
@@ -86,6 +87,8 @@ def main(argv=None) -> int:
     ap.add_argument("--copy-write", required=True)
     ap.add_argument("--copy-bytes", type=int, required=True)
     ap.add_argument("--algorithmic-bytes", type=int, required=True)
+    ap.add_argument("--variant", default=None,
+                    help="launch variant the counters were taken on, schedule:wg_per_cu:order:store")
     ap.add_argument("--command", default="")
     a = ap.parse_args(argv)
 
@@ -110,6 +113,8 @@ def main(argv=None) -> int:
         "traffic_over_algorithmic": round((fetch_b + write_b) / a.algorithmic_bytes, 4),
         "command": a.command,
     }
+    if a.variant is not None:
+        entry["variant"] = a.variant
     data = json.loads(TRAFFIC_JSON.read_text()) if TRAFFIC_JSON.exists() else {}
     data[a.key] = entry
     TRAFFIC_JSON.parent.mkdir(exist_ok=True)

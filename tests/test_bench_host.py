@@ -1,5 +1,5 @@
 """Host-side helpers of bench.py (CPU only): which kernel a variant runs,
-and that recorded traffic is only used for that kernel."""
+and that recorded traffic is only used for that kernel and launch variant."""
 import json
 
 import bench
@@ -22,7 +22,7 @@ def test_launched_schedule_and_symbol():
 
 def test_traffic_entry_requires_matching_kernel(tmp_path, monkeypatch):
     entry = {"kernel_sha": bench.kernel_sha("configX-fp32"), "kernel": "apply_fp32_ws",
-             "traffic_bytes_per_launch": 123}
+             "variant": "3:0:0:2", "traffic_bytes_per_launch": 123}
     root = tmp_path
     (root / "profiles").mkdir()
     (root / "profiles" / "traffic.json").write_text(json.dumps({"configX-fp32": entry}))
@@ -30,3 +30,6 @@ def test_traffic_entry_requires_matching_kernel(tmp_path, monkeypatch):
     assert bench.load_traffic("configX-fp32", "apply_fp32_ws") == 123
     assert bench.load_traffic("configX-fp32", "apply_fp32_single") is None
     assert bench.load_traffic("configY-fp32", "apply_fp32_ws") is None
+    # the variant the counters were taken on must match the launched one
+    assert bench.load_traffic("configX-fp32", "apply_fp32_ws", (3, 0, 0, 2)) == 123
+    assert bench.load_traffic("configX-fp32", "apply_fp32_ws", (3, 0, 0, 1)) is None
