@@ -523,6 +523,16 @@ def main(argv=None) -> int:
                                               "(v_mfma_f32_32x32x2_f32)",
                                       "TFLOPs": pm["TFLOPs"],
                                       "frac": round(roof["achieved"] / pm["TFLOPs"], 4)}
+        # The kernel also moves its bytes; on this device the measured copy
+        # rate, not the spec-sheet one, sets the memory floor.
+        pc = probe_copy()
+        if pm is not None and pc is not None:
+            t_mfma = flops / (pm["TFLOPs"] * 1e12) * 1e6
+            t_hbm = nbytes / (pc["GBps"] * 1e9) * 1e6
+            roof["measured_floors_us"] = {
+                "mfma_probe": round(t_mfma, 1), "hbm_copy_probe": round(t_hbm, 1),
+                "copy_probe_GBps": pc["GBps"],
+                "slower_floor_over_kernel": round(max(t_mfma, t_hbm) / (kern_s * 1e6), 4)}
 
     out = {
         "metric": METRIC,
