@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark: batched beamforming R = W x S on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--config 2] [--prec fp32]
+    python bench.py [--steps K] [--warmup W] [--workload full-width] [--prec fp32_3m]
 
 A step is one bf_apply over the whole batch (descriptor packing and upload,
 one kernel launch), with S already resident in HBM.  The default workload
@@ -39,7 +39,10 @@ PEAK_FP32_TFLOPS = 157.3
 PEAK_LP_TFLOPS = 2500.0
 PRECS = {"fp32": bf.BF_FP32, "fp32_3m": bf.BF_FP32_3M, "fp16": bf.BF_FP16, "bf16": bf.BF_BF16,
          "fp16x2": bf.BF_FP16X2, "bf16x2": bf.BF_BF16X2}
-CONFIGS = {1: wl.config1, 2: wl.config2, 3: wl.config3, 4: wl.config4, 5: None, 6: None}
+# Workloads: batches of products (generator), the serving replay and the
+# filter stage (None: handled apart).
+WORKLOADS = {"single-w": wl.single_w_batch, "full-width": wl.full_width_batch,
+             "uneven": wl.uneven_batch, "gain": wl.gain_batch, "serving": None, "filter": None}
 FILTER_METRIC = "blocks/s + %roofline for the batched 2048-point FFT -> MULT -> IFFT filter stage"
 from paper_1810_11451_amd.probe.traffic import kernel_sha  # noqa: E402
 
@@ -356,7 +359,7 @@ def filter_bench(args, torch) -> dict:
            "latency_us": {"p50": round(float(np.percentile(kern_ms, 50)) * 1e3, 2),
                           "p99": round(float(np.percentile(kern_ms, 99)) * 1e3, 2)},
            "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                        "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": load_traffic("config6-filter"),
+                        "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": load_traffic("filter"),
                         "kernel": "filter_kernel", "kernel_us_mean": round(kern_s * 1e6, 2),
                         "kernel_timing": "HIP events on the launch stream around groups of 10 back-to-back launches",
                         "algorithmic": {"bytes_per_launch": nbytes, "flops_conventional": flops_conv,
@@ -376,7 +379,7 @@ def main(argv=None) -> int:
     # warm-up covers that transient.
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--config", type=int, default=2, choices=sorted(CONFIGS))
+    ap.add_argument("--workload", default="full-width", choices=list(WORKLOADS))
     ap.add_argument("--prec", default="fp32_3m", choices=sorted(PRECS),
                     help="arithmetic form (default: FP32, three real products per complex one)")
     ap.add_argument("--no-compare", action="store_true",
@@ -407,10 +410,10 @@ def main(argv=None) -> int:
     from paper_1810_11451_amd.device import DeviceBatch
 
     torch.cuda.set_device(0)
-    if args.config == 6:
+    if args.workload == "filter":
         print(json.dumps(filter_bench(args, torch)), flush=True)
         return 0
-    if args.config == 5:
+    if args.workload == "serving":
         res = serve_bench(args, torch)
         fp = res["fp32"]
         out = {"metric": METRIC, "value": fp["complex_gflops"], "unit": "complex GFLOP/s",
@@ -425,8 +428,8 @@ def main(argv=None) -> int:
         print(json.dumps(out), flush=True)
         return 0
     prec = PRECS[args.prec]
-    batch = CONFIGS[args.config]()
-    print(f"[bench] config {args.config}: {batch.name}, prec {args.prec}", file=sys.stderr, flush=True)
+    batch = WORKLOADS[args.workload]()
+    print(f"[bench] {args.workload}: {batch.name}, prec {args.prec}", file=sys.stderr, flush=True)
     plan = bf.bf_plan_create(batch.W, bf.BF_PREC_BIT(prec))
     db = DeviceBatch(batch, copies=args.copies, fill_r=None)
     stream = torch.cuda.current_stream()
@@ -488,7 +491,7 @@ def main(argv=None) -> int:
     lp = prec not in (bf.BF_FP32, bf.BF_FP32_3M)
     peak_flops = (PEAK_LP_TFLOPS if lp else PEAK_FP32_TFLOPS) * 1e12
     ridge = peak_flops / (PEAK_HBM_GBS * 1e9)
-    key = f"config{args.config}-{args.prec}"
+    key = f"{args.workload}-{args.prec}"
     sched = launched_schedule(prec, variant[0])
     traffic = load_traffic(key, kernel_symbol(prec, sched), variant)
     if ai >= ridge:

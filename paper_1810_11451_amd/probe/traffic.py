@@ -1,6 +1,6 @@
 """HBM traffic per launch from rocprofv3 counter runs.
 
-    python -m paper_1810_11451_amd.probe.traffic --key config2-fp32 \\
+    python -m paper_1810_11451_amd.probe.traffic --key full-width-fp32 \\
         --kernel apply_fp32 --fetch K_FETCH.csv --write K_WRITE.csv \\
         --copy-fetch C_FETCH.csv --copy-write C_WRITE.csv --copy-bytes 1073741824 \\
         --algorithmic-bytes 786432000 --command "..."

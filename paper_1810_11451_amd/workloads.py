@@ -172,7 +172,7 @@ def _uniform_f_batch(name, W, w_ids, f_val, S3) -> Batch:
                  np.ascontiguousarray(S3.reshape(-1), dtype=np.complex64), s_off)
 
 
-def config1(seed: int = 1, n: int = 100) -> Batch:
+def single_w_batch(seed: int = 1, n: int = 100) -> Batch:
     """One CN(0,1) W of 64 x 8 and n CN(0,1) S of 8 x 60."""
     rng = np.random.default_rng(seed)
     W = cn01_pool(rng, 1, 8)
@@ -181,7 +181,7 @@ def config1(seed: int = 1, n: int = 100) -> Batch:
     return _uniform_f_batch("single-W 64x8, 100 S 8x60, CN(0,1)", W, w_ids, 8, S3)
 
 
-def config2(seed: int = 2, n: int = 16384, n_w: int = 64) -> Batch:
+def full_width_batch(seed: int = 2, n: int = 16384, n_w: int = 64) -> Batch:
     """Pool of n_w unit-norm W 64 x 36; n normalised 256-QAM S 36 x 60."""
     rng = np.random.default_rng(seed)
     W = unit_norm_pool(rng, n_w, F_MAX)
@@ -190,7 +190,7 @@ def config2(seed: int = 2, n: int = 16384, n_w: int = 64) -> Batch:
     return _uniform_f_batch(f"full-width f=36, {n} S, pool {n_w} W", W, w_ids, F_MAX, S3)
 
 
-def config3(seed: int = 3, n: int = 8192, n_w: int = 256) -> Batch:
+def uneven_batch(seed: int = 3, n: int = 8192, n_w: int = 256) -> Batch:
     """Uneven batch: f ~ U{1..36}, pool of n_w unit-norm W 64 x 36."""
     rng = np.random.default_rng(seed)
     W = unit_norm_pool(rng, n_w, F_MAX)
@@ -204,7 +204,7 @@ def config3(seed: int = 3, n: int = 8192, n_w: int = 256) -> Batch:
     return Batch(f"uneven f~U(1..36), {n} S, pool {n_w} W", W, w_ids, f, S, s_off)
 
 
-def config4(seed: int = 4, n: int = 16384, n_w: int = 64) -> Batch:
+def gain_batch(seed: int = 4, n: int = 16384, n_w: int = 64) -> Batch:
     """Config-2 workload with per-request gains 10**U(-3, 3) folded into S."""
     rng = np.random.default_rng(seed)
     W = unit_norm_pool(rng, n_w, F_MAX)

@@ -159,8 +159,8 @@ def pin_exact_integer(run, seed=17):
         assert np.array_equal(R[t].real, rr) and np.array_equal(R[t].imag, ri), f"item {t}"
 
 
-def pin_matmul_config1(run, tol=1e-14):
-    b = wl.config1()
+def pin_matmul_single_w(run, tol=1e-14):
+    b = wl.single_w_batch()
     R = run(b.W, b.w_ids, b.f, b.S, b.s_off, wl.M, wl.B)
     W = b.W[0].astype(np.complex128)
     for t in range(b.n):
@@ -170,7 +170,7 @@ def pin_matmul_config1(run, tol=1e-14):
 
 
 ALL_PINS = [pin_fraction_bruteforce, pin_hand_example, pin_identity, pin_f_zero, pin_dft,
-            pin_parseval, pin_linearity, pin_exact_integer, pin_matmul_config1]
+            pin_parseval, pin_linearity, pin_exact_integer, pin_matmul_single_w]
 
 
 def c_runner(oracle_mod, lib=None, threads=2):

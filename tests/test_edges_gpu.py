@@ -66,7 +66,7 @@ def test_four_times_full_width_sampled(form):
     the oracle."""
     torch = require_gpu()
     n = 4 * 16384
-    b = wl.config2(seed=903, n=n)
+    b = wl.full_width_batch(seed=903, n=n)
     plan = bf.bf_plan_create(b.W, bf.BF_PREC_BIT(FORMS[form]))
     db = DeviceBatch(b, fill_r=float("nan"))
     announce(f"four times full width form={form} n={n}")

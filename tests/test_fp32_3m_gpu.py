@@ -70,7 +70,7 @@ def test_dft_and_identity_within_bar():
 
 
 def test_full_width_workload_sampled():
-    b = wl.config2()
+    b = wl.full_width_batch()
     announce(f"3m full-width n={b.n}")
     R = run_batch(b, prec=P)
     assert not np.any(np.isnan(R.view(np.float32)))
@@ -81,7 +81,7 @@ def test_full_width_workload_sampled():
 
 
 def test_uneven_workload_all_items():
-    b = wl.config3()
+    b = wl.uneven_batch()
     announce(f"3m uneven n={b.n}")
     R = run_batch(b, prec=P)
     err, _ = rel_errors(b, R)

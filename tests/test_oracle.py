@@ -60,14 +60,14 @@ def test_threads_do_not_change_result(oracle_mod):
 
 
 def test_item_subset(oracle_mod):
-    b = wl.config1()
+    b = wl.single_w_batch()
     full = oracle_mod.apply(b)
     sub = oracle_mod.apply(b, items=[3, 0, 99])
     assert np.array_equal(sub, full[[3, 0, 99]])
 
 
 def test_oracle_rejects_bad_arguments(oracle_mod):
-    b = wl.config1(n=3)
+    b = wl.single_w_batch(n=3)
     with pytest.raises(ValueError):
         oracle_mod.apply_arrays(b.W, np.array([0, 1, 0], np.int32), b.f, b.S, b.s_off)
     with pytest.raises(ValueError):
@@ -94,7 +94,7 @@ def test_workload_shapes_match_paper(golden_dir):
     assert wl.M == g["antennas"] == int(np.prod(g["array"]))
     assert wl.B == g["resource_elements"]
     assert wl.F_MAX == g["f_max"]
-    b = wl.config2(n=8)
+    b = wl.full_width_batch(n=8)
     assert b.W.shape == (64, 64, 36) and b.S.shape == (8 * 36 * 60,)
 
 
@@ -108,11 +108,11 @@ def test_input_distributions():
     assert np.allclose(np.linalg.norm(W, axis=1), 1.0, atol=1e-6)
     c = wl.cn01(rng, (200000,))
     assert abs(np.var(c.real) - 0.5) < 0.01 and abs(np.var(c.imag) - 0.5) < 0.01
-    b4 = wl.config4(n=64)
+    b4 = wl.gain_batch(n=64)
     assert np.all(b4.gains >= 1e-3) and np.all(b4.gains <= 1e3)
 
 
 def test_config_seeds_are_deterministic():
-    a, b = wl.config3(n=50), wl.config3(n=50)
+    a, b = wl.uneven_batch(n=50), wl.uneven_batch(n=50)
     assert np.array_equal(a.S, b.S) and np.array_equal(a.f, b.f) and np.array_equal(a.w_ids, b.w_ids)
     assert a.flops() == 8 * 64 * 60 * int(a.f.sum())

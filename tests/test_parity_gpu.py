@@ -42,9 +42,9 @@ WS_VARIANTS = ["ws-sorted", "ws-8-producers", "ws-8-producers-depth-2", "ws-8-pr
 
 
 @pytest.mark.parametrize("vname", sorted(VARIANTS))
-def test_config1_fp32(vname):
-    b = wl.config1()
-    announce(f"config1 fp32 variant={vname} n={b.n}")
+def test_single_w_fp32(vname):
+    b = wl.single_w_batch()
+    announce(f"single-W fp32 variant={vname} n={b.n}")
     R = run_batch(b, variant=VARIANTS[vname])
     err, _ = rel_errors(b, R)
     assert np.max(err) <= FP32_TOL, f"max rel err {np.max(err):.3g}"
@@ -142,7 +142,7 @@ def test_dft_closed_form():
 
 def test_nothing_written_on_invalid_batch():
     torch = require_gpu()
-    b = wl.config1(n=10)
+    b = wl.single_w_batch(n=10)
     plan = bf.bf_plan_create(b.W)
     db = DeviceBatch(b)
     w_ids = b.w_ids.copy()
@@ -182,7 +182,7 @@ def test_two_streams_and_plan_reuse():
 
 def test_graph_replay_matches_direct():
     torch = require_gpu()
-    b = wl.config3(n=700)
+    b = wl.uneven_batch(n=700)
     plan = bf.bf_plan_create(b.W)
     direct = DeviceBatch(b)
     direct.apply(plan)
@@ -206,7 +206,7 @@ def test_graph_replay_matches_direct():
 
 def test_autotune_and_cache(tmp_path):
     require_gpu()
-    b = wl.config3(n=2000)
+    b = wl.uneven_batch(n=2000)
     plan = bf.bf_plan_create(b.W)
     db = DeviceBatch(b)
     announce("autotune")
@@ -232,7 +232,7 @@ def test_autotune_and_cache(tmp_path):
 
 def test_full_width_workload_sampled():
     """16384 products, f = 36, pool of 64: the benchmark's workload and launch."""
-    b = wl.config2()
+    b = wl.full_width_batch()
     announce(f"full-width n={b.n}")
     R = run_batch(b)
     assert not np.any(np.isnan(R.view(np.float32))), "some R not written"
@@ -244,7 +244,7 @@ def test_full_width_workload_sampled():
 
 def test_uneven_workload_all_items():
     """8192 products with f ~ U{1..36} from a pool of 256: every item checked."""
-    b = wl.config3()
+    b = wl.uneven_batch()
     announce(f"uneven n={b.n}")
     R = run_batch(b)
     err, _ = rel_errors(b, R)

@@ -99,7 +99,7 @@ def test_all_forms_from_one_plan():
 def test_gain_workload_sampled(form):
     """16384 products of 64x36 by 36x60 with gains 10^U(-3,3), the launch the
     benchmark times; 512 seeded products checked."""
-    b = wl.config4()
+    b = wl.gain_batch()
     announce(f"gain workload n={b.n} form={form}")
     R = run_batch(b, prec=LP[form])
     assert not np.any(np.isnan(R.view(np.float32)))

@@ -11,6 +11,6 @@ def test_comment_edits_keep_the_hash_code_edits_change_it():
 
 
 def test_kernel_sha_is_stable_and_keyed():
-    assert traffic.kernel_sha("config2-fp32_3m") == traffic.kernel_sha("config3-fp32_3m")
-    assert traffic.kernel_sha("config6-filter") != traffic.kernel_sha("config2-fp32_3m")
-    assert len(traffic.kernel_sha("config6-filter")) == 16
+    assert traffic.kernel_sha("full-width-fp32_3m") == traffic.kernel_sha("uneven-fp32_3m")
+    assert traffic.kernel_sha("filter") != traffic.kernel_sha("full-width-fp32_3m")
+    assert len(traffic.kernel_sha("filter")) == 16
