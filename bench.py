@@ -483,6 +483,17 @@ def main(argv=None) -> int:
                    "tflops": round(batch.flops() / t4 / 1e12, 2),
                    "frac": round(batch.flops() / t4 / 1e12 / PEAK_FP32_TFLOPS, 4),
                    "variant": list(v4)}
+    split = None
+    if prec == bf.BF_FP32_3M and not args.no_compare:
+        # The 2-term split FP16 form (FP32-class accuracy from 16-bit matrix
+        # cores) on the same workload, kernel time only, against this form.
+        plans = bf.bf_plan_create(batch.W, bf.BF_PREC_BIT(bf.BF_FP16X2))
+        ks = kernel_time_graph(plans, db, batch, bf.BF_FP16X2, K, args.copies, torch, stream)
+        vs = bf.bf_get_variant(plans, bf.BF_FP16X2, bf.batch_bucket(batch.f))
+        plans.close()
+        split = {"prec": "fp16x2", "kernel_us_mean": round(float(np.mean(ks)) * 1e3, 2),
+                 "hbm_gbs_equiv": round(batch.bytes_moved() / (float(np.mean(ks)) / 1e3) / 1e9, 1),
+                 "variant": list(vs)}
 
     flops = batch.flops()
     nbytes = batch.bytes_moved()
@@ -568,6 +579,9 @@ def main(argv=None) -> int:
                                     "flops counted as 8 per complex multiply-add")
     if compare is not None:
         out["compare_fp32_four_product"] = compare
+    if split is not None:
+        split["speedup_over_this_form"] = round(kern_s * 1e6 / split["kernel_us_mean"], 3)
+        out["compare_split_fp16x2"] = split
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(batch, args.cpu_seconds)
         out["cpu_other"] = cpu_extra(batch, min(3.0, args.cpu_seconds))
