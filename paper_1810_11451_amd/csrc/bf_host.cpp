@@ -448,8 +448,11 @@ bfk::LaunchCfg choose_launch(bf_plan p, bf_prec prec, int n, int max_f, bool vec
     cfg.vec16 = vec16;
     if (cfg.schedule == 3 && !vec16)   // its producers move S in 16-byte chunks only
         cfg.schedule = prec == BF_FP32_3M ? 0 : 2;
-    if (cfg.schedule == 3 && lp && p->f_max < 1)   // no 16-bit operands to load
-        cfg.schedule = 2;
+    // A pool without columns has no W operands: every product is the empty
+    // sum.  The wave-specialised kernels load W unconditionally, so such
+    // batches run the schedules whose W loads are guarded.
+    if (cfg.schedule == 3 && p->f_max < 1)
+        cfg.schedule = lp ? 2 : 0;
     cfg.stage = cfg.schedule == 3 || prec == BF_FP32_3M || (v.store >= 1 && cfg.schedule != 1);
     // For schedule 3 the store field selects producer waves and prefetch
     // depth: 0 -> (4, 1), 1 -> (8, 1), 2 -> (8, 2), 3 -> (8, 3), 4 -> (12, 1),

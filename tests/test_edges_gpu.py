@@ -77,3 +77,29 @@ def test_four_times_full_width_sampled(form):
     err = orc.rel_frobenius(R, orc.apply(b, items=items))
     assert np.max(err) <= BAR[form], f"max rel err {np.max(err):.3g}"
     plan.close()
+
+
+@pytest.mark.parametrize("variant", [None, (3, 0, 0, 2), (3, 0, 0, 5), (2, 2, 0, 0), (1, 2, 1, 0)])
+@pytest.mark.parametrize("form", sorted(FORMS))
+def test_pool_without_columns(form, variant):
+    """A pool with f_max = 0 (every product is the empty sum): the plan is
+    valid in every form, and R comes back all zeros under the default and
+    under forced variants (the wave-specialised ones, which load W
+    unconditionally, are routed to schedules that do not)."""
+    torch = require_gpu()
+    n = 70
+    W = np.zeros((2, bf.BF_M, 0), np.complex64)
+    R = torch.empty((n, bf.BF_M, bf.BF_B), dtype=torch.complex64, device="cuda")
+    R.view(torch.float32).fill_(float("nan"))
+    r_ptrs = (R.data_ptr() + np.arange(n, dtype=np.uint64) * (bf.BF_M * bf.BF_B * 8)).astype(np.uint64)
+    plan = bf.bf_plan_create(W, bf.BF_PREC_BIT(FORMS[form]))
+    assert bf.bf_plan_info(plan)[1] == 0
+    if variant is not None:
+        for bk in range(5):
+            bf.bf_set_variant(plan, FORMS[form], bk, *variant)
+    announce(f"pool with f_max = 0 form={form} variant={variant}")
+    bf.bf_apply(plan, np.arange(n, dtype=np.int32) % 2, np.zeros(n, np.int32), np.zeros(n, np.uint64),
+                r_ptrs, FORMS[form])
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(R.view(torch.float32)).item() == 0
+    plan.close()
