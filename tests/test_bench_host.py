@@ -33,3 +33,17 @@ def test_traffic_entry_requires_matching_kernel(tmp_path, monkeypatch):
     # the variant the counters were taken on must match the launched one
     assert bench.load_traffic("configX-fp32", "apply_fp32_ws", (3, 0, 0, 2)) == 123
     assert bench.load_traffic("configX-fp32", "apply_fp32_ws", (3, 0, 0, 1)) is None
+
+
+def test_more_than_one_gpu_is_refused(capsys):
+    """The library uses one GPU: --gpus N > 1 exits with status 2 and says why,
+    before touching a device."""
+    assert bench.main(["--gpus", "2"]) == 2
+    assert "one GPU" in capsys.readouterr().err
+
+
+def test_workload_names():
+    """Workloads are named by what they are; each batch generator exists."""
+    assert set(bench.WORKLOADS) == {"single-w", "full-width", "uneven", "gain", "serving", "filter"}
+    for name, gen in bench.WORKLOADS.items():
+        assert (gen is None) == (name in ("serving", "filter"))
