@@ -865,14 +865,19 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
 
 // Producer-side staging over kProd waves, in 16-byte chunks with clamped
 // indices: S of one product and, for the three-product form (kW), the
-// operands of its W (the plan's 2 x pairs x 3 x 64 floats, 96 pairs chunks).
-constexpr int kWChunksMax = kPairsMax * 96;
+// operands of its W.  The plan holds them as 2 halves x pairs x 3 planes x
+// 64 floats (Wr, Wi, Wr + Wi; 48 chunks per pair); the producers load only
+// the Wr and Wi planes, in units of one 4-lane chunk of each (2 halves x
+// pairs x 16 units), and form the third plane with one FP32 add, which is
+// exactly how the plan rounds it.
+constexpr int kWUnitsMax = kPairsMax * 32;
 constexpr int kWFloatsMax = kPairsMax * 384;
 
 template <int kProd, bool kW = false>
 struct PRegs {
     static constexpr int kN = (kFMax * kB / 2 + 64 * kProd - 1) / (64 * kProd);
-    static constexpr int kNW = kW ? (kWChunksMax + 64 * kProd - 1) / (64 * kProd) : 1;
+    static constexpr int kWRounds = (kWUnitsMax + 64 * kProd - 1) / (64 * kProd);
+    static constexpr int kNW = kW ? 2 * kWRounds : 1;
     f4v v[kN];
     f4v w[kNW];
 };
@@ -887,45 +892,60 @@ __device__ __forceinline__ void p_load_s(PRegs<kProd, kW> &r, const float2 *__re
         r.v[u] = __builtin_nontemporal_load(src + min(ptid + u * 64 * kProd, last));
 }
 
-// W operands (L2-resident pool: plain loads, no streaming hint).  Each
-// antenna half holds pairs * 48 chunks; only the first `need` (>= 1) pairs
-// of each half are used by the product, and chunks of later pairs
-// load the last used chunk of their half again (a cache hit; the LDS slots
-// they fill feed no product).
+// Chunk index (in the plan's layout) of the Wr chunk of unit u: half h,
+// pair q, 4-lane group j; the Wi chunk follows 16 chunks later and the
+// Wr + Wi chunk 32 later.
+__device__ __forceinline__ int w_unit_chunk(int u, int pairs)
+{
+    const int per_half = pairs * 16;
+    const int h = u >= per_half ? 1 : 0;
+    const int rem = u - h * per_half;
+    return h * pairs * 48 + (rem >> 4) * 48 + (rem & 15);
+}
+
+// W operands (L2-resident pool: plain loads, no streaming hint), Wr and Wi
+// planes only.  Only the first `need` (>= 1) pairs of each half are used by
+// the product; units of later pairs load the last used pair's unit again
+// (a cache hit; nothing of them reaches LDS).  Units past the end repeat
+// the last unit.
 template <int kProd>
 __device__ __forceinline__ void p_load_w(PRegs<kProd, true> &r, const float *__restrict__ wsrc, int pairs,
                                          int need, int ptid)
 {
     g_cf4v *src = (g_cf4v *)wsrc;
-    const int half = pairs * 48;
-    if (need >= pairs) {   // uniform: every pair is used
+    const int units = pairs * 32;
+    const int last_q = min(pairs, need) - 1;
 #pragma unroll
-        for (int u = 0; u < PRegs<kProd, true>::kNW; ++u)
-            r.w[u] = src[min(ptid + u * 64 * kProd, 2 * half - 1)];
-        return;
-    }
-    const int used = need * 48 - 1;
-#pragma unroll
-    for (int u = 0; u < PRegs<kProd, true>::kNW; ++u) {
-        const int c = min(ptid + u * 64 * kProd, 2 * half - 1);
-        const int h = c >= half ? half : 0;
-        r.w[u] = src[h + min(c - h, used)];
+    for (int k = 0; k < PRegs<kProd, true>::kWRounds; ++k) {
+        int u = min(ptid + k * 64 * kProd, units - 1);
+        const int per_half = pairs * 16;
+        const int h = u >= per_half ? 1 : 0;
+        const int rem = u - h * per_half;
+        u = h * per_half + min(rem >> 4, last_q) * 16 + (rem & 15);
+        const int c = w_unit_chunk(u, pairs);
+        r.w[2 * k] = src[c];
+        r.w[2 * k + 1] = src[c + 16];
     }
 }
 
-// Puts the chunks of the first `need` pairs of each antenna half (the
-// only ones the product's chain reads).
+// Puts the three planes of the first `need` pairs of each antenna half (the
+// only ones the product's chain reads), the third as Wr + Wi.
 template <int kProd>
 __device__ __forceinline__ void p_put_w(float *__restrict__ lds_a, const PRegs<kProd, true> &r, int pairs,
                                         int need, int ptid)
 {
-    const int half = pairs * 48;
-    const int used = min(pairs, need) * 48;
+    const int per_half = pairs * 16;
+    const int used = min(pairs, need) * 16;
 #pragma unroll
-    for (int u = 0; u < PRegs<kProd, true>::kNW; ++u) {
-        const int c = ptid + u * 64 * kProd;
-        if (c < 2 * half && (c < half ? c : c - half) < used)
-            reinterpret_cast<f4v *>(lds_a)[c] = r.w[u];
+    for (int k = 0; k < PRegs<kProd, true>::kWRounds; ++k) {
+        const int u = ptid + k * 64 * kProd;
+        if (u < 2 * per_half && (u < per_half ? u : u - per_half) < used) {
+            const int c = w_unit_chunk(u, pairs);
+            f4v *dst = reinterpret_cast<f4v *>(lds_a) + c;
+            dst[0] = r.w[2 * k];
+            dst[16] = r.w[2 * k + 1];
+            dst[32] = r.w[2 * k] + r.w[2 * k + 1];
+        }
     }
 }
 
