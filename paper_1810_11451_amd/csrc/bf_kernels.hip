@@ -514,10 +514,11 @@ __device__ __forceinline__ void stage_row_3m(const floatx16 &t1, const floatx16 
 }
 
 // The three-product chain of one product for the wave-specialised schedule,
-// with the operands of W staged in LDS by the producer waves (component
-// planes, as in the plan: [2 halves][pairs][3][64 lanes] floats).  The A
-// and B values of each pair are read ahead of its products in batches of 6
-// pairs: batch k is issued once pair 6k - 4 is, so at most 10 pairs occupy
+// with the operands of W staged in LDS by the producer waves as two
+// component planes, [2 halves][pairs][2][64 lanes] floats (Wr, Wi; the
+// third operand Wr + Wi is formed right before its matrix-core step, as the
+// plan rounds it).  The A and B values of each pair are read ahead of its
+// products in batches of 6 pairs: batch k is issued once pair 6k - 4 is, so at most 10 pairs occupy
 // registers and each wait covers only the oldest reads.  kFull (f > 34):
 // every batch is read, in straight-line code; otherwise only the batches
 // holding pairs below ceil(f / 2).  Rows past f and pairs past the plan's
@@ -538,17 +539,17 @@ __device__ __forceinline__ void chain_3m_body(const f2v *__restrict__ lds, const
     const int nt = wave & 1;
     constexpr int kBatch = 6, kLead = 4;
     const f2v *col = lds + h * kLdsCols + 32 * nt + n;
-    const float *ab = lds_a + mt * pairs * 192 + lane;
+    const float *ab = lds_a + mt * pairs * 128 + lane;
     t1 = floatx16{};
     t2 = floatx16{};
     t3 = floatx16{};
-    f3v a[kPairsMax];
+    f2v a[kPairsMax];
     f2v b[kPairsMax];
     if (kFull || np > 0) {
 #pragma unroll
         for (int q = 0; q < kBatch; ++q) {
             b[q] = col[2 * q * kLdsCols];
-            a[q] = f3v{ab[(3 * q) * 64], ab[(3 * q + 1) * 64], ab[(3 * q + 2) * 64]};
+            a[q] = f2v{ab[(2 * q) * 64], ab[(2 * q + 1) * 64]};
         }
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -558,11 +559,11 @@ __device__ __forceinline__ void chain_3m_body(const f2v *__restrict__ lds, const
 #pragma unroll
             for (int q = p + kLead; q < p + kLead + kBatch; ++q) {
                 b[q] = col[2 * q * kLdsCols];
-                a[q] = f3v{ab[(3 * q) * 64], ab[(3 * q + 1) * 64], ab[(3 * q + 2) * 64]};
+                a[q] = f2v{ab[(2 * q) * 64], ab[(2 * q + 1) * 64]};
             }
         }
         if (kFull || p < np)
-            mfma3(a[p], b[p], t1, t2, t3);
+            mfma3(f3v{a[p].x, a[p].y, a[p].x + a[p].y}, b[p], t1, t2, t3);
         if constexpr (kEpi) {
             if (p < 16)
                 stage_row_3m(p1, p2, p3, p, wave, lane, prev_tile);
@@ -868,10 +869,10 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
 // operands of its W.  The plan holds them as 2 halves x pairs x 3 planes x
 // 64 floats (Wr, Wi, Wr + Wi; 48 chunks per pair); the producers load only
 // the Wr and Wi planes, in units of one 4-lane chunk of each (2 halves x
-// pairs x 16 units), and form the third plane with one FP32 add, which is
-// exactly how the plan rounds it.
+// pairs x 16 units), and stage those two planes; the consumers form Wr + Wi
+// with one FP32 add, which is exactly how the plan rounds it.
 constexpr int kWUnitsMax = kPairsMax * 32;
-constexpr int kWFloatsMax = kPairsMax * 384;
+constexpr int kWFloatsMax = kPairsMax * 256;   // staged in LDS: 2 halves x pairs x 2 planes x 64
 
 template <int kProd, bool kW = false>
 struct PRegs {
@@ -928,8 +929,10 @@ __device__ __forceinline__ void p_load_w(PRegs<kProd, true> &r, const float *__r
     }
 }
 
-// Puts the three planes of the first `need` pairs of each antenna half (the
-// only ones the product's chain reads), the third as Wr + Wi.
+// Puts the Wr and Wi planes of the first `need` pairs of each antenna half
+// (the only ones the product's chain reads) into the staged layout,
+// [2 halves][pairs][2][64] floats: unit u's Wr chunk at 32 (u / 16) +
+// u % 16, its Wi chunk 16 later.
 template <int kProd>
 __device__ __forceinline__ void p_put_w(float *__restrict__ lds_a, const PRegs<kProd, true> &r, int pairs,
                                         int need, int ptid)
@@ -940,11 +943,9 @@ __device__ __forceinline__ void p_put_w(float *__restrict__ lds_a, const PRegs<k
     for (int k = 0; k < PRegs<kProd, true>::kWRounds; ++k) {
         const int u = ptid + k * 64 * kProd;
         if (u < 2 * per_half && (u < per_half ? u : u - per_half) < used) {
-            const int c = w_unit_chunk(u, pairs);
-            f4v *dst = reinterpret_cast<f4v *>(lds_a) + c;
+            f4v *dst = reinterpret_cast<f4v *>(lds_a) + (u >> 4) * 32 + (u & 15);
             dst[0] = r.w[2 * k];
             dst[16] = r.w[2 * k + 1];
-            dst[32] = r.w[2 * k] + r.w[2 * k + 1];
         }
     }
 }
