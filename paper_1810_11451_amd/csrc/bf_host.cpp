@@ -207,17 +207,19 @@ extern "C" bf_status bf_plan_create(bf_plan *out, const void *w_pool, int32_t n_
         if (!want)
             continue;
         const bool want_lo = prec_mask & BF_PREC_BIT(split);
-        const size_t bytes = std::max<size_t>(16, 2 * (size_t)n_w * p->lp_stride * 16);
-        e = hipMalloc(&p->lp_hi[ty], bytes);
-        if (e == hipSuccess && want_lo)
-            e = hipMalloc(&p->lp_lo[ty], bytes);
+        p->lp_split[ty] = want_lo;
+        // the per-lane operand layout serves the plain form only
+        if (prec_mask & BF_PREC_BIT(plain)) {
+            const size_t bytes = std::max<size_t>(16, 2 * (size_t)n_w * p->lp_stride * 16);
+            e = hipMalloc(&p->lp_hi[ty], bytes);
+        }
         if (e == hipSuccess)
             e = hipMalloc(&p->lp_exp[ty], sizeof(int) * 2 * (size_t)n_w);
         p->lp_wc_stride[ty] = bfk::lp_wc_stride(want_lo);
         if (e == hipSuccess)
             e = hipMalloc(&p->lp_wc[ty], sizeof(uint32_t) * 2 * (size_t)n_w * p->lp_wc_stride[ty]);
         if (e == hipSuccess && w_dev)
-            e = bfk::launch_w_transform_lp(w_dev, n_w, f_max, ty == 1, p->lp_hi[ty], p->lp_lo[ty],
+            e = bfk::launch_w_transform_lp(w_dev, n_w, f_max, ty == 1, p->lp_hi[ty], p->lp_split[ty],
                                            p->lp_exp[ty], p->lp_wc[ty], st);
         if (e != hipSuccess) {
             if (w_dev)
@@ -250,8 +252,6 @@ extern "C" bf_status bf_plan_destroy(bf_plan p)
     for (int ty = 0; ty < 2; ++ty) {
         if (p->lp_hi[ty])
             (void)hipFree(p->lp_hi[ty]);
-        if (p->lp_lo[ty])
-            (void)hipFree(p->lp_lo[ty]);
         if (p->lp_exp[ty])
             (void)hipFree(p->lp_exp[ty]);
         if (p->lp_wc[ty])
@@ -353,12 +353,12 @@ extern "C" bf_status bf_plan_update(bf_plan p, int32_t w_id, const void *w, void
         e = bfk::launch_w_transform_3m(p->w_stage, 1, p->f_max, p->a_3m + slot * p->a_3m_stride,
                                        p->pairs, p->update_stream);
     for (int ty = 0; ty < 2 && e == hipSuccess; ++ty) {
-        if (!p->lp_hi[ty])
+        if (!p->lp_wc[ty])
             continue;
         const size_t off = slot * p->lp_stride * 16;
-        void *lo = p->lp_lo[ty] ? static_cast<char *>(p->lp_lo[ty]) + off : nullptr;
         e = bfk::launch_w_transform_lp(p->w_stage, 1, p->f_max, ty == 1,
-                                       static_cast<char *>(p->lp_hi[ty]) + off, lo,
+                                       p->lp_hi[ty] ? static_cast<char *>(p->lp_hi[ty]) + off : nullptr,
+                                       p->lp_split[ty],
                                        p->lp_exp[ty] + slot, p->lp_wc[ty] + slot * p->lp_wc_stride[ty],
                                        p->update_stream);
     }
@@ -611,7 +611,6 @@ hipError_t launch_for_plan(bf_plan p, const bfk::LaunchCfg &cfg, BfHeader *blk, 
     pd.a_3m_stride = (int)p->a_3m_stride;
     const int ty = (cfg.prec == BF_BF16 || cfg.prec == BF_BF16X2) ? 1 : 0;
     pd.lp_hi = p->lp_hi[ty];
-    pd.lp_lo = p->lp_lo[ty];
     pd.lp_exp = p->lp_exp[ty];
     pd.lp_stride = (int)p->lp_stride;
     pd.lp_chunks = bfk::lp_chunks(p->f_max);

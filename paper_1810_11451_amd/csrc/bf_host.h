@@ -43,7 +43,7 @@ struct bf_plan_s {
     size_t a_3m_stride = 0;
     // 16-bit operand layouts, index 0 = FP16, 1 = BF16 (lo only for split forms)
     void *lp_hi[2] = {nullptr, nullptr};
-    void *lp_lo[2] = {nullptr, nullptr};
+    bool lp_split[2] = {false, false};   // compact layout holds the lo part
     int *lp_exp[2] = {nullptr, nullptr};
     uint32_t *lp_wc[2] = {nullptr, nullptr};   // compact 16-bit W (wave-specialised schedule)
     size_t lp_wc_stride[2] = {0, 0};           // dwords per W

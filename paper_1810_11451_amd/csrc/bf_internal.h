@@ -58,8 +58,7 @@ struct PlanDev {
     int pairs;                // ceil(f_max / 2)
     const float *a_3m;        // three-product form: 2 x pairs x 3 x 64 floats per W
     int a_3m_stride;          // floats per W
-    const void *lp_hi;        // 16-bit forms: kWaves x chunks x 64 x 16 bytes per W
-    const void *lp_lo;        // (lo part, split forms only)
+    const void *lp_hi;        // plain 16-bit forms: kWaves x chunks x 64 x 16 bytes per W
     const int *lp_exp;        // per-W power-of-two exponent of the 16-bit operands
     int lp_stride;            // 16-byte units per W
     int lp_chunks;            // ceil(f_max / 8)
@@ -81,10 +80,11 @@ hipError_t launch_w_transform_fp32(const float2 *w_dev, int n_w, int f_max, floa
                                    int pairs, hipStream_t st);
 hipError_t launch_w_transform_3m(const float2 *w_dev, int n_w, int f_max, float *a_out,
                                  int pairs, hipStream_t st);
-// bf16 selects BF16 (else FP16); lo may be null (plain forms only); wc
-// (compact layout, lp_wc_stride(lo != null) dwords per W) may be null.
+// bf16 selects BF16 (else FP16); hi (null when the plan has no plain form)
+// receives the plain forms' operand layout, wc the compact layout
+// (lp_wc_stride(split) dwords per W: the lo part only when split).
 hipError_t launch_w_transform_lp(const float2 *w_dev, int n_w, int f_max, bool bf16, void *hi,
-                                 void *lo, int *w_exp, uint32_t *wc, hipStream_t st);
+                                 bool split, int *w_exp, uint32_t *wc, hipStream_t st);
 
 struct LaunchCfg {
     int prec;        // bf_prec

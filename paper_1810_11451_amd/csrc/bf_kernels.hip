@@ -1361,21 +1361,23 @@ __device__ __forceinline__ void split16(float x, unsigned short &hi, unsigned sh
     lo = to16<kBf16>((x - from16<kBf16>(hi)) * (float)(1 << Lp<kBf16>::kShift));
 }
 
-// Plan time: one block per W.  Layout per W and part (hi, lo):
-// [kWaves][chunks][64 lanes][8 x 16-bit], slot s of lane l in step t being
-// real row m = l % 32 of the wave (antenna 16 wave + m / 2, c = m % 2) and
-// K index (flow 8t + 4(l / 32) + s / 2, part q = s % 2):
+// Plan time: one block per W.  Operand layout (hi part; the plain forms'
+// per-lane operands): [kWaves][chunks][64 lanes][8 x 16-bit], slot s of
+// lane l in step t being real row m = l % 32 of the wave (antenna
+// 16 wave + m / 2, c = m % 2) and K index (flow 8t + 4(l / 32) + s / 2,
+// part q = s % 2):
 //   (c, q) = (0, 0): Wr   (0, 1): -Wi   (1, 0): Wi   (1, 1): Wr.
 //
-// Compact layout (wc, when given): per part (hi, then lo if `lo` is given)
-// dword 40 i + k holds the (re, im) codes of entry (antenna i, flow k < 40)
-// of the scaled W, zero past f_max; the same codes as the operand layout,
-// whose -Wi entries are the negated (sign-flipped) codes.
+// Compact layout (wc): per part (hi, then lo when `split`) dword 40 i + k
+// holds the (re, im) codes of entry (antenna i, flow k < 40) of the scaled
+// W, zero past f_max; the same codes as the operand layout, whose -Wi
+// entries are the negated (sign-flipped) codes.  The split forms read only
+// this layout.
 template <bool kBf16>
 __global__ __launch_bounds__(256) void w_transform_lp_kernel(const float2 *__restrict__ w, int f_max,
                                                              int chunks,
                                                              unsigned short *__restrict__ hi,
-                                                             unsigned short *__restrict__ lo,
+                                                             bool split,
                                                              int *__restrict__ w_exp,
                                                              uint32_t *__restrict__ wc)
 {
@@ -1397,7 +1399,7 @@ __global__ __launch_bounds__(256) void w_transform_lp_kernel(const float2 *__res
     if (threadIdx.x == 0)
         w_exp[wi] = ew;
     const size_t per_w = (size_t)kWaves * chunks * 64 * 8;
-    for (size_t idx = threadIdx.x; idx < per_w; idx += blockDim.x) {
+    for (size_t idx = threadIdx.x; hi && idx < per_w; idx += blockDim.x) {
         const int s = (int)(idx % 8);
         const int lane = (int)((idx / 8) % 64);
         const int t = (int)((idx / 512) % chunks);
@@ -1412,16 +1414,11 @@ __global__ __launch_bounds__(256) void w_transform_lp_kernel(const float2 *__res
             const float2 v = W[(size_t)i * f_max + k];
             x = c == 0 ? (q == 0 ? v.x : -v.y) : (q == 0 ? v.y : v.x);
         }
-        unsigned short h, l;
-        split16<kBf16>(x * scale, h, l);
-        hi[wi * per_w + idx] = h;
-        if (lo)
-            lo[wi * per_w + idx] = l;
+        if (hi)
+            hi[wi * per_w + idx] = to16<kBf16>(x * scale);
     }
-    if (!wc)
-        return;
     const size_t part = (size_t)kM * kLpWcFlows;
-    uint32_t *dst = wc + wi * part * (lo ? 2 : 1);
+    uint32_t *dst = wc + wi * part * (split ? 2 : 1);
     for (int idx = threadIdx.x; idx < (int)part; idx += blockDim.x) {
         const int i = idx / kLpWcFlows;
         const int k = idx - i * kLpWcFlows;
@@ -1430,25 +1427,23 @@ __global__ __launch_bounds__(256) void w_transform_lp_kernel(const float2 *__res
         split16<kBf16>(v.x * scale, rh, rl);
         split16<kBf16>(v.y * scale, ih, il);
         dst[idx] = (uint32_t)rh | ((uint32_t)ih << 16);
-        if (lo)
+        if (split)
             dst[part + idx] = (uint32_t)rl | ((uint32_t)il << 16);
     }
 }
 
 hipError_t launch_w_transform_lp(const float2 *w_dev, int n_w, int f_max, bool bf16, void *hi,
-                                 void *lo, int *w_exp, uint32_t *wc, hipStream_t st)
+                                 bool split, int *w_exp, uint32_t *wc, hipStream_t st)
 {
     const int chunks = lp_chunks(f_max);
     if (n_w <= 0 || chunks == 0)
         return hipSuccess;
     if (bf16)
         hipLaunchKernelGGL(w_transform_lp_kernel<true>, dim3(n_w), dim3(256), 0, st, w_dev, f_max,
-                           chunks, static_cast<unsigned short *>(hi),
-                           static_cast<unsigned short *>(lo), w_exp, wc);
+                           chunks, static_cast<unsigned short *>(hi), split, w_exp, wc);
     else
         hipLaunchKernelGGL(w_transform_lp_kernel<false>, dim3(n_w), dim3(256), 0, st, w_dev, f_max,
-                           chunks, static_cast<unsigned short *>(hi),
-                           static_cast<unsigned short *>(lo), w_exp, wc);
+                           chunks, static_cast<unsigned short *>(hi), split, w_exp, wc);
     return hipGetLastError();
 }
 
@@ -1545,20 +1540,14 @@ struct LpA {
     u4v lo[kSplit ? kLpChunksMax : 1];
 };
 
-template <bool kSplit>
-__device__ __forceinline__ void load_a_lp(LpA<kSplit> &a, const PlanDev &pd, int w, int wave, int lane)
+// A operands of the plain forms from the plan's per-lane operand layout.
+__device__ __forceinline__ void load_a_lp(LpA<false> &a, const PlanDev &pd, int w, int wave, int lane)
 {
     const size_t base = (size_t)w * pd.lp_stride + (size_t)wave * pd.lp_chunks * 64 + lane;
     const g_cu4v *h = (const g_cu4v *)pd.lp_hi + base;
 #pragma unroll
     for (int t = 0; t < kLpChunksMax; ++t)
         a.hi[t] = h[min(t, pd.lp_chunks - 1) * 64];
-    if constexpr (kSplit) {
-        const g_cu4v *l = (const g_cu4v *)pd.lp_lo + base;
-#pragma unroll
-        for (int t = 0; t < kLpChunksMax; ++t)
-            a.lo[t] = l[min(t, pd.lp_chunks - 1) * 64];
-    }
 }
 
 // Matrix-core steps of one product from the staged 16-bit tile, then the
@@ -1938,6 +1927,41 @@ __global__ __launch_bounds__(64 * (kWaves + kProd)) void apply_lp_ws(BfHeader *_
 constexpr int kLpTile = 64 * kLpPitch;   // dwords per staged 16-bit tile
 
 // kSched 0 for the 16-bit forms: one product per workgroup.
+// A operands of the split forms (hi and lo parts) for one wave (16
+// antennas, both components) and all chunks of a W, formed from the plan's
+// compact layout as the wave-specialised consumers form them: lane l's row
+// is antenna 16 wave + (l % 32) / 2, component l % 2, and lanes l and l ^ 1
+// read the same dwords, so a wave loads half the bytes a per-lane operand
+// layout would take.  (For the plain forms the per-lane layout measured
+// faster and is kept.)
+__device__ __forceinline__ void load_a_lp(LpA<true> &a, const PlanDev &pd, int w, int wave, int lane)
+{
+    constexpr bool kSplit = true;
+    const int h = lane >> 5;
+    const int n = lane & 31;
+    const g_cu4v *src = (const g_cu4v *)(pd.lp_wc + (size_t)w * pd.lp_wc_stride +
+                                         (16 * wave + (n >> 1)) * kLpWcFlows + 4 * h);
+    const uint32_t rot = (n & 1) ? 16u : 0u;
+    const uint32_t flip = (n & 1) ? 0u : 0x80000000u;
+    u4v raw[kSplit ? 2 * kLpChunksMax : kLpChunksMax];
+#pragma unroll
+    for (int t = 0; t < kLpChunksMax; ++t)
+        raw[t] = src[2 * t];
+    if constexpr (kSplit) {
+#pragma unroll
+        for (int t = 0; t < kLpChunksMax; ++t)
+            raw[kLpChunksMax + t] = src[kLpWcP / 4 + 2 * t];
+    }
+#pragma unroll
+    for (int t = 0; t < kLpChunksMax; ++t)
+        a.hi[t] = lp_a_of(raw[t], rot, flip);
+    if constexpr (kSplit) {
+#pragma unroll
+        for (int t = 0; t < kLpChunksMax; ++t)
+            a.lo[t] = lp_a_of(raw[kLpChunksMax + t], rot, flip);
+    }
+}
+
 template <bool kBf16, bool kSplit, bool kVec16, bool kStage>
 __global__ __launch_bounds__(kThreads) void apply_lp_single(BfHeader *__restrict__ blk,
                                                             const BfItem *__restrict__ items,
@@ -1957,7 +1981,7 @@ __global__ __launch_bounds__(kThreads) void apply_lp_single(BfHeader *__restrict
     LpA<kSplit> a;
     int ew = 0;
     if (pd.lp_chunks > 0) {
-        load_a_lp<kSplit>(a, pd, d.w_id, wave, lane);
+        load_a_lp(a, pd, d.w_id, wave, lane);
         ew = pd.lp_exp[d.w_id];
     }
     const uint32_t m = wave_max_u32(absmax_bits<kVec16>(sr, d.f));
@@ -2017,7 +2041,7 @@ __global__ __launch_bounds__(kThreads) void apply_lp_stream(BfHeader *__restrict
             smax[buf][wave] = m;
         if (d.w_id != cur_w && pd.lp_chunks > 0) {
             cur_w = d.w_id;
-            load_a_lp<kSplit>(a, pd, cur_w, wave, lane);
+            load_a_lp(a, pd, cur_w, wave, lane);
             ew = pd.lp_exp[cur_w];
             wait_vmem_all();
         }
