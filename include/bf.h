@@ -59,7 +59,7 @@ typedef enum {
  *              per complex product.
  *   BF_FP32_3M FP32 operands, three real products per complex product
  *              (Gauss): Re = Wr Sr - Wi Si, Im = (Wr + Wi)(Sr + Si) - Wr Sr
- *              - Wi Si, with Wr + Wi formed once in the plan.  A quarter
+ *              - Wi Si, with Wr + Wi formed by one FP32 add.  A quarter
  *              fewer matrix-core steps; rounding differs from BF_FP32 (for
  *              example an identity W no longer returns S bit for bit) but
  *              stays within the FP32 error bar.

@@ -47,16 +47,17 @@ constexpr int kThreads = 64 * kWaves;
 // Operand layout of one W for the FP32 matrix-core form: float2 entries
 // [kWaves][pairs][64 lanes]; see bf_kernels.hip.
 inline size_t fp32_w_stride(int pairs) { return (size_t)kWaves * pairs * 64; }
-// Three-product FP32 form: floats [2 antenna halves][pairs][3][64 lanes] per
-// W, the 3 being Wr, Wi and Wr + Wi of the lane's (antenna, flow).
-inline size_t fp32_3m_w_stride(int pairs) { return (size_t)2 * pairs * 3 * 64; }
+// Three-product FP32 form: floats [2 antenna halves][pairs][2][64 lanes] per
+// W, the 2 being Wr and Wi of the lane's (antenna, flow); the kernels form
+// Wr + Wi with one FP32 add.
+inline size_t fp32_3m_w_stride(int pairs) { return (size_t)2 * pairs * 2 * 64; }
 
 // Device-side view of a plan, as the apply kernels need it.
 struct PlanDev {
     const float2 *a_fp32;     // FP32 form: kWaves x pairs x 64 float2 per W
     int a_fp32_stride;        // float2 per W
     int pairs;                // ceil(f_max / 2)
-    const float *a_3m;        // three-product form: 2 x pairs x 3 x 64 floats per W
+    const float *a_3m;        // three-product form: 2 x pairs x 2 x 64 floats per W
     int a_3m_stride;          // floats per W
     const void *lp_hi;        // plain 16-bit forms: kWaves x chunks x 64 x 16 bytes per W
     const int *lp_exp;        // per-W power-of-two exponent of the 16-bit operands

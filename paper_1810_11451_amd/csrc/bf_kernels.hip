@@ -116,21 +116,21 @@ __global__ void w_transform_3m_kernel(const float2 *__restrict__ w, int n_w, int
                                       float *__restrict__ a, int pairs)
 {
     // Entry (W wi, half mt, pair p, component c, lane): antenna 32 mt + lane % 32,
-    // flow 2 p + lane / 32; c = 0, 1, 2 -> Wr, Wi, Wr + Wi (zero past f_max).
-    const size_t total = (size_t)n_w * 2 * pairs * 3 * 64;
+    // flow 2 p + lane / 32; c = 0, 1 -> Wr, Wi (zero past f_max).
+    const size_t total = (size_t)n_w * 2 * pairs * 2 * 64;
     for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
          idx += (size_t)gridDim.x * blockDim.x) {
         const int lane = (int)(idx % 64);
-        const int c = (int)((idx / 64) % 3);
-        const int p = (int)((idx / (64 * 3)) % pairs);
-        const int mt = (int)((idx / (64 * 3 * (size_t)pairs)) % 2);
-        const size_t wi = idx / (64 * 3 * (size_t)pairs * 2);
+        const int c = (int)((idx / 64) % 2);
+        const int p = (int)((idx / (64 * 2)) % pairs);
+        const int mt = (int)((idx / (64 * 2 * (size_t)pairs)) % 2);
+        const size_t wi = idx / (64 * 2 * (size_t)pairs * 2);
         const int i = 32 * mt + (lane & 31);
         const int k = 2 * p + (lane >> 5);
         float out = 0.f;
         if (k < f_max) {
             const float2 v = w[(wi * kM + i) * (size_t)f_max + k];
-            out = c == 0 ? v.x : (c == 1 ? v.y : v.x + v.y);
+            out = c == 0 ? v.x : v.y;
         }
         a[idx] = out;
     }
@@ -139,7 +139,7 @@ __global__ void w_transform_3m_kernel(const float2 *__restrict__ w, int n_w, int
 hipError_t launch_w_transform_3m(const float2 *w_dev, int n_w, int f_max, float *a_out,
                                  int pairs, hipStream_t st)
 {
-    const size_t total = (size_t)n_w * 2 * pairs * 3 * 64;
+    const size_t total = (size_t)n_w * 2 * pairs * 2 * 64;
     if (total == 0)
         return hipSuccess;
     const int block = 256;
@@ -434,22 +434,23 @@ __device__ __forceinline__ void contract_fp32_reload(const f2v *__restrict__ lds
 // nt = w % 2, and accumulates T1 = Wr Sr, T2 = Wi Si, T3 = (Wr + Wi)(Sr + Si)
 // over the flows; then Re R = T1 - T2 and Im R = (T3 - T1) - T2.
 
-// Operands of pool entry w for antenna half mt: 3 registers per pair, read
-// from the plan's component planes (pairs >= 1).  The product uses `need`
+// Operands of pool entry w for antenna half mt: Wr and Wi, 2 registers per
+// pair, read from the plan's component planes (pairs >= 1); the third
+// operand Wr + Wi is formed at each matrix-core step.  The product uses `need`
 // (>= 1) pairs; the loads of later pairs repeat the last used one, so they
 // hit in cache instead of fetching W columns the product does not use, and
 // those registers feed no matrix-core step.
-__device__ __forceinline__ void load_a_3m(f3v (&a)[kPairsMax], const float *__restrict__ apool,
+__device__ __forceinline__ void load_a_3m(f2v (&a)[kPairsMax], const float *__restrict__ apool,
                                           int w, int a_w_stride, int pairs, int mt, int lane,
                                           int need)
 {
     typedef __attribute__((address_space(1))) const float g_cf;
-    const g_cf *ap = (const g_cf *)(apool + (size_t)w * a_w_stride + (size_t)mt * pairs * 192 + lane);
+    const g_cf *ap = (const g_cf *)(apool + (size_t)w * a_w_stride + (size_t)mt * pairs * 128 + lane);
     const int last = min(pairs, need) - 1;
 #pragma unroll
     for (int p = 0; p < kPairsMax; ++p) {
         const int q = min(p, last);
-        a[p] = f3v{ap[(3 * q) * 64], ap[(3 * q + 1) * 64], ap[(3 * q + 2) * 64]};
+        a[p] = f2v{ap[(2 * q) * 64], ap[(2 * q + 1) * 64]};
     }
 }
 
@@ -464,7 +465,7 @@ __device__ __forceinline__ void mfma3(const f3v &a, const f2v &b, floatx16 &t1, 
 // Contracts the staged S (LDS, pitch kLdsCols) and writes the wave's
 // quadrant of R, row-major 64 x 60, into `tile` (LDS).
 __device__ __forceinline__ void contract_stage_3m(const f2v *__restrict__ lds,
-                                                  const f3v (&a)[kPairsMax], int f, int wave,
+                                                  const f2v (&a)[kPairsMax], int f, int wave,
                                                   int lane, f2v *__restrict__ tile)
 {
     const int h = lane >> 5;
@@ -485,12 +486,12 @@ __device__ __forceinline__ void contract_stage_3m(const f2v *__restrict__ lds,
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int p = 0; p < kPairsMax; ++p)
-            mfma3(a[p], b[p], t1, t2, t3);
+            mfma3(f3v{a[p].x, a[p].y, a[p].x + a[p].y}, b[p], t1, t2, t3);
     } else {
 #pragma unroll
         for (int p = 0; p < kPairsMax; ++p)
             if (p < np)
-                mfma3(a[p], col[2 * p * kLdsCols], t1, t2, t3);
+                mfma3(f3v{a[p].x, a[p].y, a[p].x + a[p].y}, col[2 * p * kLdsCols], t1, t2, t3);
     }
     const int j = 32 * nt + n;
 #pragma unroll
@@ -627,7 +628,7 @@ __global__ __launch_bounds__(kThreads) void apply_fp32_3m_single(BfHeader *__res
     float2 *sink = sink_of(blk);
     const int it = xcd_contiguous(blockIdx.x, n_items);
     const BfItem d = items[it];
-    f3v a[kPairsMax];
+    f2v a[kPairsMax];
     SRegs<kVec16> sr;
     load_s<kVec16>(sr, d.f > 0 ? d.S : sink, d.f);
     if (pairs > 0)
@@ -866,11 +867,10 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
 
 // Producer-side staging over kProd waves, in 16-byte chunks with clamped
 // indices: S of one product and, for the three-product form (kW), the
-// operands of its W.  The plan holds them as 2 halves x pairs x 3 planes x
-// 64 floats (Wr, Wi, Wr + Wi; 48 chunks per pair); the producers load only
-// the Wr and Wi planes, in units of one 4-lane chunk of each (2 halves x
-// pairs x 16 units), and stage those two planes; the consumers form Wr + Wi
-// with one FP32 add, which is exactly how the plan rounds it.
+// operands of its W.  The plan holds them as 2 halves x pairs x 2 planes x
+// 64 floats (Wr, Wi; 32 chunks per pair); the producers load them in units
+// of one 4-lane chunk of each plane (2 halves x pairs x 16 units) and stage
+// them in the same layout; the consumers form Wr + Wi with one FP32 add.
 constexpr int kWUnitsMax = kPairsMax * 32;
 constexpr int kWFloatsMax = kPairsMax * 256;   // staged in LDS: 2 halves x pairs x 2 planes x 64
 
@@ -893,19 +893,18 @@ __device__ __forceinline__ void p_load_s(PRegs<kProd, kW> &r, const float2 *__re
         r.v[u] = __builtin_nontemporal_load(src + min(ptid + u * 64 * kProd, last));
 }
 
-// Chunk index (in the plan's layout) of the Wr chunk of unit u: half h,
-// pair q, 4-lane group j; the Wi chunk follows 16 chunks later and the
-// Wr + Wi chunk 32 later.
+// Chunk index (in the plan's and the staged layout) of the Wr chunk of unit
+// u: half h, pair q, 4-lane group j; the Wi chunk follows 16 chunks later.
 __device__ __forceinline__ int w_unit_chunk(int u, int pairs)
 {
     const int per_half = pairs * 16;
     const int h = u >= per_half ? 1 : 0;
     const int rem = u - h * per_half;
-    return h * pairs * 48 + (rem >> 4) * 48 + (rem & 15);
+    return h * pairs * 32 + (rem >> 4) * 32 + (rem & 15);
 }
 
-// W operands (L2-resident pool: plain loads, no streaming hint), Wr and Wi
-// planes only.  Only the first `need` (>= 1) pairs of each half are used by
+// W operands (L2-resident pool: plain loads, no streaming hint).  Only the
+// first `need` (>= 1) pairs of each half are used by
 // the product; units of later pairs load the last used pair's unit again
 // (a cache hit; nothing of them reaches LDS).  Units past the end repeat
 // the last unit.
@@ -931,8 +930,7 @@ __device__ __forceinline__ void p_load_w(PRegs<kProd, true> &r, const float *__r
 
 // Puts the Wr and Wi planes of the first `need` pairs of each antenna half
 // (the only ones the product's chain reads) into the staged layout,
-// [2 halves][pairs][2][64] floats: unit u's Wr chunk at 32 (u / 16) +
-// u % 16, its Wi chunk 16 later.
+// [2 halves][pairs][2][64] floats, the plan's own.
 template <int kProd>
 __device__ __forceinline__ void p_put_w(float *__restrict__ lds_a, const PRegs<kProd, true> &r, int pairs,
                                         int need, int ptid)
@@ -943,7 +941,7 @@ __device__ __forceinline__ void p_put_w(float *__restrict__ lds_a, const PRegs<k
     for (int k = 0; k < PRegs<kProd, true>::kWRounds; ++k) {
         const int u = ptid + k * 64 * kProd;
         if (u < 2 * per_half && (u < per_half ? u : u - per_half) < used) {
-            f4v *dst = reinterpret_cast<f4v *>(lds_a) + (u >> 4) * 32 + (u & 15);
+            f4v *dst = reinterpret_cast<f4v *>(lds_a) + w_unit_chunk(u, pairs);
             dst[0] = r.w[2 * k];
             dst[16] = r.w[2 * k + 1];
         }
