@@ -109,9 +109,9 @@ hipError_t launch_w_transform_fp32(const float2 *w_dev, int n_w, int f_max, floa
 
 // Plan-time operand layout, three-product FP32 form.  For
 // v_mfma_f32_32x32x2_f32 with real rows = antennas: lane l of antenna half
-// mt holds, for pair p, antenna i = 32 mt + l % 32 and flow k = 2p + l / 32:
-// (Wr, Wi, Wr + Wi, 0), the sum rounded once here.  Flows k >= f_max hold
-// zeros.
+// mt holds, for pair p, antenna i = 32 mt + l % 32 and flow k = 2p + l / 32,
+// in two planes: Wr, then Wi (the kernels form Wr + Wi).  Flows k >= f_max
+// hold zeros.
 __global__ void w_transform_3m_kernel(const float2 *__restrict__ w, int n_w, int f_max,
                                       float *__restrict__ a, int pairs)
 {
