@@ -98,10 +98,8 @@ static bf_status default_variants(bf_plan p)
             bf_variant v{};
             const bool full = b == kBucketCount - 1;
             const bool fp32 = pr == BF_FP32 || pr == BF_FP32_3M;
-            if (pr == BF_FP32_3M && full)
-                v = bf_variant{3, 0, 0, 2};   // wave-specialised, 8 producers, depth 2, as given
-            else if (pr == BF_FP32_3M && b > 0)
-                v = bf_variant{3, 0, 0, 1};   // mixed f: wave-specialised, 8 producers, depth 1
+            if (pr == BF_FP32_3M && b > 0)
+                v = bf_variant{3, 0, 0, 1};   // wave-specialised, 8 producers, depth 1, as given
             else if (full && fp32)
                 v = bf_variant{3, 0, 0, 5};   // wave-specialised, 12 producers, depth 2, as given
             else if (full && (pr == BF_FP16 || pr == BF_BF16))
