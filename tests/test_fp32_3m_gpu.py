@@ -106,3 +106,19 @@ def test_ws_long_shares(vname, per_wg):
     nz = b.f > 0
     assert np.max(err[nz]) <= FP32_TOL, f"max rel err {np.max(err[nz]):.3g}"
     assert np.all(R[~nz] == 0)
+
+
+def test_variants_agree_bitwise():
+    """The one-product-per-workgroup and wave-specialised kernels issue the
+    same matrix-core steps in the same order on the same operands (Wr + Wi
+    formed by one FP32 add in both), so their results agree bit for bit on
+    random data, every f included."""
+    require_gpu()
+    n = bf.bf_device_cu_count() * 3 + 5
+    rng = np.random.default_rng(832)
+    b = wl.random_batch(rng, n, 9, f_values=np.arange(0, 37))
+    announce(f"3m variants bitwise n={n}")
+    ref = run_batch(b, prec=P, variant=VARIANTS["one-per-wg"])
+    for vname in ["ws-8-producers", "ws-8-producers-depth-2", "ws-asgiven"]:
+        R = run_batch(b, prec=P, variant=VARIANTS[vname])
+        assert np.array_equal(R.view(np.uint32), ref.view(np.uint32)), vname
