@@ -178,6 +178,9 @@ struct SRegs<false> {
 // Issues the loads of one S (f x 60 complex) into registers: thread t takes
 // 16-byte chunks t, t + 256, ... (8-byte elements when S is only 8-byte
 // aligned).  For f = 0, S must point at the sink and one chunk is read.
+// S is loaded through the caches (here and in the producers' p_load_s):
+// streaming hints cost about 8% on batches of mixed f and gained nothing
+// measurable at full width.
 template <bool kVec16>
 __device__ __forceinline__ void load_s(SRegs<kVec16> &r, const float2 *__restrict__ S, int f,
                                        int tid = threadIdx.x)
@@ -188,7 +191,7 @@ __device__ __forceinline__ void load_s(SRegs<kVec16> &r, const float2 *__restric
 #pragma unroll
         for (int u = 0; u < kChunks16; ++u) {
             const int c = min(tid + u * kThreads, last);
-            r.v[u] = __builtin_nontemporal_load(src + c);
+            r.v[u] = src[c];
         }
     } else {
         g_cf2v *src = (g_cf2v *)S;
@@ -196,7 +199,7 @@ __device__ __forceinline__ void load_s(SRegs<kVec16> &r, const float2 *__restric
 #pragma unroll
         for (int u = 0; u < kChunks8; ++u) {
             const int c = min(tid + u * kThreads, last);
-            r.v[u] = __builtin_nontemporal_load(src + c);
+            r.v[u] = src[c];
         }
     }
 }
@@ -890,7 +893,7 @@ __device__ __forceinline__ void p_load_s(PRegs<kProd, kW> &r, const float2 *__re
     const int last = (f > 0 ? f * (kB / 2) : 1) - 1;
 #pragma unroll
     for (int u = 0; u < PRegs<kProd, kW>::kN; ++u)
-        r.v[u] = __builtin_nontemporal_load(src + min(ptid + u * 64 * kProd, last));
+        r.v[u] = src[min(ptid + u * 64 * kProd, last)];
 }
 
 // Chunk index (in the plan's and the staged layout) of the Wr chunk of unit
