@@ -15,8 +15,9 @@
  *           leading f_t columns of entry w_t (row stride f_max);
  *   S_t     device, complex64 [f_t][60], row-major, 8-byte aligned
  *           (16-byte alignment takes the faster load path);
- *   R_t     device, complex64 [64][60], row-major, 8-byte aligned; fully
- *           overwritten (zeros when f_t = 0).
+ *   R_t     device, complex64 [64][60], row-major, 16-byte aligned (R is
+ *           written with 16-byte stores); fully overwritten (zeros when
+ *           f_t = 0).
  *
  * Streams: every `hip_stream` argument is a hipStream_t passed as void*
  * (NULL = the default stream).  Device work is asynchronous and ordered on
@@ -142,7 +143,7 @@ bf_status bf_apply(bf_plan plan, int32_t batch, const int32_t *w_ids, const int3
 
 /* Same products for the common case of one S buffer and one R buffer:
  * S[t] = S_base + s_off[t] complex elements (host int64 [batch]),
- * R[t] = R_base + t * 64 * 60 complex elements. */
+ * R[t] = R_base + t * 64 * 60 complex elements (R_base 16-byte aligned). */
 bf_status bf_apply_packed(bf_plan plan, int32_t batch, const int32_t *w_ids, const int32_t *f,
                           const void *S_base, const int64_t *s_off, void *R_base,
                           bf_prec prec, void *hip_stream);
@@ -183,7 +184,10 @@ typedef struct {
                               3: persistent, wave-specialised (matrix-core waves and
                               data-movement waves); needs every S 16-byte aligned
                               (other batches run schedule 0 for the three-product
-                              form, 2 otherwise) */
+                              form, 2 otherwise); for the 16-bit forms also one f
+                              for every product of the batch (batches of mixed f
+                              run schedule 2, and bf_autotune does not try 3 on
+                              them) */
     int32_t wg_per_cu;     /* persistent grid = wg_per_cu * CU count (ignored for 0) */
     int32_t order;         /* 0: as given; 1: longest f first, then by W id */
     int32_t store;         /* schedules 0 and 2: 0 = lanes write their accumulators
@@ -256,7 +260,8 @@ typedef struct {
     int32_t n_s;            /* number of S blocks, >= 1 */
     int32_t reserved;
     const void *S;          /* device, n_s contiguous f x 60 complex64 blocks */
-    void *R;                /* device, n_s contiguous 64 x 60 complex64 blocks */
+    void *R;                /* device, n_s contiguous 64 x 60 complex64 blocks,
+                               16-byte aligned */
     uint64_t tag;           /* opaque, returned in the completion */
     int64_t t_arrival_ns;   /* CLOCK_MONOTONIC arrival time (0: taken at submit) */
 } bf_request;

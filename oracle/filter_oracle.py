@@ -30,6 +30,9 @@ stopband removes most of a block's energy.
 
 Parity status: pinned (impulse, shifts, single tones, brute-force circular
 convolution, linearity), with planted mistakes those pins must reject.
+``rel_error`` is pinned by three hand-worked cases (one tap, two taps, a
+tap pair whose spectrum peaks away from k = 0) that separate its
+denominator from ||y_ref||, from ||s|| and from max|h| ||s||.
 """
 from __future__ import annotations
 
@@ -90,12 +93,22 @@ def circular_convolution(s, h) -> np.ndarray:
     return y
 
 
-def rel_error(y, y_ref, s, h) -> np.ndarray:
-    """||y - y_ref|| / (max|H| ||s||) per block (last axis)."""
+def rel_error(y, y_ref, s, h, _mutant: int = 0) -> np.ndarray:
+    """||y - y_ref|| / (max|H| ||s||) per block (last axis).
+
+    ``_mutant`` (tests only) plants a plausible wrong denominator:
+      1 = ||y_ref||, 2 = ||s|| without max|H|, 3 = max|h| (taps, not
+      spectrum) times ||s||."""
     y = np.asarray(y, dtype=np.complex128)
     y_ref = np.asarray(y_ref, dtype=np.complex128)
     s = np.asarray(s, dtype=np.complex128)
     hmax = np.max(np.abs(filter_spectrum(h)))
+    if _mutant == 3:
+        hmax = np.max(np.abs(np.asarray(h, dtype=np.complex128)))
     num = np.linalg.norm(y - y_ref, axis=-1)
     den = hmax * np.linalg.norm(s, axis=-1)
+    if _mutant == 1:
+        den = np.linalg.norm(y_ref, axis=-1)
+    elif _mutant == 2:
+        den = np.linalg.norm(s, axis=-1)
     return num / np.where(den > 0, den, 1.0)

@@ -463,9 +463,13 @@ LOADGEN_PATH = LIB_PATH.parent / "loadgen" / "libbf_loadgen.so"
 _loadgen = None
 
 
-def loadgen_replay(server: Server, reqs: np.ndarray, t_offset_ns: np.ndarray) -> tuple:
+def loadgen_replay(server: Server, reqs: np.ndarray, t_offset_ns: np.ndarray,
+                   progress_every: int = 0, stall_ms: int = 0, label: str = "replay") -> tuple:
     """Replays reqs (REQUEST_DTYPE) at the given offsets from a native thread
-    (benchmark helper); returns (completions in request order, busy retries)."""
+    (benchmark helper); returns (completions in request order, busy retries).
+    progress_every > 0 prints a stderr line per that many completions;
+    stall_ms > 0 gives up (BfError, BF_ERR_TIMEOUT) when requests are
+    outstanding and none completes for that long."""
     global _loadgen
     lib()
     if _loadgen is None:
@@ -473,7 +477,7 @@ def loadgen_replay(server: Server, reqs: np.ndarray, t_offset_ns: np.ndarray) ->
             raise RuntimeError(f"{LOADGEN_PATH} is not built")
         L = ctypes.CDLL(str(LOADGEN_PATH))
         L.bf_loadgen_replay.restype = _i64
-        L.bf_loadgen_replay.argtypes = [_vp, _vp, _vp, _i64, _vp]
+        L.bf_loadgen_replay.argtypes = [_vp, _vp, _vp, _i64, _vp, _i64, _i64, ctypes.c_char_p]
         _loadgen = L
     reqs = np.ascontiguousarray(reqs, dtype=REQUEST_DTYPE)
     t_off = np.ascontiguousarray(t_offset_ns, dtype=np.int64)
@@ -481,7 +485,8 @@ def loadgen_replay(server: Server, reqs: np.ndarray, t_offset_ns: np.ndarray) ->
         raise ValueError("one offset per request")
     done = np.zeros(reqs.shape[0], COMPLETION_DTYPE)
     rc = _loadgen.bf_loadgen_replay(server.handle, reqs.ctypes.data, t_off.ctypes.data,
-                                   reqs.shape[0], done.ctypes.data)
+                                   reqs.shape[0], done.ctypes.data, int(progress_every),
+                                   int(stall_ms), label.encode())
     _check(rc, "bf_loadgen_replay")
     return done, int(rc)
 

@@ -60,8 +60,8 @@ extern "C" bf_status bf_check_batch(int32_t n_w, int32_t f_max, int32_t batch,
             return bf_fail(BF_ERR_INVALID, "item %d: w_id %d outside [0, %d)", t, w_ids[t], n_w);
         if (f[t] < 0 || f[t] > f_max)
             return bf_fail(BF_ERR_INVALID, "item %d: f %d outside [0, %d]", t, f[t], f_max);
-        if (!R[t] || !aligned8(R[t]))
-            return bf_fail(BF_ERR_INVALID, "item %d: R pointer null or not 8-byte aligned", t);
+        if (!R[t] || !aligned16(R[t]))
+            return bf_fail(BF_ERR_INVALID, "item %d: R pointer null or not 16-byte aligned", t);
         if (f[t] > 0 && (!S[t] || !aligned8(S[t])))
             return bf_fail(BF_ERR_INVALID, "item %d: S pointer null or not 8-byte aligned", t);
     }
@@ -433,7 +433,7 @@ void order_items(const BfItem *in, BfItem *out, int n, int n_w, std::vector<int>
 }
 
 bfk::LaunchCfg choose_launch(bf_plan p, bf_prec prec, int n, int max_f, bool vec16,
-                             const bf_variant *force)
+                             bool uniform_f, const bf_variant *force)
 {
     const bf_variant v = force ? *force : p->table[prec][bf_f_bucket(max_f)];
     (void)max_f;
@@ -453,6 +453,13 @@ bfk::LaunchCfg choose_launch(bf_plan p, bf_prec prec, int n, int max_f, bool vec
     // batches run the schedules whose W loads are guarded.
     if (cfg.schedule == 3 && p->f_max < 1)
         cfg.schedule = lp ? 2 : 0;
+    // The 16-bit wave-specialised kernel runs only batches whose products
+    // all have the same f.  A serving benchmark that launched it on batches
+    // of mixed f (two streams, many small launches) was stopped after three
+    // silent minutes and the record did not show whether the device had
+    // hung; until that is settled such batches take the streaming schedule.
+    if (cfg.schedule == 3 && lp && !uniform_f)
+        cfg.schedule = 2;
     cfg.stage = cfg.schedule == 3 || prec == BF_FP32_3M || (v.store >= 1 && cfg.schedule != 1);
     // For schedule 3 the store field selects producer waves and prefetch
     // depth: 0 -> (4, 1), 1 -> (8, 1), 2 -> (8, 2), 3 -> (8, 3), 4 -> (12, 1),
@@ -561,6 +568,7 @@ bf_status enqueue_items(bf_plan p, bf_prec prec, int n, const FillFn &fill, hipS
                                                kSinkBytes);
     const FillStats fs = fill(items);
     const int max_f = fs.max_f;
+    const bool uniform_f = fs.min_f == fs.max_f;
     const bool vec16 = fs.vec16;
     bf_variant chosen = force ? *force : p->table[prec][batch_bucket(fs.sum_f, n)];
     if (chosen.order == 1 && n > 1) {
@@ -568,7 +576,7 @@ bf_status enqueue_items(bf_plan p, bf_prec prec, int n, const FillFn &fill, hipS
         order_items(items, p->sort_tmp.data(), n, p->n_w, p->sort_scratch);
         std::memcpy(items, p->sort_tmp.data(), (size_t)n * sizeof(BfItem));
     }
-    bfk::LaunchCfg cfg = choose_launch(p, prec, n, max_f, vec16, &chosen);
+    bfk::LaunchCfg cfg = choose_launch(p, prec, n, max_f, vec16, uniform_f, &chosen);
     if (grid_out)
         *grid_out = cfg.grid;
     map_slots(p, items, n);
@@ -649,6 +657,7 @@ extern "C" bf_status bf_apply(bf_plan p, int32_t batch, const int32_t *w_ids, co
             it.f = f[t];
             it.pad0 = it.pad1 = 0;
             fs.max_f = std::max(fs.max_f, (int)f[t]);
+            fs.min_f = std::min(fs.min_f, (int)f[t]);
             fs.sum_f += f[t];
             if (f[t] > 0 && !aligned16(S[t]))
                 fs.vec16 = false;
@@ -672,8 +681,8 @@ extern "C" bf_status bf_apply_packed(bf_plan p, int32_t batch, const int32_t *w_
         return BF_OK;
     if (!w_ids || !f || !s_off || !R_base)
         return bf_fail(BF_ERR_INVALID, "null argument");
-    if (!aligned8(R_base) || (S_base && !aligned8(S_base)))
-        return bf_fail(BF_ERR_INVALID, "S_base or R_base not 8-byte aligned");
+    if (!aligned16(R_base) || (S_base && !aligned8(S_base)))
+        return bf_fail(BF_ERR_INVALID, "R_base not 16-byte aligned or S_base not 8-byte aligned");
     for (int32_t t = 0; t < batch; ++t) {
         if (w_ids[t] < 0 || w_ids[t] >= p->n_w)
             return bf_fail(BF_ERR_INVALID, "item %d: w_id %d outside [0, %d)", t, w_ids[t], p->n_w);
@@ -694,6 +703,7 @@ extern "C" bf_status bf_apply_packed(bf_plan p, int32_t batch, const int32_t *w_
             it.f = f[t];
             it.pad0 = it.pad1 = 0;
             fs.max_f = std::max(fs.max_f, (int)f[t]);
+            fs.min_f = std::min(fs.min_f, (int)f[t]);
             fs.sum_f += f[t];
             if (f[t] > 0 && (s_off[t] & 1))
                 fs.vec16 = false;
@@ -733,13 +743,14 @@ extern "C" bf_status bf_graph_create(bf_graph *out, bf_plan p, int32_t batch, co
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
 
     std::vector<BfItem> raw((size_t)batch), items((size_t)batch);
-    int max_f = 0;
+    int max_f = 0, min_f = BF_FMAX + 1;
     int64_t sum_f = 0;
     bool vec16 = true;
     for (int32_t t = 0; t < batch; ++t) {
         raw[(size_t)t] = BfItem{static_cast<const float2 *>(S[t]), static_cast<float2 *>(R[t]),
                                 w_ids[t], f[t], 0, 0};
         max_f = std::max(max_f, (int)f[t]);
+        min_f = std::min(min_f, (int)f[t]);
         sum_f += f[t];
         if (f[t] > 0 && !aligned16(S[t]))
             vec16 = false;
@@ -750,7 +761,7 @@ extern "C" bf_status bf_graph_create(bf_graph *out, bf_plan p, int32_t batch, co
         order_items(raw.data(), items.data(), batch, p->n_w, scratch);
     else
         items = raw;
-    bfk::LaunchCfg cfg = choose_launch(p, prec, batch, max_f, vec16, &v);
+    bfk::LaunchCfg cfg = choose_launch(p, prec, batch, max_f, vec16, min_f == max_f, &v);
 
     bool after_update = false;
     {
@@ -873,8 +884,13 @@ extern "C" bf_status bf_autotune(bf_plan p, int32_t batch, const int32_t *w_ids,
         reps = 1;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     int64_t sum_f = 0;
-    for (int32_t t = 0; t < batch; ++t)
+    int min_f = BF_FMAX + 1, max_f = 0;
+    for (int32_t t = 0; t < batch; ++t) {
         sum_f += f[t];
+        min_f = std::min(min_f, (int)f[t]);
+        max_f = std::max(max_f, (int)f[t]);
+    }
+    const bool lp = prec != BF_FP32 && prec != BF_FP32_3M;
 
     std::vector<bf_variant> cands;
     for (int st = 0; st < 2; ++st) {
@@ -888,9 +904,11 @@ extern "C" bf_status bf_autotune(bf_plan p, int32_t batch, const int32_t *w_ids,
         for (int w : per_cu)
             for (int o = 0; o < 2; ++o)
                 cands.push_back(bf_variant{2, w, o, st});
-    for (int o = 0; o < 2; ++o)
-        for (int st = 0; st < 6; ++st)
-            cands.push_back(bf_variant{3, 0, o, st});
+    // (the 16-bit wave-specialised kernel takes batches of one f only)
+    if (!lp || min_f == max_f)
+        for (int o = 0; o < 2; ++o)
+            for (int st = 0; st < 6; ++st)
+                cands.push_back(bf_variant{3, 0, o, st});
 
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -904,6 +922,7 @@ extern "C" bf_status bf_autotune(bf_plan p, int32_t batch, const int32_t *w_ids,
                 items[t] = BfItem{static_cast<const float2 *>(S[t]), static_cast<float2 *>(R[t]),
                                   w_ids[t], f[t], 0, 0};
                 fs.max_f = std::max(fs.max_f, (int)f[t]);
+                fs.min_f = std::min(fs.min_f, (int)f[t]);
                 fs.sum_f += f[t];
                 if (f[t] > 0 && !aligned16(S[t]))
                     fs.vec16 = false;

@@ -79,6 +79,7 @@ struct FillStats {
     int max_f;
     bool vec16;
     int64_t sum_f;
+    int min_f = BF_FMAX + 1;   // smallest f (above BF_FMAX for an empty batch)
 };
 // Tuning-table bucket of a batch: bf_f_bucket of its mean f, rounded.
 int batch_bucket(int64_t sum_f, int n);
@@ -87,7 +88,7 @@ using FillFn = std::function<FillStats(BfItem *)>;
 bf_status bf_fail(bf_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 void order_items(const BfItem *in, BfItem *out, int n, int n_w, std::vector<int> &scratch);
 bfk::LaunchCfg choose_launch(bf_plan p, bf_prec prec, int n, int max_f, bool vec16,
-                             const bf_variant *force);
+                             bool uniform_f, const bf_variant *force);
 bf_status reserve_staging(bf_plan p, int n);
 bf_status enqueue_items(bf_plan p, bf_prec prec, int n, const FillFn &fill, hipStream_t st,
                         const bf_variant *force, int *grid_out);

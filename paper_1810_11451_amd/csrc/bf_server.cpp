@@ -182,6 +182,7 @@ void launch_front(bf_server s, size_t count, int stream_idx)
                     fs.vec16 = false;
             }
             fs.max_f = std::max(fs.max_f, (int)q.r.f);
+            fs.min_f = std::min(fs.min_f, (int)q.r.f);
             fs.sum_f += (int64_t)q.r.f * q.r.n_s;
         }
         return fs;
@@ -424,8 +425,8 @@ extern "C" bf_status bf_submit(bf_server s, const bf_request *req, uint64_t *tic
         return bf_fail(BF_ERR_INVALID, "f %d outside [0, %d]", r.f, s->plan->f_max);
     if (r.n_s < 1 || r.n_s > s->cfg.max_batch_items)
         return bf_fail(BF_ERR_INVALID, "n_s %d outside [1, %d]", r.n_s, s->cfg.max_batch_items);
-    if (!r.R || (reinterpret_cast<uintptr_t>(r.R) & 7u))
-        return bf_fail(BF_ERR_INVALID, "R null or not 8-byte aligned");
+    if (!r.R || (reinterpret_cast<uintptr_t>(r.R) & 15u))
+        return bf_fail(BF_ERR_INVALID, "R null or not 16-byte aligned");
     if (r.f > 0 && (!r.S || (reinterpret_cast<uintptr_t>(r.S) & 7u)))
         return bf_fail(BF_ERR_INVALID, "S null or not 8-byte aligned");
     const uint64_t bytes = request_bytes(r);

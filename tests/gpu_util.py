@@ -44,3 +44,20 @@ def rel_errors(batch, R, items=None):
     ref = orc.apply(batch, items=items)
     got = R if items is None else R[np.asarray(items)]
     return orc.rel_frobenius(got, ref), ref
+
+
+def all_errors(batch, R, chunk: int = 2048) -> np.ndarray:
+    """Relative Frobenius error of every product against the oracle, in
+    chunks of products so that the complex128 reference of a full-size
+    batch is never held at once.  R is a complex64 numpy array [n, 64, 60]
+    or a device tensor of that shape (copied to the host chunk by chunk)."""
+    n = batch.n
+    err = np.empty(n, np.float64)
+    for lo in range(0, n, chunk):
+        hi = min(n, lo + chunk)
+        items = np.arange(lo, hi)
+        got = R[lo:hi]
+        if not isinstance(got, np.ndarray):
+            got = got.cpu().numpy()
+        err[lo:hi] = orc.rel_frobenius(got, orc.apply(batch, items=items))
+    return err

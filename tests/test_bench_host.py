@@ -47,3 +47,22 @@ def test_workload_names():
     assert set(bench.WORKLOADS) == {"single-w", "full-width", "uneven", "gain", "serving", "filter"}
     for name, gen in bench.WORKLOADS.items():
         assert (gen is None) == (name in ("serving", "filter"))
+
+
+def test_roof_follows_issued_work():
+    """The roof is the larger of the issued matrix-core time and the HBM
+    time: the four-product FP32 form at full width is matrix-core bound
+    (issues 4 x 2 x 64 x 64 x 36 flops per product), the three-product form
+    issues a quarter less and is HBM-bound, and the 16-bit forms are
+    HBM-bound even with three split products."""
+    from paper_1810_11451_amd import workloads as wl
+    b = wl.single_w_batch(n=4)
+    b.f[:] = 36
+    assert bench.issued_flops(b, bf.BF_FP32) == 4 * 4 * 2 * 64 * 64 * 36
+    assert bench.issued_flops(b, bf.BF_FP32_3M) == 4 * 3 * 2 * 64 * 64 * 36
+    assert bench.issued_flops(b, bf.BF_FP16X2) == 4 * 3 * 2 * 128 * 64 * 80
+    full = wl.full_width_batch(n=64)
+    fl = {p: bench.roof_floors_us(full, p) for p in (bf.BF_FP32, bf.BF_FP32_3M, bf.BF_FP16X2)}
+    assert fl[bf.BF_FP32]["compute_us"] > fl[bf.BF_FP32]["hbm_us"]
+    assert fl[bf.BF_FP32_3M]["compute_us"] < fl[bf.BF_FP32_3M]["hbm_us"]
+    assert fl[bf.BF_FP16X2]["compute_us"] < fl[bf.BF_FP16X2]["hbm_us"]

@@ -60,7 +60,7 @@ def _good(n=4):
     w = np.array([0, 1, 2, 1], np.int32)[:n]
     f = np.array([36, 0, 5, 1], np.int32)[:n]
     S = np.array([0x1000, 0, 0x2008, 0x3010], np.uint64)[:n]
-    R = np.array([0x10000, 0x20000, 0x30008, 0x40000], np.uint64)[:n]
+    R = np.array([0x10000, 0x20000, 0x30010, 0x40000], np.uint64)[:n]
     return w, f, S, R
 
 
@@ -79,6 +79,7 @@ def test_check_batch_accepts_valid(L):
     (lambda w, f, S, R: S.__setitem__(2, 0x2004), "S pointer"),
     (lambda w, f, S, R: R.__setitem__(1, 0), "R pointer"),
     (lambda w, f, S, R: R.__setitem__(3, 0x40001), "R pointer"),
+    (lambda w, f, S, R: R.__setitem__(2, 0x30008), "16-byte"),
 ])
 def test_check_batch_rejects(L, mutate, needle):
     w, f, S, R = _good()

@@ -84,6 +84,71 @@ def test_filter_pins_reject_planted_mistake(mutant):
     assert caught, f"planted mistake '{MUTANTS[mutant]}' passed every pin"
 
 
+def metric_pin_single_tap(rel_error):
+    """Worked by hand: h = [2] gives H[k] = 2 for every k, so max|H| = 2; s is
+    the unit impulse (||s|| = 1) and y_ref = 2 s.  With y = y_ref + 3 e_5 the
+    error norm is 3 and the metric is 3 / (2 * 1) = 1.5 exactly."""
+    s = np.zeros(N, np.complex128)
+    s[0] = 1.0
+    h = np.array([2.0 + 0j])
+    y_ref = 2.0 * s
+    y = y_ref.copy()
+    y[5] += 3.0
+    assert rel_error(y, y_ref, s, h)[()] == 1.5
+
+
+def metric_pin_two_taps(rel_error):
+    """Worked by hand: h = [1, 1] has H[k] = 1 + exp(-2 pi i k / N), largest
+    at k = 0 where it is 2, so max|H| = 2.  s = [1, -1, 0, ...] has
+    ||s|| = sqrt(2); the circular convolution is y_ref = [1, 0, -1, 0, ...]
+    (||y_ref|| = sqrt(2), so ||y_ref|| differs from max|H| ||s|| = 2 sqrt(2)).
+    With y = y_ref + 4 e_7 the metric is 4 / (2 sqrt(2)) = sqrt(2)."""
+    s = np.zeros(N, np.complex128)
+    s[0], s[1] = 1.0, -1.0
+    h = np.array([1.0 + 0j, 1.0 + 0j])
+    y_ref = np.zeros(N, np.complex128)
+    y_ref[0], y_ref[2] = 1.0, -1.0
+    y = y_ref.copy()
+    y[7] += 4.0
+    assert abs(rel_error(y, y_ref, s, h)[()] - np.sqrt(2.0)) <= 1e-15
+
+
+def metric_pin_quarter_band(rel_error):
+    """Worked by hand: h = [1, 1j] has |H[k]| = |1 + 1j exp(-2 pi i k / N)|,
+    largest (2) where exp(-2 pi i k / N) = -1j, i.e. k = N / 4, while max|h|
+    is 1.  s = unit impulse at n = 3 (||s|| = 1), y = y_ref + 1 e_0 (an error
+    of norm 1): the metric is 1 / 2."""
+    s = np.zeros(N, np.complex128)
+    s[3] = 1.0
+    h = np.array([1.0 + 0j, 1j])
+    y_ref = np.zeros(N, np.complex128)
+    y_ref[3], y_ref[4] = 1.0, 1j
+    y = y_ref.copy()
+    y[0] += 1.0
+    assert abs(rel_error(y, y_ref, s, h)[()] - 0.5) <= 1e-15
+
+
+METRIC_PINS = [metric_pin_single_tap, metric_pin_two_taps, metric_pin_quarter_band]
+METRIC_MUTANTS = {1: "denominator ||y_ref||", 2: "denominator ||s|| without max|H|",
+                  3: "max over the taps instead of the spectrum"}
+
+
+@pytest.mark.parametrize("pin", METRIC_PINS, ids=lambda p: p.__name__)
+def test_rel_error_hand_values(pin):
+    pin(fo.rel_error)
+
+
+@pytest.mark.parametrize("mutant", sorted(METRIC_MUTANTS), ids=lambda k: METRIC_MUTANTS[k].replace(" ", "_"))
+def test_rel_error_pins_reject_planted_mistake(mutant):
+    caught = []
+    for pin in METRIC_PINS:
+        try:
+            pin(lambda *a: fo.rel_error(*a, _mutant=mutant))
+        except AssertionError:
+            caught.append(pin.__name__)
+    assert caught, f"planted mistake '{METRIC_MUTANTS[mutant]}' passed every metric pin"
+
+
 def test_rel_error_metric():
     rng = np.random.default_rng(32)
     s = wl.filter_signals(rng, 4)
