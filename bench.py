@@ -4,7 +4,9 @@
     python bench.py [--steps K] [--warmup W] [--workload full-width] [--prec fp32_3m]
 
 A step is one bf_apply over the whole batch (descriptor packing and upload,
-one kernel launch), with S already resident in HBM.  The default workload
+one kernel launch), with S already resident in HBM.  Before the --warmup
+steps the path runs for --settle-ms of wall time, so that the device has
+raised its clock as it does under continuous load.  The default workload
 is the full-width batch: 16384 products of 64x36 by 36x60 complex64, W from
 a pool of 64 unit-norm precoders, S normalised 256-QAM.  Three disjoint
 S/R buffer sets (2.4 GB) rotate so that the 256 MB last-level cache cannot
@@ -132,6 +134,27 @@ def probe_copy(mib: int = 1024) -> dict | None:
 
 
 GROUP = 10   # launches per event pair in the kernel timing
+
+
+def settle(step, ms: float, torch) -> int:
+    """Runs step(i) back to back for `ms` milliseconds of wall time and
+    returns how many ran.  The device raises its engine clock over the
+    first tens of milliseconds of sustained load (about 2.2 to 2.45 GHz,
+    GRBM_GUI_ACTIVE per dispatch) and lowers it again after a pause of a
+    few hundred milliseconds, so a fixed number of warm-up steps alone
+    would time part of that ramp instead of the continuous operation the
+    stage is built for."""
+    if ms <= 0:
+        return 0
+    t0 = time.perf_counter()
+    i = 0
+    while (time.perf_counter() - t0) * 1e3 < ms:
+        step(i)
+        i += 1
+        if i % 32 == 0:
+            torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    return i
 
 
 def time_launches(launch, steps, torch, stream, group=GROUP):
@@ -374,6 +397,8 @@ def filter_bench(args, torch) -> dict:
     ys = [torch.empty_like(xs[0]) for _ in range(args.copies)]
     stream = torch.cuda.current_stream()
     K, W = args.steps, args.warmup
+    settle(lambda i: bf.bf_filter_apply(flt, n, xs[i % args.copies], ys[i % args.copies]),
+           args.settle_ms, torch)
     for i in range(W):
         bf.bf_filter_apply(flt, n, xs[i % args.copies], ys[i % args.copies])
     torch.cuda.synchronize()
@@ -413,11 +438,12 @@ def filter_bench(args, torch) -> dict:
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    # The step time settles over the first ~200 steps of a process (about
-    # 235 -> 200 us at full width, whatever ran before), so the default
-    # warm-up covers that transient.
+    # Warm-up: --settle-ms of continuous running (the device's clock ramp),
+    # then --warmup steps.
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--settle-ms", type=float, default=400.0,
+                    help="run the path this long before the warm-up steps (device clock ramp)")
     ap.add_argument("--workload", default="full-width", choices=list(WORKLOADS))
     ap.add_argument("--prec", default="fp32_3m", choices=sorted(PRECS),
                     help="arithmetic form (default: FP32, three real products per complex one)")
@@ -481,6 +507,7 @@ def main(argv=None) -> int:
         tuned = bf.bf_autotune(plan, batch.w_ids, batch.f, db.s_ptrs[0], db.r_ptrs[0], prec, reps=5)
     variant = bf.bf_get_variant(plan, prec, bf.batch_bucket(batch.f))
 
+    settle_steps = settle(lambda i: db.apply(plan, prec, copy=i % args.copies), args.settle_ms, torch)
     for i in range(args.warmup):
         db.apply(plan, prec, copy=i % args.copies)
     torch.cuda.synchronize()
@@ -607,7 +634,8 @@ def main(argv=None) -> int:
                    "f": int(batch.f.max()) if batch.f.min() == batch.f.max() else "U{1..36}",
                    "prec": args.prec, "variant": {"schedule": variant[0], "wg_per_cu": variant[1],
                                                   "order": variant[2], "store": variant[3]},
-                   "buffer_sets": args.copies},
+                   "buffer_sets": args.copies,
+                   "settle": {"ms": args.settle_ms, "steps": settle_steps}},
         "latency_us": {"p50": round(float(np.percentile(step_ms, 50)) * 1e3, 2),
                        "p99": round(float(np.percentile(step_ms, 99)) * 1e3, 2)},
         "roofline": roof,

@@ -23,6 +23,11 @@ BUILD = PKG / "_build"
 LIB = PKG / "libbf.so"
 LOADGEN_SRC = PKG / "loadgen" / "bf_loadgen.cpp"
 LOADGEN = PKG / "loadgen" / "libbf_loadgen.so"
+HOSTEXEC = PKG / "hostexec" / "libbf_serve_host.so"
+# The serving loop's device-independent core, shared by libbf.so and the
+# host executor (no HIP in these sources).
+SERVE_CORE = [CSRC / "bf_serve_core.cpp", CSRC / "bf_status.cpp"]
+HOSTEXEC_SRC = PKG / "hostexec" / "bf_serve_host.cpp"
 
 ARCH = "gfx950"
 COMMON = [
@@ -78,9 +83,28 @@ def build(verbose: bool = False) -> Path:
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LOADGEN)
+    build_hostexec()
     if verbose:
-        print(f"built {LIB} and {LOADGEN}", file=sys.stderr)
+        print(f"built {LIB}, {LOADGEN} and {HOSTEXEC}", file=sys.stderr)
     return LIB
+
+
+def hostexec_cmd(out: Path, extra=()) -> list[str]:
+    """g++ line of the host executor (the serving core on a null device)."""
+    return ["g++", "-O2", "-std=c++17", "-fPIC", "-pthread", "-Wall", "-Wextra",
+            "-I", str(INCLUDE), "-I", str(CSRC), *extra,
+            str(HOSTEXEC_SRC), *map(str, SERVE_CORE), "-o", str(out)]
+
+
+def build_hostexec() -> Path:
+    """Builds hostexec/libbf_serve_host.so with g++ (no ROCm needed)."""
+    tmp = HOSTEXEC.with_suffix(".so.tmp")
+    cmd = hostexec_cmd(tmp, ["-shared"])
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"host executor build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, HOSTEXEC)
+    return HOSTEXEC
 
 
 if __name__ == "__main__":

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "bf_internal.h"
+#include "bf_status.h"
 
 #define BF_STRINGIFY2(x) #x
 #define BF_STRINGIFY(x) BF_STRINGIFY2(x)
@@ -15,6 +16,8 @@
 constexpr int kPrecCount = 6;
 constexpr int kBucketCount = 5;
 constexpr int kRingSlots = 8;
+// Items per descriptor block that every staging slot holds from plan creation.
+constexpr int kReserveItems = 16384;
 constexpr uint32_t kSupportedMask = BF_PREC_ALL;
 
 // One slot of the descriptor staging ring: a pinned host block, its device
@@ -85,7 +88,6 @@ struct FillStats {
 int batch_bucket(int64_t sum_f, int n);
 using FillFn = std::function<FillStats(BfItem *)>;
 
-bf_status bf_fail(bf_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 void order_items(const BfItem *in, BfItem *out, int n, int n_w, std::vector<int> &scratch);
 bfk::LaunchCfg choose_launch(bf_plan p, bf_prec prec, int n, int max_f, bool vec16,
                              bool uniform_f, const bf_variant *force);

@@ -15,10 +15,11 @@ from paper_1810_11451_amd import bf
 ROOT = Path(__file__).resolve().parents[1]
 
 
-def declared_functions():
-    text = (ROOT / "include" / "bf.h").read_text()
+def declared_functions(header="bf.h", prefix="bf_"):
+    text = (ROOT / "include" / header).read_text()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(bf_[a-z_0-9]+)\s*\(", text, flags=re.M)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(" + prefix + r"[a-z_0-9]+)\s*\(", text,
+                       flags=re.M)
     return sorted(set(names))
 
 
@@ -205,3 +206,15 @@ def test_packed_binding_checks_tensor_sizes():
     S_ok = torch.zeros(300, dtype=torch.complex64)
     with pytest.raises(ValueError, match="R_base"):
         bf.bf_apply_packed(NoPlan(), w, f, S_ok, s_off, R_ok[:2])
+
+
+def test_host_executor_exports_its_header():
+    """include/bf_serve_host.h: the host-only executor of the serving loop
+    exports every declared call, and its binding names them all."""
+    from paper_1810_11451_amd import hostexec
+    names = declared_functions("bf_serve_host.h", "bfh_")
+    assert "bfh_submit" in names and "bfh_device_complete" in names
+    H = hostexec.lib()
+    missing = [n for n in names if not hasattr(H, n)]
+    assert not missing, f"not exported: {missing}"
+    assert set(names) <= set(hostexec._SIGS), set(names) - set(hostexec._SIGS)
