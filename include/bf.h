@@ -141,6 +141,25 @@ bf_status bf_plan_update(bf_plan plan, int32_t w_id, const void *w, void *hip_st
 bf_status bf_apply(bf_plan plan, int32_t batch, const int32_t *w_ids, const int32_t *f,
                    const void *const *S, void *const *R, bf_prec prec, void *hip_stream);
 
+/* bf_apply for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.
+ * Same arguments, checks, products and results as bf_apply, for at most
+ * BF_NOALLOC_MAX_ITEMS products (more: BF_ERR_INVALID, nothing launched).
+ * The call allocates nothing: the descriptor block of the launch (the
+ * counters of the persistent kernels, which start at zero each call, the
+ * sink and the items) is written into a fixed array of the library
+ * (about 520 KB, held on each device it is used on until the process
+ * ends), uploaded on hip_stream from pinned host memory the plan reserved
+ * when it was created.  Every call on one device shares that array and it
+ * keeps the last call's contents: calls on different streams whose device
+ * work overlaps race on it (calls on one stream are ordered).  The
+ * current device must be the plan's (else BF_ERR_INVALID).  The tuning
+ * table's product order (order = 1) is not applied; every product's
+ * result is the same as in any order. */
+#define BF_NOALLOC_MAX_ITEMS 16384
+bf_status bf_apply_noalloc(bf_plan plan, int32_t batch, const int32_t *w_ids, const int32_t *f,
+                           const void *const *S, void *const *R, bf_prec prec, void *hip_stream);
+
 /* Same products for the common case of one S buffer and one R buffer:
  * S[t] = S_base + s_off[t] complex elements (host int64 [batch]),
  * R[t] = R_base + t * 64 * 60 complex elements (R_base 16-byte aligned). */

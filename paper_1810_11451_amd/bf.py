@@ -85,6 +85,7 @@ _SIGS = {
     "bf_filter_destroy": (_i32, [_vp]),
     "bf_apply": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _i32, _vp]),
     "bf_apply_packed": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _i32, _vp]),
+    "bf_apply_noalloc": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _i32, _vp]),
     "bf_check_batch": (_i32, [_i32, _i32, _i32, _vp, _vp, _vp, _vp]),
     "bf_graph_create": (_i32, [ctypes.POINTER(_vp), _vp, _i32, _vp, _vp, _vp, _vp, _i32, _vp]),
     "bf_graph_launch": (_i32, [_vp, _vp]),
@@ -262,6 +263,16 @@ def bf_apply(plan: Plan, w_ids, f, S_ptrs, R_ptrs, prec: int = BF_FP32, stream=N
     R = _ptr_array(R_ptrs, n)
     _check(lib().bf_apply(plan.handle, n, w_ids.ctypes.data, f.ctypes.data, S.ctypes.data,
                           R.ctypes.data, int(prec), _stream(stream)), "bf_apply")
+
+
+def bf_apply_noalloc(plan: Plan, w_ids, f, S_ptrs, R_ptrs, prec: int = BF_FP32, stream=None) -> None:
+    w_ids = _i32_array(w_ids)
+    n = w_ids.shape[0]
+    f = _i32_array(f, n)
+    S = _ptr_array(S_ptrs, n)
+    R = _ptr_array(R_ptrs, n)
+    _check(lib().bf_apply_noalloc(plan.handle, n, w_ids.ctypes.data, f.ctypes.data, S.ctypes.data,
+                                  R.ctypes.data, int(prec), _stream(stream)), "bf_apply_noalloc")
 
 
 def bf_apply_packed(plan: Plan, w_ids, f, S_base, s_off, R_base, prec: int = BF_FP32,

@@ -534,6 +534,56 @@ static void map_slots(bf_plan p, BfItem *items, int n)
         items[t].w_id += p->n_w * (int)p->half[(size_t)items[t].w_id];
 }
 
+// Uploads the descriptor block that `slot.host` holds (header, sink, n
+// items filled in, with statistics fs) to the device block `dev_blk` and
+// launches the apply kernel on st.  The upload runs on `copy_st`, which the
+// launch waits for.  With `may_order` the variant's product order is
+// applied (on host buffers of the plan).  Caller holds p->mu, and the
+// slot's previous launch has finished.
+static bf_status upload_and_launch(bf_plan p, bf_prec prec, int n, const FillStats &fs, StagingSlot &slot,
+                                   void *dev_blk, hipStream_t copy_st, hipStream_t st, bool may_order,
+                                   const bf_variant *force, int *grid_out)
+{
+    const size_t bytes = block_bytes(n);
+    BfItem *items = reinterpret_cast<BfItem *>(static_cast<char *>(slot.host) + sizeof(BfHeader) +
+                                               kSinkBytes);
+    const bool uniform_f = fs.min_f == fs.max_f;
+    bf_variant chosen = force ? *force : p->table[prec][batch_bucket(fs.sum_f, n)];
+    if (chosen.order == 1 && n > 1 && may_order) {
+        p->sort_tmp.resize((size_t)n);
+        order_items(items, p->sort_tmp.data(), n, p->n_w, p->sort_scratch);
+        std::memcpy(items, p->sort_tmp.data(), (size_t)n * sizeof(BfItem));
+    }
+    bfk::LaunchCfg cfg = choose_launch(p, prec, n, fs.max_f, fs.vec16, uniform_f, &chosen);
+    if (grid_out)
+        *grid_out = cfg.grid;
+    map_slots(p, items, n);
+
+    hipError_t e = hipMemcpyAsync(dev_blk, slot.host, bytes, hipMemcpyHostToDevice, copy_st);
+    if (e != hipSuccess)
+        return bf_fail(BF_ERR_DEVICE, "hipMemcpyAsync(descriptors): %s", hipGetErrorString(e));
+    if (copy_st != st) {
+        e = hipEventRecord(slot.copied, copy_st);
+        if (e == hipSuccess)
+            e = hipStreamWaitEvent(st, slot.copied, 0);
+        if (e != hipSuccess)
+            return bf_fail(BF_ERR_DEVICE, "descriptor upload ordering: %s", hipGetErrorString(e));
+    }
+    if (p->any_update) {   // the W of updated entries must be in place
+        e = hipStreamWaitEvent(st, p->updated, 0);
+        if (e != hipSuccess)
+            return bf_fail(BF_ERR_DEVICE, "update ordering: %s", hipGetErrorString(e));
+    }
+    e = launch_for_plan(p, cfg, static_cast<BfHeader *>(dev_blk), n, st);
+    if (e != hipSuccess)
+        return bf_fail(BF_ERR_DEVICE, "kernel launch: %s", hipGetErrorString(e));
+    e = hipEventRecord(slot.ev, st);
+    if (e != hipSuccess)
+        return bf_fail(BF_ERR_DEVICE, "hipEventRecord: %s", hipGetErrorString(e));
+    slot.launched = true;
+    return BF_OK;
+}
+
 // Common tail of bf_apply / bf_apply_packed / the serving batcher: items
 // are already validated and written by `fill` into host memory.
 bf_status enqueue_items(bf_plan p, bf_prec prec, int n, const FillFn &fill, hipStream_t st,
@@ -546,56 +596,18 @@ bf_status enqueue_items(bf_plan p, bf_prec prec, int n, const FillFn &fill, hipS
         p->ring.resize(kRingSlots);
     StagingSlot &slot = p->ring[p->ring_next];
     p->ring_next = (p->ring_next + 1) % p->ring.size();
-    const size_t bytes = block_bytes(n);
-    bf_status s = ensure_slot(slot, bytes);
+    bf_status s = ensure_slot(slot, block_bytes(n));
     if (s != BF_OK)
         return s;
-
     BfHeader *hdr = static_cast<BfHeader *>(slot.host);
     std::memset(hdr, 0, sizeof *hdr);
     hdr->n_items = (uint32_t)n;
-    BfItem *items = reinterpret_cast<BfItem *>(static_cast<char *>(slot.host) + sizeof(BfHeader) +
-                                               kSinkBytes);
-    const FillStats fs = fill(items);
-    const int max_f = fs.max_f;
-    const bool uniform_f = fs.min_f == fs.max_f;
-    const bool vec16 = fs.vec16;
-    bf_variant chosen = force ? *force : p->table[prec][batch_bucket(fs.sum_f, n)];
-    if (chosen.order == 1 && n > 1) {
-        p->sort_tmp.resize((size_t)n);
-        order_items(items, p->sort_tmp.data(), n, p->n_w, p->sort_scratch);
-        std::memcpy(items, p->sort_tmp.data(), (size_t)n * sizeof(BfItem));
-    }
-    bfk::LaunchCfg cfg = choose_launch(p, prec, n, max_f, vec16, uniform_f, &chosen);
-    if (grid_out)
-        *grid_out = cfg.grid;
-    map_slots(p, items, n);
-
+    const FillStats fs = fill(reinterpret_cast<BfItem *>(static_cast<char *>(slot.host) + sizeof(BfHeader) +
+                                                         kSinkBytes));
     // The slot's previous launch has finished (ensure_slot waited for it), so
     // the upload may run on the copy stream while the caller's stream is
     // still busy with earlier work; the launch waits only for the upload.
-    hipError_t e = hipMemcpyAsync(slot.dev, slot.host, bytes, hipMemcpyHostToDevice,
-                                  p->copy_stream);
-    if (e != hipSuccess)
-        return bf_fail(BF_ERR_DEVICE, "hipMemcpyAsync(descriptors): %s", hipGetErrorString(e));
-    e = hipEventRecord(slot.copied, p->copy_stream);
-    if (e == hipSuccess)
-        e = hipStreamWaitEvent(st, slot.copied, 0);
-    if (e != hipSuccess)
-        return bf_fail(BF_ERR_DEVICE, "descriptor upload ordering: %s", hipGetErrorString(e));
-    if (p->any_update) {   // the W of updated entries must be in place
-        e = hipStreamWaitEvent(st, p->updated, 0);
-        if (e != hipSuccess)
-            return bf_fail(BF_ERR_DEVICE, "update ordering: %s", hipGetErrorString(e));
-    }
-    e = launch_for_plan(p, cfg, static_cast<BfHeader *>(slot.dev), n, st);
-    if (e != hipSuccess)
-        return bf_fail(BF_ERR_DEVICE, "kernel launch: %s", hipGetErrorString(e));
-    e = hipEventRecord(slot.ev, st);
-    if (e != hipSuccess)
-        return bf_fail(BF_ERR_DEVICE, "hipEventRecord: %s", hipGetErrorString(e));
-    slot.launched = true;
-    return BF_OK;
+    return upload_and_launch(p, prec, n, fs, slot, slot.dev, p->copy_stream, st, true, force, grid_out);
 }
 
 hipError_t launch_for_plan(bf_plan p, const bfk::LaunchCfg &cfg, BfHeader *blk, int n,
@@ -656,6 +668,106 @@ extern "C" bf_status bf_apply(bf_plan p, int32_t batch, const int32_t *w_ids, co
     };
     return enqueue_items(p, prec, batch, fill, static_cast<hipStream_t>(hip_stream), nullptr,
                          nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// bf_apply_noalloc: bf_apply with its descriptor block (header with the
+// persistent kernels' counters, sink, items) in `scratch`, a fixed array of
+// the library that each device holds until the process ends, instead of a
+// staging slot's device block.  Host code reaches the array only through the
+// device address looked up once per device (g_scratch_ptr): the array's own
+// name is a host-side stand-in, not a device address.
+
+constexpr size_t kScratchBytes = sizeof(BfHeader) + kSinkBytes + (size_t)BF_NOALLOC_MAX_ITEMS * sizeof(BfItem);
+// (Referenced from host code, the array is emitted as a global symbol of
+// the device code object, which the runtime resolves by name.  An explicit
+// `used` attribute would keep it as a local symbol instead, which the
+// runtime cannot find.)
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+// Device address of `scratch` on device dev, which must be current.
+static bf_status scratch_on(int dev, void **out)
+{
+    if (dev < 0 || dev >= kMaxDevices)
+        return bf_fail(BF_ERR_UNSUPPORTED, "device %d beyond the %d this library tracks", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return bf_fail(BF_ERR_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return BF_OK;
+}
+
+extern "C" bf_status bf_apply_noalloc(bf_plan p, int32_t batch, const int32_t *w_ids, const int32_t *f,
+                                      const void *const *S, void *const *R, bf_prec prec, void *hip_stream)
+{
+    bf_status s = check_plan_prec(p, prec);
+    if (s != BF_OK)
+        return s;
+    if (batch > BF_NOALLOC_MAX_ITEMS)
+        return bf_fail(BF_ERR_INVALID, "batch %d above the %d products bf_apply_noalloc holds", batch,
+                       BF_NOALLOC_MAX_ITEMS);
+    s = bf_check_batch(p->n_w, p->f_max, batch, w_ids, f, S, R);
+    if (s != BF_OK || batch == 0)
+        return s;
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return bf_fail(BF_ERR_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev != p->device)
+        return bf_fail(BF_ERR_INVALID, "current device %d is not the plan's device %d", dev, p->device);
+    void *blk = nullptr;
+    s = scratch_on(dev, &blk);
+    if (s != BF_OK)
+        return s;
+    const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+
+    std::lock_guard<std::mutex> lk(p->mu);
+    const size_t bytes = block_bytes(batch);
+    if (p->ring.empty())
+        return bf_fail(BF_ERR_DEVICE, "plan has no staging ring");
+    StagingSlot &slot = p->ring[p->ring_next];
+    // (every slot holds kReserveItems >= BF_NOALLOC_MAX_ITEMS items from plan creation on)
+    if (slot.cap < bytes || !slot.ev || !slot.host)
+        return bf_fail(BF_ERR_DEVICE, "staging slot below its reserve");
+    p->ring_next = (p->ring_next + 1) % p->ring.size();
+    e = hipEventSynchronize(slot.ev);   // the slot's previous launch is done with its host block
+    if (e != hipSuccess)
+        return bf_fail(BF_ERR_DEVICE, "hipEventSynchronize(staging): %s", hipGetErrorString(e));
+    BfHeader *hdr = static_cast<BfHeader *>(slot.host);
+    std::memset(hdr, 0, sizeof *hdr);   // the kernels' counters start at zero
+    hdr->n_items = (uint32_t)batch;
+    BfItem *items = reinterpret_cast<BfItem *>(static_cast<char *>(slot.host) + sizeof(BfHeader) + kSinkBytes);
+    FillStats fs{0, true, 0};
+    for (int32_t t = 0; t < batch; ++t) {
+        BfItem &it = items[t];
+        it.S = static_cast<const float2 *>(S[t]);
+        it.R = static_cast<float2 *>(R[t]);
+        it.w_id = w_ids[t];
+        it.f = f[t];
+        it.pad0 = it.pad1 = 0;
+        fs.max_f = std::max(fs.max_f, (int)f[t]);
+        fs.min_f = std::min(fs.min_f, (int)f[t]);
+        fs.sum_f += f[t];
+        if (f[t] > 0 && !aligned16(S[t]))
+            fs.vec16 = false;
+    }
+    // The upload is ordered on the caller's stream: the array is shared by
+    // every call on this device, so it must not be overwritten while an
+    // earlier call's kernel on that stream still reads it.
+    return upload_and_launch(p, prec, batch, fs, slot, blk, st, st, false, nullptr, nullptr);
 }
 
 extern "C" bf_status bf_apply_packed(bf_plan p, int32_t batch, const int32_t *w_ids,

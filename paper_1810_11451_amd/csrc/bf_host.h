@@ -18,6 +18,7 @@ constexpr int kBucketCount = 5;
 constexpr int kRingSlots = 8;
 // Items per descriptor block that every staging slot holds from plan creation.
 constexpr int kReserveItems = 16384;
+static_assert(kReserveItems >= BF_NOALLOC_MAX_ITEMS, "staging reserve covers bf_apply_noalloc");
 constexpr uint32_t kSupportedMask = BF_PREC_ALL;
 
 // One slot of the descriptor staging ring: a pinned host block, its device
