@@ -177,18 +177,101 @@ def time_launches(launch, steps, torch, stream, group=GROUP):
     return np.array([a.elapsed_time(b) / group for a, b in ev])
 
 
-def kernel_time_graph(plan, db, batch, prec, steps, copies, torch, stream):
+def kernel_time_graph(plan, db, batch, prec, steps, copies, torch, stream, settle_ms: float = 200.0):
     """Average duration of the apply kernel alone: the same kernel and grid,
     launched from captured graphs (descriptors already on the device), one
-    graph per buffer set, timed with HIP events on the launch stream."""
+    graph per buffer set, run for settle_ms (creating the graphs leaves the
+    device idle long enough for its clock to drop), then at least 200
+    launches timed with HIP events on the launch stream."""
     graphs = [bf.bf_graph_create(plan, batch.w_ids, batch.f, db.s_ptrs[c], db.r_ptrs[c], prec)
               for c in range(copies)]
-    for c in range(copies):
-        bf.bf_graph_launch(graphs[c], stream)
-    ms = time_launches(lambda i: bf.bf_graph_launch(graphs[i % copies], stream), steps, torch, stream)
+    launch = lambda i: bf.bf_graph_launch(graphs[i % copies], stream)  # noqa: E731
+    settle(launch, settle_ms, torch)
+    ms = time_launches(launch, max(steps, 200), torch, stream)
     for g in graphs:
         g.close()
     return ms
+
+
+def workload_kernel(batch, prec: int, torch, stream, copies: int, settle_ms: float, launches: int,
+                    sample: int = 256) -> dict:
+    """Kernel time of one precision form on one workload at steady state:
+    the plan's default variant, launched from captured graphs over `copies`
+    disjoint buffer sets, run for settle_ms, then `launches` launches timed
+    with HIP events in groups.  Also returns (under "_sample") host copies of
+    a seeded sample of the products of the last launch, for the CPU leg's
+    error check."""
+    from paper_1810_11451_amd.device import DeviceBatch
+    plan = bf.bf_plan_create(batch.W, bf.BF_PREC_BIT(prec))
+    db = DeviceBatch(batch, copies=copies, fill_r=None)
+    graphs = [bf.bf_graph_create(plan, batch.w_ids, batch.f, db.s_ptrs[c], db.r_ptrs[c], prec)
+              for c in range(copies)]
+    launch = lambda i: bf.bf_graph_launch(graphs[i % copies], stream)  # noqa: E731
+    settle(launch, settle_ms, torch)
+    ms = time_launches(launch, launches, torch, stream)
+    last = (len(ms) * GROUP - 1) % copies
+    items = np.sort(np.random.default_rng(777).choice(batch.n, size=min(sample, batch.n), replace=False))
+    got = db.R[last].index_select(0, torch.as_tensor(items, device=db.R[last].device)).cpu().numpy()
+    variant = bf.bf_get_variant(plan, prec, bf.batch_bucket(batch.f))
+    for g in graphs:
+        g.close()
+    plan.close()
+    del db
+    torch.cuda.empty_cache()
+    us = float(np.mean(ms)) * 1e3
+    nbytes = batch.bytes_moved()
+    sched = launched_schedule(prec, variant[0])
+    return {"prec": bf.PREC_NAMES[prec], "kernel": kernel_symbol(prec, sched, variant[3]),
+            "variant": list(variant), "kernel_us_mean": round(us, 2),
+            "kernel_us_p50": round(float(np.median(ms)) * 1e3, 2),
+            "hbm_gbs": round(nbytes / (us * 1e-6) / 1e9, 1),
+            "hbm_frac": round(nbytes / (us * 1e-6) / (PEAK_HBM_GBS * 1e9), 4),
+            "complex_gflops": round(batch.flops() / (us * 1e-6) / 1e9, 1),
+            "_sample": (items, got)}
+
+
+def side_workloads(args, torch, stream) -> dict:
+    """The two further workloads in the same run, kernel time only: the
+    uneven batch (8192 products, f ~ U{1..36}, pool of 256 W) in the
+    three-product FP32 form, and the gain workload (the full-width batch
+    with per-product gains 10^U(-3, 3)) in the four 16-bit forms."""
+    out = {}
+    ub = wl.uneven_batch()
+    e = workload_kernel(ub, bf.BF_FP32_3M, torch, stream, args.copies, 200.0, 200)
+    e["traffic"] = load_traffic("uneven-fp32_3m", e["kernel"], e["variant"])
+    e["workload"] = ub.name
+    e["_batch"] = ub
+    out["uneven_batch"] = e
+    gb = wl.gain_batch()
+    forms = {}
+    for name in ("fp16x2", "bf16x2", "fp16", "bf16"):
+        r = workload_kernel(gb, PRECS[name], torch, stream, args.copies, 200.0, 200)
+        r["traffic"] = load_traffic(f"gain-{name}", r["kernel"], r["variant"])
+        forms[name] = r
+        print(f"[bench] gain workload {name}: {r['kernel_us_mean']} us", file=sys.stderr, flush=True)
+    out["gain_workload"] = {"workload": gb.name, "forms": forms, "_batch": gb}
+    return out
+
+
+def side_errors(side: dict) -> None:
+    """CPU leg: relative Frobenius error of the sampled products of each side
+    workload against the FP64 oracle (FP32 bar 2e-6, split forms 2e-5,
+    plain 16-bit forms reported only)."""
+    from oracle import oracle as orc
+
+    def err_of(batch, entry):
+        items, got = entry.pop("_sample")
+        nz = batch.f[items] > 0
+        err = orc.rel_frobenius(got, orc.apply(batch, items=items))
+        entry["max_rel_err_sample"] = float(f"{np.max(err[nz]):.3g}") if np.any(nz) else 0.0
+        entry["sample"] = f"{len(items)} seeded products of the last launch"
+
+    ue = side["uneven_batch"]
+    err_of(ue.pop("_batch"), ue)
+    g = side["gain_workload"]
+    gb = g.pop("_batch")
+    for entry in g["forms"].values():
+        err_of(gb, entry)
 
 
 def issued_flops(batch, prec: int) -> int:
@@ -230,12 +313,13 @@ def launched_schedule(prec: int, schedule: int) -> int:
     return schedule
 
 
-def kernel_symbol(prec: int, schedule: int) -> str:
+def kernel_symbol(prec: int, schedule: int, store: int = 0) -> str:
     """Name (as rocprofv3 lists it, without template arguments) of the apply
-    kernel that a precision form and launched schedule run."""
+    kernel that a precision form, launched schedule and variant store field
+    run (store 6 and 7: the three-product form on 16 x 16 tiles)."""
     if prec in (bf.BF_FP32, bf.BF_FP32_3M):
         if schedule == 3:
-            return "apply_fp32_ws"
+            return "apply_fp32_3m16_ws" if prec == bf.BF_FP32_3M and store >= 6 else "apply_fp32_ws"
         if prec == bf.BF_FP32_3M:
             return "apply_fp32_3m_single"
         return {0: "apply_fp32_single", 1: "apply_fp32_claim", 2: "apply_fp32_stream"}[schedule]
@@ -561,6 +645,10 @@ def main(argv=None) -> int:
                  "hbm_gbs_equiv": round(batch.bytes_moved() / (float(np.mean(ks)) / 1e3) / 1e9, 1),
                  "variant": list(vs)}
 
+    side = None
+    if args.workload == "full-width" and prec == bf.BF_FP32_3M and not args.no_compare:
+        side = side_workloads(args, torch, stream)
+
     flops = batch.flops()
     nbytes = batch.bytes_moved()
     value = flops * K / wall / 1e9
@@ -569,7 +657,7 @@ def main(argv=None) -> int:
     peak_flops = (PEAK_LP_TFLOPS if lp else PEAK_FP32_TFLOPS) * 1e12
     key = f"{args.workload}-{args.prec}"
     sched = launched_schedule(prec, variant[0])
-    traffic = load_traffic(key, kernel_symbol(prec, sched), variant)
+    traffic = load_traffic(key, kernel_symbol(prec, sched, variant[3]), variant)
     floors = roof_floors_us(batch, prec)
     if floors["compute_us"] > floors["hbm_us"]:
         ach = flops / kern_s / 1e12
@@ -580,12 +668,12 @@ def main(argv=None) -> int:
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(ach / PEAK_HBM_GBS, 4)}
     roof["traffic"] = traffic
-    roof["kernel"] = kernel_symbol(prec, sched)
+    roof["kernel"] = kernel_symbol(prec, sched, variant[3])
     roof["kernel_us_mean"] = round(kern_s * 1e6, 2)
     roof["kernel_us_p50"] = round(float(np.median(kern_ms)) * 1e3, 2)
     roof["kernel_us_min"] = round(float(np.min(kern_ms)) * 1e3, 2)
     roof["kernel_timing"] = ("HIP events on the launch stream around groups of 10 back-to-back graph "
-                             "launches of the same kernel and grid")
+                             "launches of the same kernel and grid, after 200 ms of such launches")
     roof["step_us_mean"] = round(float(np.mean(step_ms)) * 1e3, 2)
     roof["algorithmic"] = {"flops_per_launch": flops, "bytes_per_launch": nbytes,
                            "ai_flop_per_byte": round(ai, 2)}
@@ -650,9 +738,22 @@ def main(argv=None) -> int:
     if split is not None:
         split["speedup_over_this_form"] = round(kern_s * 1e6 / split["kernel_us_mean"], 3)
         out["compare_split_fp16x2"] = split
+    if side is not None:
+        g = side["gain_workload"]
+        for entry in g["forms"].values():
+            entry["speedup_over_fp32_3m_full_width"] = round(kern_s * 1e6 / entry["kernel_us_mean"], 3)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(batch, args.cpu_seconds)
         out["cpu_other"] = cpu_extra(batch, min(3.0, args.cpu_seconds))
+        if side is not None:
+            side_errors(side)
+    if side is not None:
+        for entry in [side["uneven_batch"]] + list(side["gain_workload"]["forms"].values()):
+            entry.pop("_sample", None)
+        side["uneven_batch"].pop("_batch", None)
+        side["gain_workload"].pop("_batch", None)
+        out["uneven_batch"] = side["uneven_batch"]
+        out["gain_workload"] = side["gain_workload"]
     plan.close()
     print(json.dumps(out), flush=True)
     return 0

@@ -216,7 +216,10 @@ typedef struct {
                               workgroup and products prefetched in their
                               registers, 0 = (4, 1), 1 = (8, 1), 2 = (8, 2),
                               3 = (8, 3), 4 = (12, 1), 5 = (12, 2); the
-                              three-product form uses at most 8 producers; the
+                              three-product form uses at most 8 producers, and
+                              with 6 = (8, 1) or 7 = (8, 2) runs 8 matrix-core
+                              waves on 16 x 16 tiles instead of 4 on 32 x 32
+                              (6 and 7 read as 0 for the other forms); the
                               16-bit forms prefetch at least 2 products, and 3
                               only with 8 producers */
 } bf_variant;

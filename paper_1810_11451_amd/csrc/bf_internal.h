@@ -47,17 +47,25 @@ constexpr int kThreads = 64 * kWaves;
 // Operand layout of one W for the FP32 matrix-core form: float2 entries
 // [kWaves][pairs][64 lanes]; see bf_kernels.hip.
 inline size_t fp32_w_stride(int pairs) { return (size_t)kWaves * pairs * 64; }
-// Three-product FP32 form: floats [2 antenna halves][pairs][2][64 lanes] per
-// W, the 2 being Wr and Wi of the lane's (antenna, flow); the kernels form
-// Wr + Wi with one FP32 add.
-inline size_t fp32_3m_w_stride(int pairs) { return (size_t)2 * pairs * 2 * 64; }
+// Three-product FP32 form, two layouts of each W one after the other (the
+// kernels form Wr + Wi with one FP32 add):
+//   32 x 32 tiles: floats [2 antenna halves][pairs][2][64 lanes], the 2
+//     being Wr and Wi of the lane's (antenna, flow);
+//   16 x 16 tiles, at fp32_3m16_offset: floats [4 antenna blocks][steps]
+//     [2][64 lanes], steps = ceil(pairs / 2) blocks of 4 flows.
+constexpr size_t fp32_3m16_offset(int pairs) { return (size_t)2 * pairs * 2 * 64; }
+constexpr int fp32_3m16_steps(int pairs) { return (pairs + 1) / 2; }
+constexpr size_t fp32_3m_w_stride(int pairs)
+{
+    return fp32_3m16_offset(pairs) + (size_t)4 * fp32_3m16_steps(pairs) * 2 * 64;
+}
 
 // Device-side view of a plan, as the apply kernels need it.
 struct PlanDev {
     const float2 *a_fp32;     // FP32 form: kWaves x pairs x 64 float2 per W
     int a_fp32_stride;        // float2 per W
     int pairs;                // ceil(f_max / 2)
-    const float *a_3m;        // three-product form: 2 x pairs x 2 x 64 floats per W
+    const float *a_3m;        // three-product form: both layouts, a_3m_stride floats per W
     int a_3m_stride;          // floats per W
     const void *lp_hi;        // plain 16-bit forms: kWaves x chunks x 64 x 16 bytes per W
     const int *lp_exp;        // per-W power-of-two exponent of the 16-bit operands
@@ -94,8 +102,9 @@ struct LaunchCfg {
     int grid;        // workgroups
     bool vec16;      // all S 16-byte aligned
     bool stage;      // R rows staged in LDS and written as contiguous 16-byte stores
-    int producers;   // schedule 3: producer waves per workgroup (4 or 8)
+    int producers;   // schedule 3: producer waves per workgroup (4, 8 or 12)
     int depth;       // schedule 3: products of S prefetched in producer registers (1..3)
+    bool tile16;     // schedule 3, three-product form: 8 matrix-core waves on 16 x 16 tiles
 };
 
 hipError_t launch_apply(const LaunchCfg &cfg, BfHeader *blk, int n_items, const PlanDev &pd,

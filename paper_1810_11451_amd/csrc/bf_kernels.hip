@@ -30,6 +30,7 @@
 namespace bfk {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef float f2v __attribute__((ext_vector_type(2)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef float f3v __attribute__((ext_vector_type(3)));
@@ -107,26 +108,42 @@ hipError_t launch_w_transform_fp32(const float2 *w_dev, int n_w, int f_max, floa
     return hipGetLastError();
 }
 
-// Plan-time operand layout, three-product FP32 form.  For
-// v_mfma_f32_32x32x2_f32 with real rows = antennas: lane l of antenna half
-// mt holds, for pair p, antenna i = 32 mt + l % 32 and flow k = 2p + l / 32,
-// in two planes: Wr, then Wi (the kernels form Wr + Wi).  Flows k >= f_max
-// hold zeros.
+// Plan-time operand layouts, three-product FP32 form, both per W (Wr and Wi
+// planes; flows k >= f_max hold zeros; the kernels form Wr + Wi):
+//   32 x 32 tiles (v_mfma_f32_32x32x2_f32, real rows = antennas): lane l of
+//     antenna half mt holds, for pair p, antenna 32 mt + l % 32 and flow
+//     2p + l / 32;
+//   16 x 16 tiles (v_mfma_f32_16x16x4_f32), after the first: lane l of
+//     antenna block rb holds, for step s, antenna 16 rb + l % 16 and flow
+//     4s + l / 16 (the instruction's A operand: row l % 16, K index l / 16).
 __global__ void w_transform_3m_kernel(const float2 *__restrict__ w, int n_w, int f_max,
                                       float *__restrict__ a, int pairs)
 {
-    // Entry (W wi, half mt, pair p, component c, lane): antenna 32 mt + lane % 32,
-    // flow 2 p + lane / 32; c = 0, 1 -> Wr, Wi (zero past f_max).
-    const size_t total = (size_t)n_w * 2 * pairs * 2 * 64;
+    const size_t per_w = fp32_3m_w_stride(pairs);
+    const size_t off16 = fp32_3m16_offset(pairs);
+    const int steps = fp32_3m16_steps(pairs);
+    const size_t total = (size_t)n_w * per_w;
     for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
          idx += (size_t)gridDim.x * blockDim.x) {
-        const int lane = (int)(idx % 64);
-        const int c = (int)((idx / 64) % 2);
-        const int p = (int)((idx / (64 * 2)) % pairs);
-        const int mt = (int)((idx / (64 * 2 * (size_t)pairs)) % 2);
-        const size_t wi = idx / (64 * 2 * (size_t)pairs * 2);
-        const int i = 32 * mt + (lane & 31);
-        const int k = 2 * p + (lane >> 5);
+        const size_t wi = idx / per_w;
+        const size_t e = idx - wi * per_w;
+        const int lane = (int)(e % 64);
+        const int c = (int)((e / 64) % 2);
+        int i, k;
+        if (e < off16) {
+            // (half mt, pair p, component c, lane)
+            const int p = (int)((e / (64 * 2)) % pairs);
+            const int mt = (int)(e / (64 * 2 * (size_t)pairs));
+            i = 32 * mt + (lane & 31);
+            k = 2 * p + (lane >> 5);
+        } else {
+            // (block rb, step s, component c, lane)
+            const size_t e16 = e - off16;
+            const int s = (int)((e16 / (64 * 2)) % steps);
+            const int rb = (int)(e16 / (64 * 2 * (size_t)steps));
+            i = 16 * rb + (lane & 15);
+            k = 4 * s + (lane >> 4);
+        }
         float out = 0.f;
         if (k < f_max) {
             const float2 v = w[(wi * kM + i) * (size_t)f_max + k];
@@ -139,7 +156,7 @@ __global__ void w_transform_3m_kernel(const float2 *__restrict__ w, int n_w, int
 hipError_t launch_w_transform_3m(const float2 *w_dev, int n_w, int f_max, float *a_out,
                                  int pairs, hipStream_t st)
 {
-    const size_t total = (size_t)n_w * 2 * pairs * 2 * 64;
+    const size_t total = (size_t)n_w * fp32_3m_w_stride(pairs);
     if (total == 0)
         return hipSuccess;
     const int block = 256;
@@ -869,24 +886,31 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
 }
 
 // Producer-side staging over kProd waves, in 16-byte chunks with clamped
-// indices: S of one product and, for the three-product form (kW), the
-// operands of its W.  The plan holds them as 2 halves x pairs x 2 planes x
-// 64 floats (Wr, Wi; 32 chunks per pair); the producers load them in units
-// of one 4-lane chunk of each plane (2 halves x pairs x 16 units) and stage
-// them in the same layout; the consumers form Wr + Wi with one FP32 add.
+// indices: S of one product and, for the three-product form, the operands
+// of its W in one of the plan's two layouts (kW = 1: 32 x 32 tiles, kW = 2:
+// 16 x 16 tiles; kW = 0: no W).  The 32 x 32 layout is 2 halves x pairs x 2
+// planes x 64 floats (Wr, Wi; 32 chunks per pair); the producers load it in
+// units of one 4-lane chunk of each plane (2 halves x pairs x 16 units).
+// The 16 x 16 layout is 4 blocks x steps x 2 planes x 64 floats, loaded in
+// plain 16-byte chunks.  Both are staged in LDS in the plan's layout; the
+// consumers form Wr + Wi with one FP32 add.
 constexpr int kWUnitsMax = kPairsMax * 32;
-constexpr int kWFloatsMax = kPairsMax * 256;   // staged in LDS: 2 halves x pairs x 2 planes x 64
+constexpr int kWFloatsMax = kPairsMax * 256;   // staged in LDS (either layout fits)
+constexpr int kSteps16Max = (kPairsMax + 1) / 2;          // blocks of 4 flows
+constexpr int kW16ChunksMax = 4 * kSteps16Max * 2 * 16;   // 16-byte chunks of a 16 x 16 layout W
+static_assert(4 * kSteps16Max * 2 * 64 <= kWFloatsMax, "16 x 16 layout fits the W buffer");
 
-template <int kProd, bool kW = false>
+template <int kProd, int kW = 0>
 struct PRegs {
     static constexpr int kN = (kFMax * kB / 2 + 64 * kProd - 1) / (64 * kProd);
-    static constexpr int kWRounds = (kWUnitsMax + 64 * kProd - 1) / (64 * kProd);
-    static constexpr int kNW = kW ? 2 * kWRounds : 1;
+    static constexpr int kWRounds = kW == 2 ? (kW16ChunksMax + 64 * kProd - 1) / (64 * kProd)
+                                            : (kWUnitsMax + 64 * kProd - 1) / (64 * kProd);
+    static constexpr int kNW = kW == 1 ? 2 * kWRounds : (kW == 2 ? kWRounds : 1);
     f4v v[kN];
     f4v w[kNW];
 };
 
-template <int kProd, bool kW>
+template <int kProd, int kW>
 __device__ __forceinline__ void p_load_s(PRegs<kProd, kW> &r, const float2 *__restrict__ S, int f, int ptid)
 {
     g_cf4v *src = (g_cf4v *)S;
@@ -912,14 +936,14 @@ __device__ __forceinline__ int w_unit_chunk(int u, int pairs)
 // (a cache hit; nothing of them reaches LDS).  Units past the end repeat
 // the last unit.
 template <int kProd>
-__device__ __forceinline__ void p_load_w(PRegs<kProd, true> &r, const float *__restrict__ wsrc, int pairs,
+__device__ __forceinline__ void p_load_w(PRegs<kProd, 1> &r, const float *__restrict__ wsrc, int pairs,
                                          int need, int ptid)
 {
     g_cf4v *src = (g_cf4v *)wsrc;
     const int units = pairs * 32;
     const int last_q = min(pairs, need) - 1;
 #pragma unroll
-    for (int k = 0; k < PRegs<kProd, true>::kWRounds; ++k) {
+    for (int k = 0; k < PRegs<kProd, 1>::kWRounds; ++k) {
         int u = min(ptid + k * 64 * kProd, units - 1);
         const int per_half = pairs * 16;
         const int h = u >= per_half ? 1 : 0;
@@ -935,13 +959,13 @@ __device__ __forceinline__ void p_load_w(PRegs<kProd, true> &r, const float *__r
 // (the only ones the product's chain reads) into the staged layout,
 // [2 halves][pairs][2][64] floats, the plan's own.
 template <int kProd>
-__device__ __forceinline__ void p_put_w(float *__restrict__ lds_a, const PRegs<kProd, true> &r, int pairs,
+__device__ __forceinline__ void p_put_w(float *__restrict__ lds_a, const PRegs<kProd, 1> &r, int pairs,
                                         int need, int ptid)
 {
     const int per_half = pairs * 16;
     const int used = min(pairs, need) * 16;
 #pragma unroll
-    for (int k = 0; k < PRegs<kProd, true>::kWRounds; ++k) {
+    for (int k = 0; k < PRegs<kProd, 1>::kWRounds; ++k) {
         const int u = ptid + k * 64 * kProd;
         if (u < 2 * per_half && (u < per_half ? u : u - per_half) < used) {
             f4v *dst = reinterpret_cast<f4v *>(lds_a) + w_unit_chunk(u, pairs);
@@ -951,7 +975,46 @@ __device__ __forceinline__ void p_put_w(float *__restrict__ lds_a, const PRegs<k
     }
 }
 
-template <int kProd, bool kW>
+// The 16 x 16 layout of one W (`steps` blocks of 4 flows per antenna block
+// and plane): chunk u holds floats 4 (u % 16) .. of the 64 lanes of block
+// u / 32 / steps, step (u / 32) % steps, plane (u / 16) % 2.  Only steps
+// below `need` (>= 1) are used by the product; chunks of later steps load
+// the last used step's chunk again (a cache hit) and are not staged.
+__device__ __forceinline__ int w16_chunk(int u, int steps, int need)
+{
+    const int s = (u >> 5) % steps;
+    return s < need ? u : u - ((s - need + 1) << 5);
+}
+
+template <int kProd>
+__device__ __forceinline__ void p_load_w16(PRegs<kProd, 2> &r, const float *__restrict__ wsrc, int steps,
+                                           int need, int ptid)
+{
+    g_cf4v *src = (g_cf4v *)wsrc;
+    const int units = steps * 128;
+#pragma unroll
+    for (int k = 0; k < PRegs<kProd, 2>::kWRounds; ++k)
+        r.w[k] = src[w16_chunk(min(ptid + k * 64 * kProd, units - 1), steps, need)];
+}
+
+template <int kProd>
+__device__ __forceinline__ void p_put_w16(float *__restrict__ lds_a, const PRegs<kProd, 2> &r, int steps,
+                                          int need, int ptid)
+{
+    const int units = steps * 128;
+#pragma unroll
+    for (int k = 0; k < PRegs<kProd, 2>::kWRounds; ++k) {
+        const int u = ptid + k * 64 * kProd;
+        if (u < units && ((u >> 5) % steps) < need)
+            reinterpret_cast<f4v *>(lds_a)[u] = r.w[k];
+    }
+}
+
+// Puts S into LDS row by row (pitch kLdsCols).  The rows between f and the
+// next multiple of the contraction's flow granularity (2 flows for the
+// 32 x 32 tiles, 4 for the 16 x 16 tiles) are cleared, so that the unused
+// part of the last step multiplies zeros.
+template <int kProd, int kW>
 __device__ __forceinline__ void p_put_s(f2v *__restrict__ lds, const PRegs<kProd, kW> &r, int f, int ptid)
 {
     const int chunks = f * (kB / 2);
@@ -964,7 +1027,11 @@ __device__ __forceinline__ void p_put_s(f2v *__restrict__ lds, const PRegs<kProd
             *reinterpret_cast<f4v *>(lds + row * kLdsCols + 2 * col2) = r.v[u];
         }
     }
-    if (f & 1) {
+    if constexpr (kW == 2) {
+        const int gap = ((f + 3) & ~3) - f;
+        if (ptid < gap * kLdsCols)
+            lds[f * kLdsCols + ptid] = f2v{0.f, 0.f};
+    } else if (f & 1) {
         if (ptid < kLdsCols)
             lds[f * kLdsCols + ptid] = f2v{0.f, 0.f};
     }
@@ -992,18 +1059,22 @@ __device__ __forceinline__ void p_store_r(float2 *__restrict__ Rp, const f2v *__
 
 // Everything the producers move for one product: its S and, for the
 // three-product form, its W operands.
-template <int kProd, bool k3M>
-__device__ __forceinline__ void p_load_item(PRegs<kProd, k3M> &r, const BfItem &d, bool real, float2 *sink,
+template <int kProd, int kW>
+__device__ __forceinline__ void p_load_item(PRegs<kProd, kW> &r, const BfItem &d, bool real, float2 *sink,
                                             const void *apool, int a_w_stride, int pairs, int ptid)
 {
-    p_load_s<kProd, k3M>(r, real && d.f > 0 ? d.S : sink, real ? d.f : 0, ptid);
-    if constexpr (k3M)
+    p_load_s<kProd, kW>(r, real && d.f > 0 ? d.S : sink, real ? d.f : 0, ptid);
+    if constexpr (kW == 1)
         p_load_w<kProd>(r, static_cast<const float *>(apool) + (size_t)d.w_id * a_w_stride, pairs,
                         max((d.f + 1) >> 1, 1), ptid);
+    if constexpr (kW == 2)
+        p_load_w16<kProd>(r, static_cast<const float *>(apool) + (size_t)d.w_id * a_w_stride +
+                                 fp32_3m16_offset(pairs),
+                          fp32_3m16_steps(pairs), max((d.f + 3) >> 2, 1), ptid);
 }
 
 // Largest |Re|, |Im| (as float bits) over the valid chunks of a staged S.
-template <int kProd, bool kW>
+template <int kProd, int kW>
 __device__ __forceinline__ uint32_t p_absmax(const PRegs<kProd, kW> &r, int f, int ptid)
 {
     const int chunks = f * (kB / 2);
@@ -1022,16 +1093,18 @@ __device__ __forceinline__ uint32_t p_absmax(const PRegs<kProd, kW> &r, int f, i
 // Puts one product's data into LDS.  kMax (16-bit forms): each producer wave
 // also leaves the largest |Re|, |Im| of its part of S in smax[wave], from
 // which the consumers take the product's power-of-two scale.
-template <int kProd, bool k3M, bool kMax>
+template <int kProd, int kW, bool kMax>
 __device__ __forceinline__ void p_put_item(f2v *__restrict__ s_lds, float *__restrict__ a_lds,
-                                           uint32_t *__restrict__ smax, const PRegs<kProd, k3M> &r,
+                                           uint32_t *__restrict__ smax, const PRegs<kProd, kW> &r,
                                            int f, int pairs, int ptid)
 {
-    p_put_s<kProd, k3M>(s_lds, r, f, ptid);
-    if constexpr (k3M)
+    p_put_s<kProd, kW>(s_lds, r, f, ptid);
+    if constexpr (kW == 1)
         p_put_w<kProd>(a_lds, r, pairs, max((f + 1) >> 1, 1), ptid);
+    if constexpr (kW == 2)
+        p_put_w16<kProd>(a_lds, r, fp32_3m16_steps(pairs), max((f + 3) >> 2, 1), ptid);
     if constexpr (kMax) {
-        const uint32_t m = wave_max_u32(p_absmax<kProd, k3M>(r, f, ptid));
+        const uint32_t m = wave_max_u32(p_absmax<kProd, kW>(r, f, ptid));
         if ((ptid & 63) == 0)
             smax[ptid >> 6] = m;
     }
@@ -1074,38 +1147,39 @@ struct WsLds<true, kProd> {
 // the end of the share the descriptor index is clamped and the S loads read
 // the sink, so every memory instruction is unconditional; a put past the
 // end fills LDS buffers nobody reads any more.
-template <int kProd, int kDepth, int kPut, bool k3M, bool kMax, int kLag>
-__device__ __forceinline__ void ws_produce_step(PRegs<kProd, k3M> (&sr)[kDepth], c_item *my, int stride,
-                                                int t, int n_my, float2 *sink, WsLds<k3M, kProd> &L,
+template <int kProd, int kDepth, int kPut, int kW, bool kMax, int kLag>
+__device__ __forceinline__ void ws_produce_step(PRegs<kProd, kW> (&sr)[kDepth], c_item *my, int stride,
+                                                int t, int n_my, float2 *sink, WsLds<kW != 0, kProd> &L,
                                                 const void *apool, int a_w_stride, int pairs, int ptid)
 {
     p_store_r<kProd>(item_at(my, t - kLag, stride).R, L.r_buf[(t - kLag) & 1], ptid);
     const BfItem d1 = item_at(my, min(t + 1, n_my - 1), stride);
-    p_put_item<kProd, k3M, kMax>(L.s_buf[(t + 1) & 1], L.a_buf.v[(t + 1) & 1], L.smax[(t + 1) & 1],
-                                 sr[kPut], d1.f, pairs, ptid);
+    p_put_item<kProd, kW, kMax>(L.s_buf[(t + 1) & 1], L.a_buf.v[(t + 1) & 1], L.smax[(t + 1) & 1],
+                                sr[kPut], d1.f, pairs, ptid);
     const int tn = t + 1 + kDepth;
     const BfItem dn = item_at(my, min(tn, n_my - 1), stride);
-    p_load_item<kProd, k3M>(sr[kPut], dn, tn < n_my, sink, apool, a_w_stride, pairs, ptid);
+    p_load_item<kProd, kW>(sr[kPut], dn, tn < n_my, sink, apool, a_w_stride, pairs, ptid);
 }
 
-// The producer role of the wave-specialised kernels (threads 64 kWaves ..):
-// product 0 straight to LDS, products u = 1..kDepth into register set
-// u % kDepth, then one iteration per barrier of the consumers.  The
-// consumers stage R(t) during iteration t (four-product and 16-bit forms)
-// or t + 1 (three-product form, epilogue folded into the next chain), so
-// iteration t writes R(t - kLag).
-template <int kProd, int kDepth, bool k3M, bool kMax>
+// The producer role of the wave-specialised kernels (threads 64 kCons ..,
+// after the kCons matrix-core waves): product 0 straight to LDS, products
+// u = 1..kDepth into register set u % kDepth, then one iteration per
+// barrier of the consumers.  The consumers stage R(t) during iteration t
+// (four-product and 16-bit forms) or t + 1 (three-product form, epilogue
+// folded into the next chain), so iteration t writes R(t - kLag).  kW selects the W layout the
+// producers stage (0: none).
+template <int kProd, int kDepth, int kW, bool kMax, int kCons = kWaves>
 __device__ __forceinline__ void ws_producer(c_item *my, int stride, int n_my, float2 *sink,
-                                            WsLds<k3M, kProd> &L, const void *apool, int a_w_stride,
+                                            WsLds<kW != 0, kProd> &L, const void *apool, int a_w_stride,
                                             int pairs)
 {
-    constexpr int kLag = k3M ? 2 : 1;
-    const int ptid = threadIdx.x - 64 * kWaves;
-    PRegs<kProd, k3M> sr[kDepth];
+    constexpr int kLag = kW != 0 ? 2 : 1;
+    const int ptid = threadIdx.x - 64 * kCons;
+    PRegs<kProd, kW> sr[kDepth];
     {
         const BfItem d0 = item_at(my, 0, stride);
-        p_load_item<kProd, k3M>(sr[0], d0, true, sink, apool, a_w_stride, pairs, ptid);
-        p_put_item<kProd, k3M, kMax>(L.s_buf[0], L.a_buf.v[0], L.smax[0], sr[0], d0.f, pairs, ptid);
+        p_load_item<kProd, kW>(sr[0], d0, true, sink, apool, a_w_stride, pairs, ptid);
+        p_put_item<kProd, kW, kMax>(L.s_buf[0], L.a_buf.v[0], L.smax[0], sr[0], d0.f, pairs, ptid);
     }
     // Each load group is preceded by as many sink stores as an iteration
     // issues R stores, and so is product 0, which has no R to write: the
@@ -1117,7 +1191,7 @@ __device__ __forceinline__ void ws_producer(c_item *my, int stride, int n_my, fl
     for (int u = 1; u <= kDepth; ++u) {
         prime_store_count<kPStoreRounds<kProd>>(sink, plane);
         const BfItem d = item_at(my, min(u, n_my - 1), stride);
-        p_load_item<kProd, k3M>(sr[u % kDepth], d, u < n_my, sink, apool, a_w_stride, pairs, ptid);
+        p_load_item<kProd, kW>(sr[u % kDepth], d, u < n_my, sink, apool, a_w_stride, pairs, ptid);
     }
     __syncthreads();
     // The first kLag iterations have no R to write and issue sink stores
@@ -1126,11 +1200,11 @@ __device__ __forceinline__ void ws_producer(c_item *my, int stride, int n_my, fl
     for (int t0 = 0; t0 < kLag; ++t0) {
         prime_store_count<kPStoreRounds<kProd>>(sink, plane);
         const BfItem d1 = item_at(my, min(t0 + 1, n_my - 1), stride);
-        p_put_item<kProd, k3M, kMax>(L.s_buf[(t0 + 1) & 1], L.a_buf.v[(t0 + 1) & 1], L.smax[(t0 + 1) & 1],
+        p_put_item<kProd, kW, kMax>(L.s_buf[(t0 + 1) & 1], L.a_buf.v[(t0 + 1) & 1], L.smax[(t0 + 1) & 1],
                                      sr[(t0 + 1) % kDepth], d1.f, pairs, ptid);
         const int tn = t0 + 1 + kDepth;
         const BfItem dn = item_at(my, min(tn, n_my - 1), stride);
-        p_load_item<kProd, k3M>(sr[(t0 + 1) % kDepth], dn, tn < n_my, sink, apool, a_w_stride, pairs,
+        p_load_item<kProd, kW>(sr[(t0 + 1) % kDepth], dn, tn < n_my, sink, apool, a_w_stride, pairs,
                                 ptid);
         __syncthreads();
     }
@@ -1146,16 +1220,16 @@ __device__ __forceinline__ void ws_producer(c_item *my, int stride, int n_my, fl
     constexpr int kP0 = (kLag + 1) % kDepth, kP1 = (kLag + 2) % kDepth, kP2 = (kLag + 3) % kDepth;
     int t = kLag;
     for (int g = 0; g < groups; ++g) {
-        ws_produce_step<kProd, kDepth, kP0, k3M, kMax, kLag>(sr, my, stride, t, n_my, sink, L, apool,
+        ws_produce_step<kProd, kDepth, kP0, kW, kMax, kLag>(sr, my, stride, t, n_my, sink, L, apool,
                                                              a_w_stride, pairs, ptid);
         __syncthreads();
         if constexpr (kDepth >= 2) {
-            ws_produce_step<kProd, kDepth, kP1, k3M, kMax, kLag>(sr, my, stride, t + 1, n_my, sink, L,
+            ws_produce_step<kProd, kDepth, kP1, kW, kMax, kLag>(sr, my, stride, t + 1, n_my, sink, L,
                                                                  apool, a_w_stride, pairs, ptid);
             __syncthreads();
         }
         if constexpr (kDepth >= 3) {
-            ws_produce_step<kProd, kDepth, kP2, k3M, kMax, kLag>(sr, my, stride, t + 2, n_my, sink, L,
+            ws_produce_step<kProd, kDepth, kP2, kW, kMax, kLag>(sr, my, stride, t + 2, n_my, sink, L,
                                                                  apool, a_w_stride, pairs, ptid);
             __syncthreads();
         }
@@ -1163,14 +1237,14 @@ __device__ __forceinline__ void ws_producer(c_item *my, int stride, int n_my, fl
     }
     if constexpr (kDepth >= 2) {
         if (rest >= 1) {
-            ws_produce_step<kProd, kDepth, kP0, k3M, kMax, kLag>(sr, my, stride, t, n_my, sink, L, apool,
+            ws_produce_step<kProd, kDepth, kP0, kW, kMax, kLag>(sr, my, stride, t, n_my, sink, L, apool,
                                                                  a_w_stride, pairs, ptid);
             __syncthreads();
         }
     }
     if constexpr (kDepth >= 3) {
         if (rest >= 2) {
-            ws_produce_step<kProd, kDepth, kP1, k3M, kMax, kLag>(sr, my, stride, t + 1, n_my, sink, L,
+            ws_produce_step<kProd, kDepth, kP1, kW, kMax, kLag>(sr, my, stride, t + 1, n_my, sink, L,
                                                                  apool, a_w_stride, pairs, ptid);
             __syncthreads();
         }
@@ -1290,6 +1364,186 @@ __global__ __launch_bounds__(64 * (kWaves + kProd)) void apply_fp32_ws(
     } else {
         ws_producer<kProd, kDepth, k3M, false>(my, stride, n_my, sink, L, apool, a_w_stride, pairs);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Three-product FP32 form on 16 x 16 tiles (v_mfma_f32_16x16x4_f32, the same
+// matrix-core rate as the 32 x 32 x 2 form), with eight matrix-core waves,
+// two per SIMD: a single wave per SIMD loses about a quarter of the matrix
+// core to its own LDS reads and epilogue, which a second wave on the SIMD
+// overlaps.  Matrix-core wave cw owns antennas 16 rb .. 16 rb + 15
+// (rb = cw / 2) and columns 32 cb .. 32 cb + 31 (cb = cw % 2) as two 16 x 16
+// tiles that share their A operands.  For v_mfma_f32_16x16x4_f32 lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16] (K = 4 flows per step)
+// and receives column l % 16, rows 4 (l / 16) + v of the tile in register v.
+constexpr int kCons16 = 8;
+
+__device__ __forceinline__ void mfma3_16(float ar, float ai, float as, f2v b, floatx4 &t1, floatx4 &t2,
+                                         floatx4 &t3)
+{
+    t1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, b.x, t1, 0, 0, 0);
+    t2 = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, b.y, t2, 0, 0, 0);
+    t3 = __builtin_amdgcn_mfma_f32_16x16x4f32(as, b.x + b.y, t3, 0, 0, 0);
+}
+
+// Row (t, v) of the epilogue of wave cw's two tiles, e = 4 t + v (0..7):
+// Re R = T1 - T2, Im R = (T3 - T1) - T2 into the staged R tile (64 x 60
+// row-major) at antenna 16 rb + 4 (lane / 16) + v, column 32 cb + 16 t +
+// lane % 16; columns 60..63 are not written.
+__device__ __forceinline__ void stage_row_3m16(const floatx4 (&acc)[2][3], int e, int cw, int lane,
+                                               f2v *__restrict__ tile)
+{
+    const int t = e >> 2;
+    const int v = e & 3;
+    const int j = 32 * (cw & 1) + 16 * t + (lane & 15);
+    const int i = 16 * (cw >> 1) + 4 * (lane >> 4) + v;
+    const floatx4 &t1 = acc[t][0], &t2 = acc[t][1], &t3 = acc[t][2];
+    if (j < kB)
+        tile[i * kB + j] = f2v{t1[v] - t2[v], (t3[v] - t1[v]) - t2[v]};
+}
+
+// One product's chain for wave cw: `steps` blocks of 4 flows (kFull: all
+// kSteps16Max), operands read from the staged S (row pitch kLdsCols) and
+// the staged W (16 x 16 layout, `plan_steps` steps per block), each step's
+// reads issued three steps ahead of its matrix-core work.  acc[t][m] is the
+// m-th product (Wr Sr, Wi Si, (Wr + Wi)(Sr + Si)) of tile t.  With kEpi, the
+// previous product's accumulators `prev` are staged to `prev_tile` one row
+// per step during the chain, so that this wave's epilogue falls between its
+// own matrix-core steps (where the other wave of the SIMD fills the matrix
+// core) instead of after the chain, where both waves of a SIMD would reach
+// it together.
+template <bool kFull, bool kEpi>
+__device__ __forceinline__ void chain_3m16(const f2v *__restrict__ s_lds, const float *__restrict__ w_lds,
+                                           int plan_steps, int steps, int cw, int lane, floatx4 (&acc)[2][3],
+                                           const floatx4 (&prev)[2][3], f2v *__restrict__ prev_tile)
+{
+    constexpr int kAhead = 3;
+    const int rb = cw >> 1;
+    const int cb = cw & 1;
+    const f2v *col = s_lds + (lane >> 4) * kLdsCols + 32 * cb + (lane & 15);
+    const float *wa = w_lds + rb * plan_steps * 128 + lane;
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+            acc[t][m] = floatx4{};
+    float ar[kSteps16Max], ai[kSteps16Max];
+    f2v b0[kSteps16Max], b1[kSteps16Max];
+#pragma unroll
+    for (int q = 0; q < kAhead; ++q) {
+        if (kFull || q < steps) {
+            ar[q] = wa[q * 128];
+            ai[q] = wa[q * 128 + 64];
+            b0[q] = col[4 * q * kLdsCols];
+            b1[q] = col[4 * q * kLdsCols + 16];
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < kSteps16Max; ++q) {
+        const int qn = q + kAhead;
+        if (qn < kSteps16Max && (kFull || qn < steps)) {
+            ar[qn] = wa[qn * 128];
+            ai[qn] = wa[qn * 128 + 64];
+            b0[qn] = col[4 * qn * kLdsCols];
+            b1[qn] = col[4 * qn * kLdsCols + 16];
+        }
+        if (kFull || q < steps) {
+            const float as = ar[q] + ai[q];
+            mfma3_16(ar[q], ai[q], as, b0[q], acc[0][0], acc[0][1], acc[0][2]);
+            mfma3_16(ar[q], ai[q], as, b1[q], acc[1][0], acc[1][1], acc[1][2]);
+        }
+        if constexpr (kEpi) {
+            if (q < 8)
+                stage_row_3m16(prev, q, cw, lane, prev_tile);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+template <bool kEpi>
+__device__ __forceinline__ void chain_3m16_any(const f2v *__restrict__ s_lds, const float *__restrict__ w_lds,
+                                               int plan_steps, int f, int cw, int lane, floatx4 (&acc)[2][3],
+                                               const floatx4 (&prev)[2][3], f2v *__restrict__ prev_tile)
+{
+    const int steps = (f + 3) >> 2;
+    if (steps == kSteps16Max)
+        chain_3m16<true, kEpi>(s_lds, w_lds, plan_steps, steps, cw, lane, acc, prev, prev_tile);
+    else
+        chain_3m16<false, kEpi>(s_lds, w_lds, plan_steps, steps, cw, lane, acc, prev, prev_tile);
+}
+
+// The matrix-core role of apply_fp32_3m16_ws.  Product k's chain runs with
+// product k - 1's epilogue folded in (two accumulator sets, A for even k, B
+// for odd k); the last product's epilogue gets an iteration of its own, so
+// the R of product k is staged during iteration k + 1 and written out by the
+// producers in iteration k + 2.  f of product k + 1 is read at the end of
+// product k, where the barrier waits for it anyway.
+template <int kProd>
+__device__ __forceinline__ void ws_3m16_consumer(c_item *my, int stride, int n_my, WsLds<true, kProd> &L,
+                                                 int pairs, int cw, int lane)
+{
+    const int plan_steps = fp32_3m16_steps(pairs);
+    floatx4 accA[2][3], accB[2][3];
+    int f = item_at(my, 0, stride).f;
+    __syncthreads();
+    chain_3m16_any<false>(L.s_buf[0], L.a_buf.v[0], plan_steps, f, cw, lane, accA, accA, nullptr);
+    __builtin_amdgcn_sched_barrier(0);
+    f = item_at(my, min(1, n_my - 1), stride).f;
+    __syncthreads();
+    int k = 1;
+    while (true) {
+        if (k >= n_my) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                stage_row_3m16(accA, e, cw, lane, L.r_buf[(k - 1) & 1]);
+            __syncthreads();
+            break;
+        }
+        chain_3m16_any<true>(L.s_buf[k & 1], L.a_buf.v[k & 1], plan_steps, f, cw, lane, accB, accA,
+                             L.r_buf[(k - 1) & 1]);
+        __builtin_amdgcn_sched_barrier(0);
+        f = item_at(my, min(k + 1, n_my - 1), stride).f;
+        __syncthreads();
+        ++k;
+        if (k >= n_my) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                stage_row_3m16(accB, e, cw, lane, L.r_buf[(k - 1) & 1]);
+            __syncthreads();
+            break;
+        }
+        chain_3m16_any<true>(L.s_buf[k & 1], L.a_buf.v[k & 1], plan_steps, f, cw, lane, accA, accB,
+                             L.r_buf[(k - 1) & 1]);
+        __builtin_amdgcn_sched_barrier(0);
+        f = item_at(my, min(k + 1, n_my - 1), stride).f;
+        __syncthreads();
+        ++k;
+    }
+}
+
+// kSched 3, three-product form on 16 x 16 tiles: 8 matrix-core waves and
+// kProd producer waves.  S must be 16-byte aligned and the plan's f_max at
+// least 1 (the host routes other batches elsewhere).
+template <int kProd, int kDepth>
+__global__ __launch_bounds__(64 * (kCons16 + kProd)) void apply_fp32_3m16_ws(
+    BfHeader *__restrict__ blk, const BfItem *__restrict__ items, int n_items,
+    const void *__restrict__ apool, int a_w_stride, int pairs)
+{
+    __shared__ WsLds<true, kProd> L;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    float2 *sink = sink_of(blk);
+    int start, stride;
+    const int n_my = ws_share(n_items, &start, &stride);
+    if (n_my <= 0)
+        return;
+
+    c_item *my = (c_item *)items + start;
+    if (wave < kCons16)
+        ws_3m16_consumer<kProd>(my, stride, n_my, L, pairs, wave, lane);
+    else
+        ws_producer<kProd, kDepth, 2, false, kCons16>(my, stride, n_my, sink, L, apool, a_w_stride, pairs);
 }
 
 // ---------------------------------------------------------------------------
@@ -2081,6 +2335,15 @@ static hipError_t launch_ws(const LaunchCfg &cfg, BfHeader *blk, int n_items, co
 {
     const BfItem *items = items_of(blk);
     const dim3 grid(cfg.grid);
+    if (k3M && cfg.tile16) {
+        if (cfg.depth >= 2)
+            hipLaunchKernelGGL((apply_fp32_3m16_ws<8, 2>), grid, dim3(64 * (kCons16 + 8)), 0, st, blk,
+                               items, n_items, apool, a_stride, pairs);
+        else
+            hipLaunchKernelGGL((apply_fp32_3m16_ws<8, 1>), grid, dim3(64 * (kCons16 + 8)), 0, st, blk,
+                               items, n_items, apool, a_stride, pairs);
+        return hipGetLastError();
+    }
     if (cfg.producers == 4)
         hipLaunchKernelGGL((apply_fp32_ws<k3M, 4, 1>), grid, dim3(64 * 8), 0, st, blk, items,
                            n_items, apool, a_stride, pairs);

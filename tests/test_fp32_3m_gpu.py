@@ -18,7 +18,9 @@ P = bf.BF_FP32_3M
 VARIANTS = {"one-per-wg": (0, 0, 0), "ws-sorted": (3, 0, 1), "ws-asgiven": (3, 0, 0),
             "mapped-from-stream": (2, 2, 1), "ws-8-producers": (3, 0, 1, 1),
             "ws-8-producers-depth-2": (3, 0, 1, 2), "ws-8-producers-depth-3": (3, 0, 1, 3),
-            "ws-12-producers-asgiven": (3, 0, 0, 4), "ws-12-producers-depth-2": (3, 0, 1, 5)}
+            "ws-12-producers-asgiven": (3, 0, 0, 4), "ws-12-producers-depth-2": (3, 0, 1, 5),
+            "ws16": (3, 0, 0, 6), "ws16-sorted-depth-2": (3, 0, 1, 7)}
+WS16 = ["ws16", "ws16-sorted-depth-2"]
 
 
 @pytest.mark.parametrize("vname", sorted(VARIANTS))
@@ -35,7 +37,7 @@ def test_ragged_all_f(vname, seed):
     assert np.max(err[nz]) <= FP32_TOL, f"max rel err {np.max(err[nz]):.3g}"
 
 
-@pytest.mark.parametrize("vname", ["one-per-wg", "ws-sorted"])
+@pytest.mark.parametrize("vname", ["one-per-wg", "ws-sorted"] + WS16)
 def test_exact_integers_bitwise(vname):
     rng = np.random.default_rng(803)
     b = wl.exact_integer_batch(rng, 200, 5)
@@ -44,12 +46,15 @@ def test_exact_integers_bitwise(vname):
     assert np.array_equal(R.astype(np.complex128), orc.apply(b))
 
 
-@pytest.mark.parametrize("f_max", [1, 2, 7, 36])
-def test_small_pools(f_max):
+@pytest.mark.parametrize("vname", [None] + WS16)
+@pytest.mark.parametrize("f_max", [1, 2, 3, 5, 7, 36])
+def test_small_pools(f_max, vname):
+    """Pools narrower than 36 flows: both W layouts of an entry, and their
+    offsets, follow from f_max."""
     rng = np.random.default_rng(810 + f_max)
     b = wl.random_batch(rng, 60, 3, f_max=f_max)
-    announce(f"3m pool f_max={f_max}")
-    R = run_batch(b, prec=P)
+    announce(f"3m pool f_max={f_max} variant={vname}")
+    R = run_batch(b, prec=P, variant=VARIANTS[vname] if vname else None)
     err, _ = rel_errors(b, R)
     nz = b.f > 0
     assert np.max(err[nz], initial=0) <= FP32_TOL
@@ -69,28 +74,30 @@ def test_dft_and_identity_within_bar():
     assert np.max(err) <= FP32_TOL
 
 
-def test_full_width_workload_all_items():
+@pytest.mark.parametrize("vname", [None] + WS16)
+def test_full_width_workload_all_items(vname):
     b = wl.full_width_batch()
-    announce(f"3m full-width n={b.n}")
-    R = run_batch(b, prec=P)
+    announce(f"3m full-width n={b.n} variant={vname}")
+    R = run_batch(b, prec=P, variant=VARIANTS[vname] if vname else None)
     assert not np.any(np.isnan(R.view(np.float32)))
     err = all_errors(b, R)
     print(f"[fp32_3m] rel err p50 {np.median(err):.3g} max {err.max():.3g}", flush=True)
     assert np.max(err) <= FP32_TOL
 
 
-def test_uneven_workload_all_items():
+@pytest.mark.parametrize("vname", [None] + WS16)
+def test_uneven_workload_all_items(vname):
     b = wl.uneven_batch()
-    announce(f"3m uneven n={b.n}")
-    R = run_batch(b, prec=P)
-    err, _ = rel_errors(b, R)
+    announce(f"3m uneven n={b.n} variant={vname}")
+    R = run_batch(b, prec=P, variant=VARIANTS[vname] if vname else None)
+    err = all_errors(b, R)
     assert np.max(err) <= FP32_TOL
 
 
 @pytest.mark.parametrize("vname", ["ws-sorted", "ws-8-producers", "ws-8-producers-depth-2",
                                    "ws-8-producers-depth-3", "ws-12-producers-asgiven",
-                                   "ws-12-producers-depth-2"])
-@pytest.mark.parametrize("per_wg", [5, 6, 7])
+                                   "ws-12-producers-depth-2"] + WS16)
+@pytest.mark.parametrize("per_wg", [1, 2, 5, 6, 7])
 def test_ws_long_shares(vname, per_wg):
     """5-8 products per persistent workgroup: the producers' prefetch ring
     wraps and every remainder of its unrolled loop occurs."""
@@ -121,3 +128,21 @@ def test_variants_agree_bitwise():
     for vname in ["ws-8-producers", "ws-8-producers-depth-2", "ws-asgiven"]:
         R = run_batch(b, prec=P, variant=VARIANTS[vname])
         assert np.array_equal(R.view(np.uint32), ref.view(np.uint32)), vname
+
+
+def test_16x16_variants_agree_bitwise():
+    """The two prefetch depths of the 16 x 16 kernel issue the same
+    matrix-core steps on the same operands, so they agree bit for bit; the
+    32 x 32 kernels sum the flows in another grouping and agree within the
+    bar only."""
+    require_gpu()
+    n = bf.bf_device_cu_count() * 3 + 5
+    rng = np.random.default_rng(833)
+    b = wl.random_batch(rng, n, 9, f_values=np.arange(0, 37))
+    announce(f"3m 16x16 variants bitwise n={n}")
+    ref = run_batch(b, prec=P, variant=VARIANTS["ws16"])
+    R = run_batch(b, prec=P, variant=(3, 0, 0, 7))
+    assert np.array_equal(R.view(np.uint32), ref.view(np.uint32))
+    err, _ = rel_errors(b, ref)
+    nz = b.f > 0
+    assert np.max(err[nz]) <= FP32_TOL and np.all(ref[~nz] == 0)
