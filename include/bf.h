@@ -154,7 +154,7 @@ bf_status bf_apply(bf_plan plan, int32_t batch, const int32_t *w_ids, const int3
  * keeps the last call's contents: calls on different streams whose device
  * work overlaps race on it (calls on one stream are ordered).  The
  * current device must be the plan's (else BF_ERR_INVALID).  The tuning
- * table's product order (order = 1) is not applied; every product's
+ * table's product orders (order 1 and 2) are not applied; every product's
  * result is the same as in any order. */
 #define BF_NOALLOC_MAX_ITEMS 16384
 bf_status bf_apply_noalloc(bf_plan plan, int32_t batch, const int32_t *w_ids, const int32_t *f,
@@ -208,7 +208,10 @@ typedef struct {
                               run schedule 2, and bf_autotune does not try 3 on
                               them) */
     int32_t wg_per_cu;     /* persistent grid = wg_per_cu * CU count (ignored for 0) */
-    int32_t order;         /* 0: as given; 1: longest f first, then by W id */
+    int32_t order;         /* 0: as given; 1: longest f first, then by W id;
+                              2: grouped by W id modulo 8 (each of the 8 XCDs
+                              then works on an eighth of the pool), caller order
+                              within a group */
     int32_t store;         /* schedules 0 and 2: 0 = lanes write their accumulators
                               directly, 1 = each wave stages its 16 rows of R in LDS
                               and writes them as contiguous 16-byte stores;

@@ -68,13 +68,14 @@ static void release_slot(StagingSlot &s)
     s = StagingSlot{};
 }
 
-// Defaults measured on MI355X at steady state: full-width batches (mean f
-// 36) run the wave-specialised schedule, except the split 16-bit forms,
-// which stream; the three-product form's batches of mixed f are
-// wave-specialised too, on 16 x 16 tiles (8 matrix-core waves, 8 producers,
-// prefetch depth 2: 1.5-2% faster than 32 x 32 tiles at full width, 4% on
-// batches of mixed f); other batches of mixed or small f run one product
-// per workgroup; all in the order given.
+// Defaults measured on MI355X at steady state.  Full-width batches (mean f
+// 36) run the wave-specialised schedule (the three-product form on 16 x 16
+// tiles), except the split 16-bit forms, which stream.  Batches of mixed or
+// smaller f run one product per workgroup, grouped by W id modulo 8 so that
+// each XCD's L2 holds an eighth of the pool, with staged R stores: on the
+// uneven batch (8192 products, f ~ U{1..36}, 256 W) this took the forms
+// from 66.7 / 90.2 / 74.9 / 82.7 us (three-product, four-product, FP16x2,
+// FP16; caller order, direct stores) to 65.4 / 75.6 / 61.3 / 54.1 us.
 static bf_status default_variants(bf_plan p)
 {
     for (int pr = 0; pr < kPrecCount; ++pr)
@@ -82,16 +83,16 @@ static bf_status default_variants(bf_plan p)
             bf_variant v{};
             const bool full = b == kBucketCount - 1;
             const bool fp32 = pr == BF_FP32 || pr == BF_FP32_3M;
-            if (pr == BF_FP32_3M && b > 0)
+            if (!full)
+                v = bf_variant{0, 0, 2, 1};   // one per workgroup, grouped by W id mod 8, staged
+            else if (pr == BF_FP32_3M)
                 v = bf_variant{3, 0, 0, 7};   // wave-specialised, 16 x 16 tiles, depth 2, as given
-            else if (full && fp32)
+            else if (fp32)
                 v = bf_variant{3, 0, 0, 5};   // wave-specialised, 12 producers, depth 2, as given
-            else if (full && (pr == BF_FP16 || pr == BF_BF16))
+            else if (pr == BF_FP16 || pr == BF_BF16)
                 v = bf_variant{3, 0, 0, 4};   // plain 16-bit: wave-specialised, 12 producers
-            else if (full)
-                v = bf_variant{2, 2, 0, 0};   // split 16-bit: streaming, 2 workgroups per CU
             else
-                v = bf_variant{0, 0, 0, 0};   // mixed or small f: one per workgroup
+                v = bf_variant{2, 2, 0, 0};   // split 16-bit: streaming, 2 workgroups per CU
             p->table[pr][b] = v;
         }
     return BF_OK;
@@ -404,8 +405,25 @@ int batch_bucket(int64_t sum_f, int n)
 // Orders items longest f first and, for equal f, by W id (so that a
 // persistent workgroup keeps its W operands across consecutive items).
 // Two stable counting sorts: by W id, then by f descending.
-void order_items(const BfItem *in, BfItem *out, int n, int n_w, std::vector<int> &scratch)
+// Product orders of the variants (items carry pool W ids at this point):
+//   1: longest f first, then by W id (counting sorts; stable);
+//   2: grouped by W id modulo 8, caller order within each group.  The
+//      kernels give each of the 8 XCDs one contiguous eighth of the item
+//      list, so this lets each XCD's L2 hold the operands of an eighth of
+//      the pool only.
+void order_items(const BfItem *in, BfItem *out, int n, int n_w, std::vector<int> &scratch, int mode)
 {
+    if (mode == 2) {
+        constexpr int kGroups = 8;
+        int cnt[kGroups + 1] = {0};
+        for (int t = 0; t < n; ++t)
+            cnt[in[t].w_id % kGroups + 1]++;
+        for (int g = 0; g < kGroups; ++g)
+            cnt[g + 1] += cnt[g];
+        for (int t = 0; t < n; ++t)
+            out[cnt[in[t].w_id % kGroups]++] = in[t];
+        return;
+    }
     std::vector<BfItem> tmp(in, in + n);
     scratch.assign((size_t)std::max(n_w, BF_FMAX + 1) + 1, 0);
     for (int t = 0; t < n; ++t)
@@ -559,9 +577,9 @@ static bf_status upload_and_launch(bf_plan p, bf_prec prec, int n, const FillSta
                                                kSinkBytes);
     const bool uniform_f = fs.min_f == fs.max_f;
     bf_variant chosen = force ? *force : p->table[prec][batch_bucket(fs.sum_f, n)];
-    if (chosen.order == 1 && n > 1 && may_order) {
+    if (chosen.order >= 1 && n > 1 && may_order) {
         p->sort_tmp.resize((size_t)n);
-        order_items(items, p->sort_tmp.data(), n, p->n_w, p->sort_scratch);
+        order_items(items, p->sort_tmp.data(), n, p->n_w, p->sort_scratch, chosen.order);
         std::memcpy(items, p->sort_tmp.data(), (size_t)n * sizeof(BfItem));
     }
     bfk::LaunchCfg cfg = choose_launch(p, prec, n, fs.max_f, fs.vec16, uniform_f, &chosen);
@@ -869,8 +887,8 @@ extern "C" bf_status bf_graph_create(bf_graph *out, bf_plan p, int32_t batch, co
     }
     std::vector<int> scratch;
     const bf_variant v = p->table[prec][batch_bucket(sum_f, batch)];
-    if (v.order == 1)
-        order_items(raw.data(), items.data(), batch, p->n_w, scratch);
+    if (v.order >= 1)
+        order_items(raw.data(), items.data(), batch, p->n_w, scratch, v.order);
     else
         items = raw;
     bfk::LaunchCfg cfg = choose_launch(p, prec, batch, max_f, vec16, min_f == max_f, &v);
@@ -953,7 +971,7 @@ extern "C" bf_status bf_graph_destroy(bf_graph g)
 static bool valid_variant(const bf_variant &v)
 {
     return v.schedule >= 0 && v.schedule <= 3 && v.wg_per_cu >= 0 && v.wg_per_cu <= 64 &&
-           (v.order == 0 || v.order == 1) && v.store >= 0 && v.store <= (v.schedule == 3 ? 7 : 1);
+           v.order >= 0 && v.order <= 2 && v.store >= 0 && v.store <= (v.schedule == 3 ? 7 : 1);
 }
 
 extern "C" bf_status bf_set_variant(bf_plan p, bf_prec prec, int32_t bucket, const bf_variant *v)
@@ -1005,10 +1023,9 @@ extern "C" bf_status bf_autotune(bf_plan p, int32_t batch, const int32_t *w_ids,
     const bool lp = prec != BF_FP32 && prec != BF_FP32_3M;
 
     std::vector<bf_variant> cands;
-    for (int st = 0; st < 2; ++st) {
-        cands.push_back(bf_variant{0, 0, 0, st});
-        cands.push_back(bf_variant{0, 0, 1, st});
-    }
+    for (int st = 0; st < 2; ++st)
+        for (int o = 0; o < 3; ++o)
+            cands.push_back(bf_variant{0, 0, o, st});
     const int per_cu[] = {1, 2, 3, 4, 6};
     for (int w : per_cu)
         cands.push_back(bf_variant{1, w, 1, 0});
@@ -1019,7 +1036,7 @@ extern "C" bf_status bf_autotune(bf_plan p, int32_t batch, const int32_t *w_ids,
     // (the 16-bit wave-specialised kernel takes batches of one f only; store
     // fields 6 and 7 exist for the three-product form only)
     if (!lp || min_f == max_f)
-        for (int o = 0; o < 2; ++o)
+        for (int o = 0; o < 3; ++o)
             for (int st = 0; st < (prec == BF_FP32_3M ? 8 : 6); ++st)
                 cands.push_back(bf_variant{3, 0, o, st});
 

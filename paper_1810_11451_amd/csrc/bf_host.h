@@ -89,7 +89,7 @@ struct FillStats {
 int batch_bucket(int64_t sum_f, int n);
 using FillFn = std::function<FillStats(BfItem *)>;
 
-void order_items(const BfItem *in, BfItem *out, int n, int n_w, std::vector<int> &scratch);
+void order_items(const BfItem *in, BfItem *out, int n, int n_w, std::vector<int> &scratch, int mode);
 bfk::LaunchCfg choose_launch(bf_plan p, bf_prec prec, int n, int max_f, bool vec16,
                              bool uniform_f, const bf_variant *force);
 bf_status reserve_staging(bf_plan p, int n);

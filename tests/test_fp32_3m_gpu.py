@@ -19,7 +19,8 @@ VARIANTS = {"one-per-wg": (0, 0, 0), "ws-sorted": (3, 0, 1), "ws-asgiven": (3, 0
             "mapped-from-stream": (2, 2, 1), "ws-8-producers": (3, 0, 1, 1),
             "ws-8-producers-depth-2": (3, 0, 1, 2), "ws-8-producers-depth-3": (3, 0, 1, 3),
             "ws-12-producers-asgiven": (3, 0, 0, 4), "ws-12-producers-depth-2": (3, 0, 1, 5),
-            "ws16": (3, 0, 0, 6), "ws16-sorted-depth-2": (3, 0, 1, 7)}
+            "ws16": (3, 0, 0, 6), "ws16-sorted-depth-2": (3, 0, 1, 7),
+            "ws16-xcd-grouped-depth-2": (3, 0, 2, 7), "one-per-wg-xcd-grouped": (0, 0, 2)}
 WS16 = ["ws16", "ws16-sorted-depth-2"]
 
 

@@ -36,6 +36,9 @@ VARIANTS = {
     "ws-8-producers-depth-3": (3, 0, 1, 3),
     "ws-12-producers-asgiven": (3, 0, 0, 4),
     "ws-12-producers-depth-2": (3, 0, 1, 5),
+    "ws-xcd-grouped": (3, 0, 2, 1),
+    "stream-xcd-grouped": (2, 2, 2),
+    "one-per-wg-xcd-grouped": (0, 0, 2),
 }
 WS_VARIANTS = ["ws-sorted", "ws-8-producers", "ws-8-producers-depth-2", "ws-8-producers-depth-3",
                "ws-12-producers-asgiven", "ws-12-producers-depth-2"]
