@@ -206,7 +206,7 @@ typedef struct {
                               form, 2 otherwise); for the 16-bit forms also one f
                               for every product of the batch (batches of mixed f
                               run schedule 2, and bf_autotune does not try 3 on
-                              them) */
+                              them); there the matrix-core waves also stage W */
     int32_t wg_per_cu;     /* persistent grid = wg_per_cu * CU count (ignored for 0) */
     int32_t order;         /* 0: as given; 1: longest f first, then by W id;
                               2: grouped by W id modulo 8 (each of the 8 XCDs

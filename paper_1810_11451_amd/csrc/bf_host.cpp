@@ -70,7 +70,8 @@ static void release_slot(StagingSlot &s)
 
 // Defaults measured on MI355X at steady state.  Full-width batches (mean f
 // 36) run the wave-specialised schedule (the three-product form on 16 x 16
-// tiles), except the split 16-bit forms, which stream.  Batches of mixed or
+// tiles; the split 16-bit forms with 12 producers, 168 against 178 us for
+// the streaming schedule on the gain workload).  Batches of mixed or
 // smaller f run one product per workgroup, grouped by W id modulo 8 so that
 // each XCD's L2 holds an eighth of the pool, with staged R stores: on the
 // uneven batch (8192 products, f ~ U{1..36}, 256 W) this took the forms
@@ -92,7 +93,7 @@ static bf_status default_variants(bf_plan p)
             else if (pr == BF_FP16 || pr == BF_BF16)
                 v = bf_variant{3, 0, 0, 4};   // plain 16-bit: wave-specialised, 12 producers
             else
-                v = bf_variant{2, 2, 0, 0};   // split 16-bit: streaming, 2 workgroups per CU
+                v = bf_variant{3, 0, 0, 5};   // split 16-bit: wave-specialised, 12 producers, depth 2
             p->table[pr][b] = v;
         }
     return BF_OK;
@@ -219,12 +220,23 @@ extern "C" bf_status bf_plan_create(bf_plan *out, const void *w_pool, int32_t n_
         return fail_dev("hipStreamSynchronize(plan)", e);
     // Every staging slot gets its pinned and device blocks now: allocating
     // them on first use cost each of a fresh plan's first eight launches
-    // about 0.2 ms of host time.
+    // about 0.2 ms.
     const bf_status rs = reserve_staging(p, kReserveItems);
     if (rs != BF_OK) {
         bf_plan_destroy(p);
         return rs;
     }
+    // One upload per slot now: a slot's first upload took about 0.1 ms more
+    // than later ones, which the first launches of a fresh plan paid.
+    for (StagingSlot &slot : p->ring) {
+        std::memset(slot.host, 0, slot.cap);
+        e = hipMemcpyAsync(slot.dev, slot.host, slot.cap, hipMemcpyHostToDevice, p->copy_stream);
+        if (e != hipSuccess)
+            return fail_dev("hipMemcpyAsync(staging)", e);
+    }
+    e = hipStreamSynchronize(p->copy_stream);
+    if (e != hipSuccess)
+        return fail_dev("hipStreamSynchronize(staging)", e);
     *out = p;
     return BF_OK;
 }

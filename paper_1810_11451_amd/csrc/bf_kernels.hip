@@ -1880,11 +1880,12 @@ struct WsLdsLp {
     int es[2];
 };
 
-// One product's S and compact W in producer registers.
-template <int kProd, bool kSplit>
+// One product's S and (unless the consumers stage W, kWC) its compact W in
+// producer registers.
+template <int kProd, bool kSplit, bool kWC = false>
 struct PRegsLp {
     static constexpr int kWChunks = (kSplit ? 2 : 1) * kLpWcP / 4;
-    static constexpr int kNW = (kWChunks + 64 * kProd - 1) / (64 * kProd);
+    static constexpr int kNW = kWC ? 1 : (kWChunks + 64 * kProd - 1) / (64 * kProd);
     PRegs<kProd, false> s;
     f4v w[kNW];
 };
@@ -1915,11 +1916,12 @@ __device__ __forceinline__ void p_publish_max(uint32_t *__restrict__ smax, const
 
 // Converts a staged S (scale 2^-es, es from the published maxima) into the
 // 16-bit operand layout, flows f .. 8 ceil(f / 8) - 1 cleared, and copies
-// the staged W.  One lane leaves es for the consumers.
-template <bool kBf16, bool kSplit, int kProd>
+// the staged W (kWC: the consumers stage W).  One lane leaves es for the
+// consumers.
+template <bool kBf16, bool kSplit, int kProd, bool kWC>
 __device__ __forceinline__ void p_put_lp(uint32_t *__restrict__ bhi, uint32_t *__restrict__ blo,
                                          uint32_t *__restrict__ wl, const uint32_t *__restrict__ smax,
-                                         int *__restrict__ es_out, const PRegsLp<kProd, kSplit> &r, int f,
+                                         int *__restrict__ es_out, const PRegsLp<kProd, kSplit, kWC> &r, int f,
                                          int ptid)
 {
     uint32_t m = 0;
@@ -1959,83 +1961,116 @@ __device__ __forceinline__ void p_put_lp(uint32_t *__restrict__ bhi, uint32_t *_
         if constexpr (kSplit)
             blo[d] = 0u;
     }
+    if constexpr (!kWC) {
 #pragma unroll
-    for (int u = 0; u < PRegsLp<kProd, kSplit>::kNW; ++u) {
-        const int c = ptid + u * 64 * kProd;
-        if (c < PRegsLp<kProd, kSplit>::kWChunks)
-            reinterpret_cast<f4v *>(wl)[c] = r.w[u];
+        for (int u = 0; u < PRegsLp<kProd, kSplit, kWC>::kNW; ++u) {
+            const int c = ptid + u * 64 * kProd;
+            if (c < PRegsLp<kProd, kSplit, kWC>::kWChunks)
+                reinterpret_cast<f4v *>(wl)[c] = r.w[u];
+        }
     }
 }
 
 // Loads of product u (S and compact W) into a register set; past the end
 // the S loads read the sink (f = 0) and W is the last product's.
-template <int kProd, bool kSplit>
-__device__ __forceinline__ void p_load_lp(PRegsLp<kProd, kSplit> &r, c_item *my, int stride, int u, int n_my,
-                                          float2 *sink, const PlanDev &pd, int ptid)
+template <int kProd, bool kSplit, bool kWC>
+__device__ __forceinline__ void p_load_lp(PRegsLp<kProd, kSplit, kWC> &r, c_item *my, int stride, int u,
+                                          int n_my, float2 *sink, const PlanDev &pd, int ptid)
 {
     const BfItem d = item_at(my, min(u, n_my - 1), stride);
     const bool real = u < n_my;
     p_load_s<kProd, false>(r.s, real && d.f > 0 ? d.S : sink, real ? d.f : 0, ptid);
-    g_cf4v *src = (g_cf4v *)(pd.lp_wc + (size_t)d.w_id * pd.lp_wc_stride);
-    constexpr int kLast = PRegsLp<kProd, kSplit>::kWChunks - 1;
+    if constexpr (!kWC) {
+        g_cf4v *src = (g_cf4v *)(pd.lp_wc + (size_t)d.w_id * pd.lp_wc_stride);
+        constexpr int kLast = PRegsLp<kProd, kSplit, kWC>::kWChunks - 1;
 #pragma unroll
-    for (int q = 0; q < PRegsLp<kProd, kSplit>::kNW; ++q)
-        r.w[q] = src[min(ptid + q * 64 * kProd, kLast)];
+        for (int q = 0; q < PRegsLp<kProd, kSplit, kWC>::kNW; ++q)
+            r.w[q] = src[min(ptid + q * 64 * kProd, kLast)];
+    }
+}
+
+// The compact W of pool entry w staged by the kWaves consumer waves
+// (thread ctid < 64 kWaves): loads into registers, then a copy into LDS.
+template <bool kSplit>
+struct CRegsW {
+    static constexpr int kChunks = (kSplit ? 2 : 1) * kLpWcP / 4;
+    static constexpr int kN = (kChunks + 64 * kWaves - 1) / (64 * kWaves);
+    f4v w[kN];
+};
+
+template <bool kSplit>
+__device__ __forceinline__ void c_load_w(CRegsW<kSplit> &r, const PlanDev &pd, int w, int ctid)
+{
+    g_cf4v *src = (g_cf4v *)(pd.lp_wc + (size_t)w * pd.lp_wc_stride);
+#pragma unroll
+    for (int q = 0; q < CRegsW<kSplit>::kN; ++q)
+        r.w[q] = src[min(ctid + q * 64 * kWaves, CRegsW<kSplit>::kChunks - 1)];
+}
+
+template <bool kSplit>
+__device__ __forceinline__ void c_put_w(uint32_t *__restrict__ wl, const CRegsW<kSplit> &r, int ctid)
+{
+#pragma unroll
+    for (int q = 0; q < CRegsW<kSplit>::kN; ++q) {
+        const int c = ctid + q * 64 * kWaves;
+        if (c < CRegsW<kSplit>::kChunks)
+            reinterpret_cast<f4v *>(wl)[c] = r.w[q];
+    }
 }
 
 // One producer iteration t >= 1: R(t - 1) out, product t + 1 converted from
 // set kPut, the maxima of product t + 2 (set kMax) published, the loads of
 // product t + 1 + kDepth into set kPut.
-template <bool kBf16, bool kSplit, int kProd, int kDepth, int kPut, int kMax>
-__device__ __forceinline__ void ws_lp_step(PRegsLp<kProd, kSplit> (&sr)[kDepth], c_item *my, int stride,
+template <bool kBf16, bool kSplit, int kProd, int kDepth, int kPut, int kMax, bool kWC>
+__device__ __forceinline__ void ws_lp_step(PRegsLp<kProd, kSplit, kWC> (&sr)[kDepth], c_item *my, int stride,
                                            int t, int n_my, float2 *sink, WsLdsLp<kProd, kSplit> &L,
                                            const PlanDev &pd, int ptid)
 {
     p_store_r<kProd>(item_at(my, t - 1, stride).R, L.r_buf[(t - 1) & 1], ptid);
     const int f1 = item_at(my, min(t + 1, n_my - 1), stride).f;
     const int f2 = t + 2 < n_my ? item_at(my, t + 2, stride).f : 0;
-    p_put_lp<kBf16, kSplit, kProd>(L.b_hi[(t + 1) & 1], L.b_lo[kSplit ? (t + 1) & 1 : 0], L.w[(t + 1) & 1],
+    p_put_lp<kBf16, kSplit, kProd, kWC>(L.b_hi[(t + 1) & 1], L.b_lo[kSplit ? (t + 1) & 1 : 0], L.w[(t + 1) & 1],
                                    L.smax[(t + 1) & 1], &L.es[(t + 1) & 1], sr[kPut], f1, ptid);
     p_publish_max<kProd>(L.smax[t & 1], sr[kMax].s, f2, ptid);
-    p_load_lp<kProd, kSplit>(sr[kPut], my, stride, t + 1 + kDepth, n_my, sink, pd, ptid);
+    p_load_lp<kProd, kSplit, kWC>(sr[kPut], my, stride, t + 1 + kDepth, n_my, sink, pd, ptid);
 }
 
 // The producer role (threads 64 kWaves ..).  Barriers: one before product
 // 0's conversion, then as the consumers: one before product 0 is used and
 // one after each product.
-template <bool kBf16, bool kSplit, int kProd, int kDepth>
+template <bool kBf16, bool kSplit, int kProd, int kDepth, bool kWC>
 __device__ __forceinline__ void ws_producer_lp(c_item *my, int stride, int n_my, float2 *sink,
                                                WsLdsLp<kProd, kSplit> &L, const PlanDev &pd)
 {
     static_assert(kDepth >= 2 && kDepth <= 3, "prefetch depth");
     const int ptid = threadIdx.x - 64 * kWaves;
     const int plane = ptid & 63;
-    PRegsLp<kProd, kSplit> sr[kDepth];
+    PRegsLp<kProd, kSplit, kWC> sr[kDepth];
     // Each load group is preceded by as many sink stores as an iteration
     // issues R stores, so that the outstanding memory operations at the
     // loop's entry follow the pattern of its back edge.
 #pragma unroll
     for (int u = 0; u < kDepth; ++u) {
         prime_store_count<kPStoreRounds<kProd>>(sink, plane);
-        p_load_lp<kProd, kSplit>(sr[u], my, stride, u, n_my, sink, pd, ptid);
+        p_load_lp<kProd, kSplit, kWC>(sr[u], my, stride, u, n_my, sink, pd, ptid);
     }
     p_publish_max<kProd>(L.smax[0], sr[0].s, item_at(my, 0, stride).f, ptid);
     __syncthreads();
-    p_put_lp<kBf16, kSplit, kProd>(L.b_hi[0], L.b_lo[0], L.w[0], L.smax[0], &L.es[0], sr[0],
+    p_put_lp<kBf16, kSplit, kProd, kWC>(L.b_hi[0], L.b_lo[0], L.w[0], L.smax[0], &L.es[0], sr[0],
                                    item_at(my, 0, stride).f, ptid);
     p_publish_max<kProd>(L.smax[1], sr[1].s, 1 < n_my ? item_at(my, 1, stride).f : 0, ptid);
     prime_store_count<kPStoreRounds<kProd>>(sink, plane);
-    p_load_lp<kProd, kSplit>(sr[0], my, stride, kDepth, n_my, sink, pd, ptid);
+    p_load_lp<kProd, kSplit, kWC>(sr[0], my, stride, kDepth, n_my, sink, pd, ptid);
     __syncthreads();
     // iteration 0: no R to write yet
     {
         prime_store_count<kPStoreRounds<kProd>>(sink, plane);
         const int f1 = item_at(my, min(1, n_my - 1), stride).f;
         const int f2 = 2 < n_my ? item_at(my, 2, stride).f : 0;
-        p_put_lp<kBf16, kSplit, kProd>(L.b_hi[1], L.b_lo[kSplit ? 1 : 0], L.w[1], L.smax[1], &L.es[1], sr[1],
+        p_put_lp<kBf16, kSplit, kProd, kWC>(L.b_hi[1], L.b_lo[kSplit ? 1 : 0], L.w[1], L.smax[1], &L.es[1], sr[1],
                                        f1, ptid);
         p_publish_max<kProd>(L.smax[0], sr[2 % kDepth].s, f2, ptid);
-        p_load_lp<kProd, kSplit>(sr[1], my, stride, 1 + kDepth, n_my, sink, pd, ptid);
+        p_load_lp<kProd, kSplit, kWC>(sr[1], my, stride, 1 + kDepth, n_my, sink, pd, ptid);
         __syncthreads();
     }
     // Iterations 1 .. n_my - 1 in groups of kDepth (constant register set
@@ -2047,24 +2082,24 @@ __device__ __forceinline__ void ws_producer_lp(c_item *my, int stride, int n_my,
     constexpr int kA2 = 4 % kDepth, kB2 = 5 % kDepth;
     int t = 1;
     for (int g = 0; g < groups; ++g) {
-        ws_lp_step<kBf16, kSplit, kProd, kDepth, kA0, kB0>(sr, my, stride, t, n_my, sink, L, pd, ptid);
+        ws_lp_step<kBf16, kSplit, kProd, kDepth, kA0, kB0, kWC>(sr, my, stride, t, n_my, sink, L, pd, ptid);
         __syncthreads();
-        ws_lp_step<kBf16, kSplit, kProd, kDepth, kA1, kB1>(sr, my, stride, t + 1, n_my, sink, L, pd, ptid);
+        ws_lp_step<kBf16, kSplit, kProd, kDepth, kA1, kB1, kWC>(sr, my, stride, t + 1, n_my, sink, L, pd, ptid);
         __syncthreads();
         if constexpr (kDepth >= 3) {
-            ws_lp_step<kBf16, kSplit, kProd, kDepth, kA2, kB2>(sr, my, stride, t + 2, n_my, sink, L, pd,
+            ws_lp_step<kBf16, kSplit, kProd, kDepth, kA2, kB2, kWC>(sr, my, stride, t + 2, n_my, sink, L, pd,
                                                                ptid);
             __syncthreads();
         }
         t += kDepth;
     }
     if (rest >= 1) {
-        ws_lp_step<kBf16, kSplit, kProd, kDepth, kA0, kB0>(sr, my, stride, t, n_my, sink, L, pd, ptid);
+        ws_lp_step<kBf16, kSplit, kProd, kDepth, kA0, kB0, kWC>(sr, my, stride, t, n_my, sink, L, pd, ptid);
         __syncthreads();
     }
     if constexpr (kDepth >= 3) {
         if (rest >= 2) {
-            ws_lp_step<kBf16, kSplit, kProd, kDepth, kA1, kB1>(sr, my, stride, t + 1, n_my, sink, L, pd,
+            ws_lp_step<kBf16, kSplit, kProd, kDepth, kA1, kB1, kWC>(sr, my, stride, t + 1, n_my, sink, L, pd,
                                                                ptid);
             __syncthreads();
         }
@@ -2141,7 +2176,7 @@ __device__ __forceinline__ void lp_chain_ws(const uint32_t *__restrict__ bhi, co
 
 // S must be 16-byte aligned and the plan's f_max at least 1 (the host routes
 // other batches elsewhere).
-template <bool kBf16, bool kSplit, int kProd, int kDepth>
+template <bool kBf16, bool kSplit, int kProd, int kDepth, bool kWC>
 __global__ __launch_bounds__(64 * (kWaves + kProd)) void apply_lp_ws(BfHeader *__restrict__ blk,
                                                                      const BfItem *__restrict__ items,
                                                                      int n_items, PlanDev pd)
@@ -2160,22 +2195,34 @@ __global__ __launch_bounds__(64 * (kWaves + kProd)) void apply_lp_ws(BfHeader *_
         // consumer.  The scalar reads for later products (f of t + 1, the W
         // exponent of t + 1) are issued at the end of product t, where the
         // barrier waits for them anyway.
+        // With kWC the consumers also stage W: product t + 1's W is loaded
+        // while product t's chain runs and copied into LDS before the
+        // barrier (the producers then move S only).
         const int wave = wave8;
         int f = item_at(my, 0, stride).f;
         int ew = pd.lp_exp[item_at(my, 0, stride).w_id];
+        CRegsW<kSplit> wr;
+        if constexpr (kWC) {
+            c_load_w<kSplit>(wr, pd, item_at(my, 0, stride).w_id, threadIdx.x);
+            c_put_w<kSplit>(L.w[0], wr, threadIdx.x);
+        }
         __syncthreads();
         __syncthreads();
         for (int t = 0; t < n_my; ++t) {
+            if constexpr (kWC)
+                c_load_w<kSplit>(wr, pd, item_at(my, min(t + 1, n_my - 1), stride).w_id, threadIdx.x);
             lp_chain_ws<kBf16, kSplit>(L.b_hi[t & 1], L.b_lo[kSplit ? t & 1 : 0], L.w[t & 1], f,
                                        ew + L.es[t & 1], wave, lane, L.r_buf[t & 1] + wave * kWaveOut);
             __builtin_amdgcn_sched_barrier(0);
+            if constexpr (kWC)
+                c_put_w<kSplit>(L.w[(t + 1) & 1], wr, threadIdx.x);
             const BfItem dn = item_at(my, min(t + 1, n_my - 1), stride);
             f = dn.f;
             ew = pd.lp_exp[dn.w_id];
             __syncthreads();
         }
     } else {
-        ws_producer_lp<kBf16, kSplit, kProd, kDepth>(my, stride, n_my, sink, L, pd);
+        ws_producer_lp<kBf16, kSplit, kProd, kDepth, kWC>(my, stride, n_my, sink, L, pd);
     }
 }
 
@@ -2419,7 +2466,9 @@ static hipError_t launch_lp_t(const LaunchCfg &cfg, BfHeader *blk, int n_items, 
 }
 
 // Schedule 3 for the 16-bit forms: producer waves and S prefetch depth from
-// the variant.
+// the variant.  The consumer waves stage W (kWC): with the producers moving
+// S only, the split forms went from 182.4 to 168.2 us and plain FP16 from
+// 152.0 to 148.7 us on the gain workload (12 producers, same box).
 template <bool kBf16, bool kSplit>
 static hipError_t launch_lp_ws(const LaunchCfg &cfg, BfHeader *blk, int n_items, const PlanDev &pd,
                                hipStream_t st)
@@ -2427,16 +2476,16 @@ static hipError_t launch_lp_ws(const LaunchCfg &cfg, BfHeader *blk, int n_items,
     const BfItem *items = items_of(blk);
     const dim3 grid(cfg.grid);
     if (cfg.producers == 4)
-        hipLaunchKernelGGL((apply_lp_ws<kBf16, kSplit, 4, 2>), grid, dim3(64 * 8), 0, st, blk, items,
+        hipLaunchKernelGGL((apply_lp_ws<kBf16, kSplit, 4, 2, true>), grid, dim3(64 * 8), 0, st, blk, items,
                            n_items, pd);
     else if (cfg.producers == 12)
-        hipLaunchKernelGGL((apply_lp_ws<kBf16, kSplit, 12, 2>), grid, dim3(64 * 16), 0, st, blk, items,
+        hipLaunchKernelGGL((apply_lp_ws<kBf16, kSplit, 12, 2, true>), grid, dim3(64 * 16), 0, st, blk, items,
                            n_items, pd);
     else if (cfg.depth >= 3)
-        hipLaunchKernelGGL((apply_lp_ws<kBf16, kSplit, 8, 3>), grid, dim3(64 * 12), 0, st, blk, items,
+        hipLaunchKernelGGL((apply_lp_ws<kBf16, kSplit, 8, 3, true>), grid, dim3(64 * 12), 0, st, blk, items,
                            n_items, pd);
     else
-        hipLaunchKernelGGL((apply_lp_ws<kBf16, kSplit, 8, 2>), grid, dim3(64 * 12), 0, st, blk, items,
+        hipLaunchKernelGGL((apply_lp_ws<kBf16, kSplit, 8, 2, true>), grid, dim3(64 * 12), 0, st, blk, items,
                            n_items, pd);
     return hipGetLastError();
 }
@@ -2489,7 +2538,7 @@ template <bool kBf16, bool kSplit, bool kStage>
 static int occ_lp(int schedule, bool vec16)
 {
     if (schedule == 3)
-        return occ_of(apply_lp_ws<kBf16, kSplit, 4, 2>, 512);
+        return occ_of(apply_lp_ws<kBf16, kSplit, 4, 2, true>, 512);
     if (schedule == 0)
         return vec16 ? occ_of(apply_lp_single<kBf16, kSplit, true, kStage>)
                      : occ_of(apply_lp_single<kBf16, kSplit, false, kStage>);
