@@ -177,44 +177,72 @@ def time_launches(launch, steps, torch, stream, group=GROUP):
     return np.array([a.elapsed_time(b) / group for a, b in ev])
 
 
-def kernel_time_graph(plan, db, batch, prec, steps, copies, torch, stream, settle_ms: float = 200.0):
-    """Average duration of the apply kernel alone: the same kernel and grid,
-    launched from captured graphs (descriptors already on the device), one
-    graph per buffer set, run for settle_ms (creating the graphs leaves the
-    device idle long enough for its clock to drop), then at least 200
-    launches timed with HIP events on the launch stream."""
+def own_kernel_times(plan, prec, apply, launches, torch, stream):
+    """Durations, in ms, of the apply kernels of `launches` calls of
+    apply(i) (each a bf_apply* call on `plan` for precision `prec`), from
+    the event pair each kernel records at its own start and end
+    (bf_plan_set_kernel_events): the kernel alone, without the descriptor
+    upload or the queue's gap between two launches."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(launches)]
+    for a, b in ev:   # creates the events
+        a.record(stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    try:
+        for i in range(launches):
+            bf.bf_plan_set_kernel_events(plan, ev[i][0], ev[i][1])
+            apply(i)
+    finally:
+        bf.bf_plan_set_kernel_events(plan, None, None)
+    torch.cuda.synchronize()
+    return np.array([a.elapsed_time(b) for a, b in ev])
+
+
+def kernel_time(plan, db, batch, prec, steps, copies, torch, stream, settle_ms: float = 200.0):
+    """Duration of the apply kernel at steady state: the batch fixed on the
+    device once per buffer set (bf_graph_create; same kernel, grid and
+    product order as bf_apply), replays launched back to back over the sets
+    in turn for settle_ms (what ran before may have left the device idle
+    long enough for its clock to drop), then at least 200 replays timed
+    with HIP events on the launch stream around groups of GROUP of them.
+    A replay is one plain kernel launch, so the queue leaves about 0.4 us
+    between two kernels: the per-launch mean is the kernel's duration to
+    within that.  Then as many replays again, each timed by the start and
+    end events the kernel records itself (hipExtLaunchKernel), which read
+    a few microseconds longer.  Returns (per-launch ms of each group,
+    per-kernel ms from the kernels' own events)."""
     graphs = [bf.bf_graph_create(plan, batch.w_ids, batch.f, db.s_ptrs[c], db.r_ptrs[c], prec)
               for c in range(copies)]
     launch = lambda i: bf.bf_graph_launch(graphs[i % copies], stream)  # noqa: E731
-    settle(launch, settle_ms, torch)
-    ms = time_launches(launch, max(steps, 200), torch, stream)
-    for g in graphs:
-        g.close()
-    return ms
+    try:
+        settle(launch, settle_ms, torch)
+        n = max(steps, 200)
+        grouped = time_launches(launch, n, torch, stream)
+        own = own_kernel_times(plan, prec, launch, n, torch, stream)
+        return grouped, own
+    finally:
+        torch.cuda.synchronize()
+        for g in graphs:
+            g.close()
 
 
 def workload_kernel(batch, prec: int, torch, stream, copies: int, settle_ms: float, launches: int,
                     sample: int = 256) -> dict:
-    """Kernel time of one precision form on one workload at steady state:
-    the plan's default variant, launched from captured graphs over `copies`
-    disjoint buffer sets, run for settle_ms, then `launches` launches timed
-    with HIP events in groups.  Also returns (under "_sample") host copies of
-    a seeded sample of the products of the last launch, for the CPU leg's
+    """Kernel time of one precision form on one workload at steady state
+    (kernel_time: the plan's default variant over `copies` disjoint buffer
+    sets, settle_ms, then `launches` kernels each timed by its own start
+    and end events).  Also returns (under "_sample") host copies of a
+    seeded sample of the products of the last launch, for the CPU leg's
     error check."""
     from paper_1810_11451_amd.device import DeviceBatch
     plan = bf.bf_plan_create(batch.W, bf.BF_PREC_BIT(prec))
     db = DeviceBatch(batch, copies=copies, fill_r=None)
-    graphs = [bf.bf_graph_create(plan, batch.w_ids, batch.f, db.s_ptrs[c], db.r_ptrs[c], prec)
-              for c in range(copies)]
-    launch = lambda i: bf.bf_graph_launch(graphs[i % copies], stream)  # noqa: E731
-    settle(launch, settle_ms, torch)
-    ms = time_launches(launch, launches, torch, stream)
-    last = (len(ms) * GROUP - 1) % copies
+    ms, own = kernel_time(plan, db, batch, prec, launches, copies, torch, stream, settle_ms)
+    last = (len(own) - 1) % copies
     items = np.sort(np.random.default_rng(777).choice(batch.n, size=min(sample, batch.n), replace=False))
     got = db.R[last].index_select(0, torch.as_tensor(items, device=db.R[last].device)).cpu().numpy()
     variant = bf.bf_get_variant(plan, prec, bf.batch_bucket(batch.f))
-    for g in graphs:
-        g.close()
     plan.close()
     del db
     torch.cuda.empty_cache()
@@ -224,6 +252,7 @@ def workload_kernel(batch, prec: int, torch, stream, copies: int, settle_ms: flo
     return {"prec": bf.PREC_NAMES[prec], "kernel": kernel_symbol(prec, sched, variant[3]),
             "variant": list(variant), "kernel_us_mean": round(us, 2),
             "kernel_us_p50": round(float(np.median(ms)) * 1e3, 2),
+            "kernel_us_own_events": round(float(np.mean(own)) * 1e3, 2),
             "hbm_gbs": round(nbytes / (us * 1e-6) / 1e9, 1),
             "hbm_frac": round(nbytes / (us * 1e-6) / (PEAK_HBM_GBS * 1e9), 4),
             "complex_gflops": round(batch.flops() / (us * 1e-6) / 1e9, 1),
@@ -618,14 +647,14 @@ def main(argv=None) -> int:
         ev[i][1].record(stream)
     torch.cuda.synchronize()
     step_ms = np.array([a.elapsed_time(b) for a, b in ev])
-    kern_ms = kernel_time_graph(plan, db, batch, prec, K, args.copies, torch, stream)
+    kern_ms, kern_own = kernel_time(plan, db, batch, prec, K, args.copies, torch, stream)
     kern_s = float(np.mean(kern_ms)) / 1e3
 
     compare = None
     if prec == bf.BF_FP32_3M and not args.no_compare:
         # The four-product FP32 form on the same workload, kernel time only.
         plan4 = bf.bf_plan_create(batch.W, bf.BF_PREC_BIT(bf.BF_FP32))
-        k4 = kernel_time_graph(plan4, db, batch, bf.BF_FP32, K, args.copies, torch, stream)
+        k4, _ = kernel_time(plan4, db, batch, bf.BF_FP32, K, args.copies, torch, stream)
         v4 = bf.bf_get_variant(plan4, bf.BF_FP32, bf.batch_bucket(batch.f))
         plan4.close()
         t4 = float(np.mean(k4)) / 1e3
@@ -638,7 +667,7 @@ def main(argv=None) -> int:
         # The 2-term split FP16 form (FP32-class accuracy from 16-bit matrix
         # cores) on the same workload, kernel time only, against this form.
         plans = bf.bf_plan_create(batch.W, bf.BF_PREC_BIT(bf.BF_FP16X2))
-        ks = kernel_time_graph(plans, db, batch, bf.BF_FP16X2, K, args.copies, torch, stream)
+        ks, _ = kernel_time(plans, db, batch, bf.BF_FP16X2, K, args.copies, torch, stream)
         vs = bf.bf_get_variant(plans, bf.BF_FP16X2, bf.batch_bucket(batch.f))
         plans.close()
         split = {"prec": "fp16x2", "kernel_us_mean": round(float(np.mean(ks)) * 1e3, 2),
@@ -672,9 +701,12 @@ def main(argv=None) -> int:
     roof["kernel_us_mean"] = round(kern_s * 1e6, 2)
     roof["kernel_us_p50"] = round(float(np.median(kern_ms)) * 1e3, 2)
     roof["kernel_us_min"] = round(float(np.min(kern_ms)) * 1e3, 2)
-    roof["kernel_timing"] = ("HIP events on the launch stream around groups of 10 back-to-back graph "
-                             "launches of the same kernel and grid, after 200 ms of such launches")
+    roof["kernel_timing"] = (f"HIP events on the launch stream around groups of {GROUP} back-to-back launches "
+                             "of the batch fixed on the device (bf_graph_launch: one plain kernel launch each, "
+                             "same kernel and grid as bf_apply), after 200 ms of them")
+    roof["kernel_us_own_events"] = round(float(np.mean(kern_own)) * 1e3, 2)
     roof["step_us_mean"] = round(float(np.mean(step_ms)) * 1e3, 2)
+    roof["launch_period_us"] = round(wall / K * 1e6, 2)
     roof["algorithmic"] = {"flops_per_launch": flops, "bytes_per_launch": nbytes,
                            "ai_flop_per_byte": round(ai, 2)}
     roof["floors_us"] = floors

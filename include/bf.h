@@ -173,13 +173,27 @@ bf_status bf_apply_packed(bf_plan plan, int32_t batch, const int32_t *w_ids, con
 bf_status bf_check_batch(int32_t n_w, int32_t f_max, int32_t batch, const int32_t *w_ids,
                          const int32_t *f, const void *const *S, void *const *R);
 
+/* ---- kernel timing ----------------------------------------------------
+ * With start and stop set (hipEvent_t, created by the caller with timing
+ * enabled), the apply kernel that each later bf_apply, bf_apply_packed,
+ * bf_apply_noalloc or bf_graph_launch call on this plan launches records
+ * start when it begins executing and stop when it ends
+ * (hipExtLaunchKernel), so that hipEventElapsedTime(start, stop) gives the
+ * duration of that kernel alone: neither the descriptor upload nor the gap
+ * the queue leaves between two launches.  Each launch overwrites the pair;
+ * set a new pair before each call to time a sequence.  NULL, NULL switches
+ * it off (the default).  Errors: BF_ERR_INVALID for a null plan or for
+ * only one of the two events. */
+bf_status bf_plan_set_kernel_events(bf_plan plan, void *start, void *stop);
+
 /* ---- graph: a fixed batch replayed many times ------------------------
  * A 5G slot loop often repeats the same set of products over the same
  * (double-buffered) S and R buffers.  bf_graph_create validates the batch
  * once, uploads its descriptors (in the order the plan's variant for this
- * batch asks for) to device memory owned by the graph, and captures the
- * apply kernel into a hipGraph; bf_graph_launch replays it on any stream
- * with no host work besides the launch.  Replays of one graph must not
+ * batch asks for) to device memory owned by the graph and fixes the launch
+ * configuration; bf_graph_launch replays it on any stream as one kernel
+ * launch, with no upload and no event (it may itself be captured into the
+ * caller's hipGraph).  Replays of one graph must not
  * overlap (one stream, or ordered by the caller): the persistent claim
  * schedule re-arms its counter at the end of each replay.  Arguments as
  * for bf_apply. */

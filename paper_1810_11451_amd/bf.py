@@ -86,6 +86,7 @@ _SIGS = {
     "bf_apply": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _i32, _vp]),
     "bf_apply_packed": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _i32, _vp]),
     "bf_apply_noalloc": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _i32, _vp]),
+    "bf_plan_set_kernel_events": (_i32, [_vp, _vp, _vp]),
     "bf_check_batch": (_i32, [_i32, _i32, _i32, _vp, _vp, _vp, _vp]),
     "bf_graph_create": (_i32, [ctypes.POINTER(_vp), _vp, _i32, _vp, _vp, _vp, _vp, _i32, _vp]),
     "bf_graph_launch": (_i32, [_vp, _vp]),
@@ -273,6 +274,18 @@ def bf_apply_noalloc(plan: Plan, w_ids, f, S_ptrs, R_ptrs, prec: int = BF_FP32, 
     R = _ptr_array(R_ptrs, n)
     _check(lib().bf_apply_noalloc(plan.handle, n, w_ids.ctypes.data, f.ctypes.data, S.ctypes.data,
                                   R.ctypes.data, int(prec), _stream(stream)), "bf_apply_noalloc")
+
+
+def bf_plan_set_kernel_events(plan: Plan, start=None, stop=None) -> None:
+    """Events (torch.cuda.Event(enable_timing=True), or raw hipEvent_t
+    handles) that the apply kernel of each later bf_apply* call on the plan
+    records at its own start and end; None, None switches it off."""
+    def handle(e):
+        if e is None:
+            return None
+        return int(e.cuda_event) if hasattr(e, "cuda_event") else int(e)
+    _check(lib().bf_plan_set_kernel_events(plan.handle, handle(start), handle(stop)),
+           "bf_plan_set_kernel_events")
 
 
 def bf_apply_packed(plan: Plan, w_ids, f, S_base, s_off, R_base, prec: int = BF_FP32,

@@ -70,7 +70,9 @@ struct bf_plan_s {
     bool any_update = false;
 
     hipStream_t copy_stream = nullptr;   // descriptor uploads (overlap the previous launch)
-    std::mutex mu;              // guards the ring, the tables and the sort buffers
+    std::mutex mu;              // guards the ring, the tables, the sort buffers and kev_*
+    hipEvent_t kev_start = nullptr;   // kernel timing events (bf_plan_set_kernel_events)
+    hipEvent_t kev_stop = nullptr;
     std::vector<StagingSlot> ring;
     size_t ring_next = 0;
     bf_variant table[kPrecCount][kBucketCount];

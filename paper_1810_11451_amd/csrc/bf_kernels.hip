@@ -21,6 +21,7 @@
 // Workgroup: 4 waves; wave w owns antennas 16w .. 16w+15 (32 real rows,
 // one 32 x 32 matrix-core tile in M) and both 32-column tiles in N.  S is
 // staged once per item in LDS and read by all four waves.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -2375,42 +2376,54 @@ static const BfItem *items_of(BfHeader *blk)
                                             sizeof(BfHeader) + kSinkBytes);
 }
 
+// Launches an apply kernel; with the timing events of the configuration
+// set, through hipExtLaunchKernel, which records them at the kernel's own
+// start and end.
+#define BF_LAUNCH(cfg, kernel, grid, block, st, ...)                                          \
+    do {                                                                                      \
+        if ((cfg).ev_start)                                                                   \
+   hipExtLaunchKernelGGL(kernel, grid, block, 0, st, (cfg).ev_start, (cfg).ev_stop, 0, \
+                         __VA_ARGS__);                                               \
+        else                                                                                  \
+   hipLaunchKernelGGL(kernel, grid, block, 0, st, __VA_ARGS__);                      \
+    } while (0)
+
 // Schedule 3 launch: producer waves and S prefetch depth from the variant.
 template <bool k3M>
 static hipError_t launch_ws(const LaunchCfg &cfg, BfHeader *blk, int n_items, const void *apool,
-                            int a_stride, int pairs, hipStream_t st)
+                   int a_stride, int pairs, hipStream_t st)
 {
     const BfItem *items = items_of(blk);
     const dim3 grid(cfg.grid);
     if (k3M && cfg.tile16) {
         if (cfg.depth >= 2)
-            hipLaunchKernelGGL((apply_fp32_3m16_ws<8, 2>), grid, dim3(64 * (kCons16 + 8)), 0, st, blk,
-                               items, n_items, apool, a_stride, pairs);
+            BF_LAUNCH(cfg, (apply_fp32_3m16_ws<8, 2>), grid, dim3(64 * (kCons16 + 8)), st, blk,
+                      items, n_items, apool, a_stride, pairs);
         else
-            hipLaunchKernelGGL((apply_fp32_3m16_ws<8, 1>), grid, dim3(64 * (kCons16 + 8)), 0, st, blk,
-                               items, n_items, apool, a_stride, pairs);
+            BF_LAUNCH(cfg, (apply_fp32_3m16_ws<8, 1>), grid, dim3(64 * (kCons16 + 8)), st, blk,
+                      items, n_items, apool, a_stride, pairs);
         return hipGetLastError();
     }
     if (cfg.producers == 4)
-        hipLaunchKernelGGL((apply_fp32_ws<k3M, 4, 1>), grid, dim3(64 * 8), 0, st, blk, items,
-                           n_items, apool, a_stride, pairs);
+        BF_LAUNCH(cfg, (apply_fp32_ws<k3M, 4, 1>), grid, dim3(64 * 8), st, blk, items,
+                  n_items, apool, a_stride, pairs);
     else if (!k3M && cfg.producers == 12 && cfg.depth == 2)
         // (the three-product form's two accumulator sets do not fit 16 waves'
         // register share; the host gives it at most 8 producers)
-        hipLaunchKernelGGL((apply_fp32_ws<false, 12, 2>), grid, dim3(64 * 16), 0, st, blk, items,
-                           n_items, apool, a_stride, pairs);
+        BF_LAUNCH(cfg, (apply_fp32_ws<false, 12, 2>), grid, dim3(64 * 16), st, blk, items,
+                  n_items, apool, a_stride, pairs);
     else if (!k3M && cfg.producers == 12)
-        hipLaunchKernelGGL((apply_fp32_ws<false, 12, 1>), grid, dim3(64 * 16), 0, st, blk, items,
-                           n_items, apool, a_stride, pairs);
+        BF_LAUNCH(cfg, (apply_fp32_ws<false, 12, 1>), grid, dim3(64 * 16), st, blk, items,
+                  n_items, apool, a_stride, pairs);
     else if (cfg.depth == 3)
-        hipLaunchKernelGGL((apply_fp32_ws<k3M, 8, 3>), grid, dim3(64 * 12), 0, st, blk, items,
-                           n_items, apool, a_stride, pairs);
+        BF_LAUNCH(cfg, (apply_fp32_ws<k3M, 8, 3>), grid, dim3(64 * 12), st, blk, items,
+                  n_items, apool, a_stride, pairs);
     else if (cfg.depth == 2)
-        hipLaunchKernelGGL((apply_fp32_ws<k3M, 8, 2>), grid, dim3(64 * 12), 0, st, blk, items,
-                           n_items, apool, a_stride, pairs);
+        BF_LAUNCH(cfg, (apply_fp32_ws<k3M, 8, 2>), grid, dim3(64 * 12), st, blk, items,
+                  n_items, apool, a_stride, pairs);
     else
-        hipLaunchKernelGGL((apply_fp32_ws<k3M, 8, 1>), grid, dim3(64 * 12), 0, st, blk, items,
-                           n_items, apool, a_stride, pairs);
+        BF_LAUNCH(cfg, (apply_fp32_ws<k3M, 8, 1>), grid, dim3(64 * 12), st, blk, items,
+                  n_items, apool, a_stride, pairs);
     return hipGetLastError();
 }
 
@@ -2421,18 +2434,18 @@ static hipError_t launch_fp32_t(const LaunchCfg &cfg, BfHeader *blk, int n_items
     const BfItem *items = items_of(blk);
     switch (cfg.schedule) {
     case 0:
-        hipLaunchKernelGGL((apply_fp32_single<kVec16, kStage>), dim3(n_items), dim3(kThreads), 0, st,
-                           blk, items, n_items, pd.a_fp32, pd.a_fp32_stride, pd.pairs);
+        BF_LAUNCH(cfg, (apply_fp32_single<kVec16, kStage>), dim3(n_items), dim3(kThreads), st,
+                  blk, items, n_items, pd.a_fp32, pd.a_fp32_stride, pd.pairs);
         break;
     case 1:
-        hipLaunchKernelGGL(apply_fp32_claim<kVec16>, dim3(cfg.grid), dim3(kThreads), 0, st, blk,
-                           items, n_items, pd.a_fp32, pd.a_fp32_stride, pd.pairs);
+        BF_LAUNCH(cfg, apply_fp32_claim<kVec16>, dim3(cfg.grid), dim3(kThreads), st, blk,
+                  items, n_items, pd.a_fp32, pd.a_fp32_stride, pd.pairs);
         break;
     case 3:
         return launch_ws<false>(cfg, blk, n_items, (const void *)pd.a_fp32, pd.a_fp32_stride, pd.pairs, st);
     default:
-        hipLaunchKernelGGL((apply_fp32_stream<kVec16, kStage>), dim3(cfg.grid), dim3(kThreads), 0,
-                           st, blk, items, n_items, pd.a_fp32, pd.a_fp32_stride, pd.pairs);
+        BF_LAUNCH(cfg, (apply_fp32_stream<kVec16, kStage>), dim3(cfg.grid), dim3(kThreads), st, blk,
+                  items, n_items, pd.a_fp32, pd.a_fp32_stride, pd.pairs);
         break;
     }
     return hipGetLastError();
@@ -2444,8 +2457,8 @@ static hipError_t launch_3m_t(const LaunchCfg &cfg, BfHeader *blk, int n_items, 
 {
     const BfItem *items = items_of(blk);
     if (cfg.schedule == 0)
-        hipLaunchKernelGGL(apply_fp32_3m_single<kVec16>, dim3(n_items), dim3(kThreads), 0, st, blk,
-                           items, n_items, pd.a_3m, pd.a_3m_stride, pd.pairs);
+        BF_LAUNCH(cfg, apply_fp32_3m_single<kVec16>, dim3(n_items), dim3(kThreads), st, blk,
+                  items, n_items, pd.a_3m, pd.a_3m_stride, pd.pairs);
     else
         return launch_ws<true>(cfg, blk, n_items, (const void *)pd.a_3m, pd.a_3m_stride, pd.pairs, st);
     return hipGetLastError();
@@ -2457,11 +2470,11 @@ static hipError_t launch_lp_t(const LaunchCfg &cfg, BfHeader *blk, int n_items, 
 {
     const BfItem *items = items_of(blk);
     if (cfg.schedule == 0)
-        hipLaunchKernelGGL((apply_lp_single<kBf16, kSplit, kVec16, kStage>), dim3(n_items),
-                           dim3(kThreads), 0, st, blk, items, n_items, pd);
+        BF_LAUNCH(cfg, (apply_lp_single<kBf16, kSplit, kVec16, kStage>), dim3(n_items),
+                  dim3(kThreads), st, blk, items, n_items, pd);
     else
-        hipLaunchKernelGGL((apply_lp_stream<kBf16, kSplit, kVec16, kStage>), dim3(cfg.grid),
-                           dim3(kThreads), 0, st, blk, items, n_items, pd);
+        BF_LAUNCH(cfg, (apply_lp_stream<kBf16, kSplit, kVec16, kStage>), dim3(cfg.grid),
+                  dim3(kThreads), st, blk, items, n_items, pd);
     return hipGetLastError();
 }
 
@@ -2476,17 +2489,17 @@ static hipError_t launch_lp_ws(const LaunchCfg &cfg, BfHeader *blk, int n_items,
     const BfItem *items = items_of(blk);
     const dim3 grid(cfg.grid);
     if (cfg.producers == 4)
-        hipLaunchKernelGGL((apply_lp_ws<kBf16, kSplit, 4, 2, true>), grid, dim3(64 * 8), 0, st, blk, items,
-                           n_items, pd);
+        BF_LAUNCH(cfg, (apply_lp_ws<kBf16, kSplit, 4, 2, true>), grid, dim3(64 * 8), st, blk, items,
+                  n_items, pd);
     else if (cfg.producers == 12)
-        hipLaunchKernelGGL((apply_lp_ws<kBf16, kSplit, 12, 2, true>), grid, dim3(64 * 16), 0, st, blk, items,
-                           n_items, pd);
+        BF_LAUNCH(cfg, (apply_lp_ws<kBf16, kSplit, 12, 2, true>), grid, dim3(64 * 16), st, blk, items,
+                  n_items, pd);
     else if (cfg.depth >= 3)
-        hipLaunchKernelGGL((apply_lp_ws<kBf16, kSplit, 8, 3, true>), grid, dim3(64 * 12), 0, st, blk, items,
-                           n_items, pd);
+        BF_LAUNCH(cfg, (apply_lp_ws<kBf16, kSplit, 8, 3, true>), grid, dim3(64 * 12), st, blk, items,
+                  n_items, pd);
     else
-        hipLaunchKernelGGL((apply_lp_ws<kBf16, kSplit, 8, 2, true>), grid, dim3(64 * 12), 0, st, blk, items,
-                           n_items, pd);
+        BF_LAUNCH(cfg, (apply_lp_ws<kBf16, kSplit, 8, 2, true>), grid, dim3(64 * 12), st, blk, items,
+                  n_items, pd);
     return hipGetLastError();
 }
 

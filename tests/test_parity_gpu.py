@@ -238,6 +238,41 @@ def test_graph_replay_matches_direct():
     g.close()
     err, _ = rel_errors(b, Rd)
     assert np.max(err) <= FP32_TOL
+
+
+@pytest.mark.parametrize("prec,variant", [(bf.BF_FP32, (1, 0, 1)), (bf.BF_FP32_3M, (3, 0, 0, 7))],
+                         ids=["fp32-claim", "fp32_3m-ws16"])
+def test_graph_launch_inside_a_captured_hip_graph(prec, variant):
+    """bf_graph_launch captured into the caller's own hipGraph (torch's
+    CUDAGraph): every replay, with eager work between replays, gives the
+    direct launch's products bit for bit (the persistent schedules re-arm
+    their counters at the end of each launch)."""
+    torch = require_gpu()
+    b = wl.uneven_batch(n=900)
+    plan = bf.bf_plan_create(b.W, bf.BF_PREC_BIT(prec))
+    for bk in range(5):
+        bf.bf_set_variant(plan, prec, bk, *variant)
+    direct = DeviceBatch(b)
+    direct.apply(plan, prec)
+    Rd = direct.result()
+    db = DeviceBatch(b)
+    g = bf.bf_graph_create(plan, b.w_ids, b.f, db.s_ptrs[0], db.r_ptrs[0], prec)
+    announce(f"bf_graph_launch captured, prec={bf.PREC_NAMES[prec]} variant={variant}")
+    outer = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(outer):
+        bf.bf_graph_launch(g, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    for rep in range(3):
+        db.R[0].view(torch.float32).fill_(float("nan"))
+        outer.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(db.result().view(np.uint32), Rd.view(np.uint32)), f"replay {rep} differs"
+        direct.apply(plan, prec)    # eager work between replays
+        torch.cuda.synchronize()
+    del outer
+    g.close()
+    plan.close()
     plan.close()
 
 
