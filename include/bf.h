@@ -319,6 +319,8 @@ typedef struct {
 typedef struct {
     uint64_t submitted, admitted, completed, refused, launches, deadline_misses;
     uint64_t inflight_bytes, peak_inflight_bytes, queued;
+    uint64_t launch_host_ns;  /* host time the batcher spent packing and
+                                 enqueueing launches, summed over them */
 } bf_server_stats;
 
 /* cfg may be NULL for defaults: 16 GiB budget, no deadline, 2 streams,
@@ -330,6 +332,15 @@ bf_status bf_server_create(bf_server *out, bf_plan plan, const bf_server_cfg *cf
  * than the whole budget), BF_ERR_BUSY if the queue is full.  One thread
  * at a time may submit to a server. */
 bf_status bf_submit(bf_server server, const bf_request *req, uint64_t *ticket);
+/* Enqueue reqs[0 .. n) as bf_submit would one by one, with one hand-over
+ * to the batcher for all of them (requests that arrive together, such as
+ * one slot's, cost a few tens of nanoseconds each this way).  Every
+ * request is checked first: on a bad one (BF_ERR_INVALID, naming its
+ * index) nothing is queued.  Then as many as the queue has room for are
+ * queued, in order, with consecutive tickets from *first_ticket (may be
+ * NULL); returns that count (0 .. n: fewer than n when the queue filled;
+ * resubmit the rest) or a bf_status.  Same threading rule as bf_submit. */
+int32_t bf_submit_batch(bf_server server, const bf_request *reqs, int32_t n, uint64_t *first_ticket);
 /* Copy up to max completions into out, waiting up to timeout_us for the
  * first (0: no wait, < 0: forever).  Returns the count (>= 0) or a
  * bf_status (BF_ERR_TIMEOUT when nothing completed in time).  May be

@@ -100,6 +100,7 @@ int32_t bfh_device_peak_unfinished(bfh_device dev);
 bf_status bfh_server_create(bfh_server *out, bfh_device dev, const bf_server_cfg *cfg, int32_t n_w,
                             int32_t f_max);
 bf_status bfh_submit(bfh_server server, const bf_request *req, uint64_t *ticket);
+int32_t bfh_submit_batch(bfh_server server, const bf_request *reqs, int32_t n, uint64_t *first_ticket);
 int32_t bfh_poll(bfh_server server, bf_completion *out, int32_t max, int64_t timeout_us);
 bf_status bfh_server_stats_get(bfh_server server, bf_server_stats *out);
 bf_status bfh_server_destroy(bfh_server server);

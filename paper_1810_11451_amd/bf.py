@@ -56,7 +56,7 @@ class bf_server_cfg(ctypes.Structure):
 class bf_server_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in
                 ("submitted", "admitted", "completed", "refused", "launches", "deadline_misses",
-                 "inflight_bytes", "peak_inflight_bytes", "queued")]
+                 "inflight_bytes", "peak_inflight_bytes", "queued", "launch_host_ns")]
 
     def as_dict(self):
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
@@ -105,6 +105,7 @@ _SIGS = {
     "bf_device_cu_count": (_i32, []),
     "bf_server_create": (_i32, [ctypes.POINTER(_vp), _vp, ctypes.POINTER(bf_server_cfg)]),
     "bf_submit": (_i32, [_vp, _vp, ctypes.POINTER(ctypes.c_uint64)]),
+    "bf_submit_batch": (_i32, [_vp, _vp, _i32, ctypes.POINTER(ctypes.c_uint64)]),
     "bf_poll": (_i32, [_vp, _vp, _i32, _i64]),
     "bf_server_stats_get": (_i32, [_vp, ctypes.POINTER(bf_server_stats)]),
     "bf_server_destroy": (_i32, [_vp]),
@@ -451,6 +452,16 @@ def make_request(w_id: int, f: int, n_s: int, S, R, tag: int = 0, t_arrival_ns: 
     return r
 
 
+def bf_submit_batch(server: Server, reqs) -> tuple:
+    """Submit REQUEST_DTYPE records in one call; returns (requests queued,
+    first ticket).  Fewer than given means the queue filled."""
+    reqs = np.ascontiguousarray(reqs, dtype=REQUEST_DTYPE)
+    t = ctypes.c_uint64()
+    n = _check(lib().bf_submit_batch(server.handle, reqs.ctypes.data, int(reqs.shape[0]),
+                                     ctypes.byref(t)), "bf_submit_batch")
+    return int(n), int(t.value)
+
+
 def bf_submit(server: Server, req) -> int:
     """Submit one request (a REQUEST_DTYPE record); returns its ticket."""
     req = np.ascontiguousarray(req, dtype=REQUEST_DTYPE)
@@ -488,9 +499,11 @@ _loadgen = None
 
 
 def loadgen_replay(server: Server, reqs: np.ndarray, t_offset_ns: np.ndarray,
-                   progress_every: int = 0, stall_ms: int = 0, label: str = "replay") -> tuple:
+                   progress_every: int = 0, stall_ms: int = 0, label: str = "replay",
+                   with_submit_ns: bool = False) -> tuple:
     """Replays reqs (REQUEST_DTYPE) at the given offsets from a native thread
-    (benchmark helper); returns (completions in request order, busy retries).
+    (benchmark helper); returns (completions in request order, busy retries),
+    and with with_submit_ns the nanoseconds spent inside bf_submit calls.
     progress_every > 0 prints a stderr line per that many completions;
     stall_ms > 0 gives up (BfError, BF_ERR_TIMEOUT) when requests are
     outstanding and none completes for that long."""
@@ -501,17 +514,21 @@ def loadgen_replay(server: Server, reqs: np.ndarray, t_offset_ns: np.ndarray,
             raise RuntimeError(f"{LOADGEN_PATH} is not built")
         L = ctypes.CDLL(str(LOADGEN_PATH))
         L.bf_loadgen_replay.restype = _i64
-        L.bf_loadgen_replay.argtypes = [_vp, _vp, _vp, _i64, _vp, _i64, _i64, ctypes.c_char_p]
+        L.bf_loadgen_replay.argtypes = [_vp, _vp, _vp, _i64, _vp, _i64, _i64, ctypes.c_char_p,
+                                        ctypes.POINTER(_i64)]
         _loadgen = L
     reqs = np.ascontiguousarray(reqs, dtype=REQUEST_DTYPE)
     t_off = np.ascontiguousarray(t_offset_ns, dtype=np.int64)
     if t_off.shape != (reqs.shape[0],):
         raise ValueError("one offset per request")
     done = np.zeros(reqs.shape[0], COMPLETION_DTYPE)
+    submit_ns = _i64(0)
     rc = _loadgen.bf_loadgen_replay(server.handle, reqs.ctypes.data, t_off.ctypes.data,
                                    reqs.shape[0], done.ctypes.data, int(progress_every),
-                                   int(stall_ms), label.encode())
+                                   int(stall_ms), label.encode(), ctypes.byref(submit_ns))
     _check(rc, "bf_loadgen_replay")
+    if with_submit_ns:
+        return done, int(rc), int(submit_ns.value)
     return done, int(rc)
 
 

@@ -557,6 +557,11 @@ static bf_status ensure_slot(StagingSlot &s, size_t bytes)
     s.cap = 0;
     if (hipHostMalloc(&s.host, cap, hipHostMallocDefault) != hipSuccess)
         return bf_fail(BF_ERR_OOM, "pinned staging of %zu bytes", cap);
+    if (hipHostGetDevicePointer(&s.host_dev, s.host, 0) != hipSuccess) {
+        (void)hipHostFree(s.host);
+        s.host = nullptr;
+        return bf_fail(BF_ERR_DEVICE, "device address of pinned staging");
+    }
     if (hipMalloc(&s.dev, cap) != hipSuccess) {
         (void)hipHostFree(s.host);
         s.host = nullptr;
@@ -574,7 +579,8 @@ bf_status reserve_staging(bf_plan p, int n)
     if (p->ring.empty())
         p->ring.resize(kRingSlots);
     for (StagingSlot &slot : p->ring) {
-        bf_status s = ensure_slot(slot, block_bytes(n));
+        // (a serving launch of n items has at most n request records)
+        bf_status s = ensure_slot(slot, block_bytes(n) + (size_t)n * sizeof(BfReqRec));
         if (s != BF_OK)
             return s;
     }
@@ -634,6 +640,95 @@ static bf_status upload_and_launch(bf_plan p, bf_prec prec, int n, const FillSta
             return bf_fail(BF_ERR_DEVICE, "update ordering: %s", hipGetErrorString(e));
     }
     e = launch_for_plan(p, cfg, static_cast<BfHeader *>(dev_blk), n, st);
+    if (e != hipSuccess)
+        return bf_fail(BF_ERR_DEVICE, "kernel launch: %s", hipGetErrorString(e));
+    e = hipEventRecord(slot.ev, st);
+    if (e != hipSuccess)
+        return bf_fail(BF_ERR_DEVICE, "hipEventRecord: %s", hipGetErrorString(e));
+    slot.launched = true;
+    return BF_OK;
+}
+
+// Record-level form of order_items (mode 1: by W id, then f descending;
+// mode 2: grouped by W id modulo 8).  Every item of a record shares its W id
+// and f, so the items come out in the order order_items gives them.
+static void order_records(std::vector<BfReqRec> &recs, std::vector<BfReqRec> &tmp, int mode)
+{
+    const size_t n = recs.size();
+    tmp.resize(n);
+    if (mode == 2) {
+        constexpr int kGroups = 8;
+        size_t cnt[kGroups + 1] = {0};
+        for (const BfReqRec &q : recs)
+            cnt[q.w_id % kGroups + 1]++;
+        for (int g = 0; g < kGroups; ++g)
+            cnt[g + 1] += cnt[g];
+        for (const BfReqRec &q : recs)
+            tmp[cnt[q.w_id % kGroups]++] = q;
+        recs.swap(tmp);
+        return;
+    }
+    std::stable_sort(recs.begin(), recs.end(), [](const BfReqRec &a, const BfReqRec &b) {
+        return a.f != b.f ? a.f > b.f : a.w_id < b.w_id;
+    });
+}
+
+bf_status enqueue_requests(bf_plan p, bf_prec prec, std::vector<BfReqRec> &recs, int n_items,
+                           hipStream_t st)
+{
+    const int n_recs = (int)recs.size();
+    if (n_items == 0)
+        return BF_OK;
+    FillStats fs{0, true, 0};
+    for (const BfReqRec &q : recs) {
+        fs.max_f = std::max(fs.max_f, (int)q.f);
+        fs.min_f = std::min(fs.min_f, (int)q.f);
+        fs.sum_f += (int64_t)q.f * q.n_s;
+        // (block k starts k f 480 bytes after S, a multiple of 16)
+        if (q.f > 0 && !aligned16(q.S))
+            fs.vec16 = false;
+    }
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (p->ring.empty())
+        p->ring.resize(kRingSlots);
+    StagingSlot &slot = p->ring[p->ring_next];
+    p->ring_next = (p->ring_next + 1) % p->ring.size();
+    const size_t rec_off = block_bytes(n_items);
+    bf_status s = ensure_slot(slot, rec_off + (size_t)n_recs * sizeof(BfReqRec));
+    if (s != BF_OK)
+        return s;
+    bf_variant chosen = p->table[prec][batch_bucket(fs.sum_f, n_items)];
+    if (chosen.order >= 1 && n_recs > 1)
+        order_records(recs, p->rec_tmp, chosen.order);
+    bfk::LaunchCfg cfg = choose_launch(p, prec, n_items, fs.max_f, fs.vec16, fs.min_f == fs.max_f, &chosen);
+    cfg.ev_start = p->kev_start;
+    cfg.ev_stop = p->kev_stop;
+    BfReqRec *dst = reinterpret_cast<BfReqRec *>(static_cast<char *>(slot.host) + rec_off);
+    int item0 = 0;
+    for (int k = 0; k < n_recs; ++k) {
+        dst[k] = recs[(size_t)k];
+        dst[k].item0 = item0;
+        item0 += recs[(size_t)k].n_s;
+        if (p->any_update)   // the slot of the entry current now (see map_slots)
+            dst[k].w_id += p->n_w * (int)p->half[(size_t)dst[k].w_id];
+    }
+    if (item0 != n_items)
+        return bf_fail(BF_ERR_INVALID, "request records hold %d items, not %d", item0, n_items);
+    // The expansion kernel reads the records straight from pinned host
+    // memory (a few kilobytes: one request is 32 bytes however many S blocks
+    // it has), so nothing is uploaded and the launch waits on no other
+    // queue; the slot is not written again before slot.ev (after the apply
+    // kernel) has completed.
+    char *dev_blk = static_cast<char *>(slot.dev);
+    hipError_t e = hipSuccess;
+    if (p->any_update)
+        e = hipStreamWaitEvent(st, p->updated, 0);
+    if (e != hipSuccess)
+        return bf_fail(BF_ERR_DEVICE, "update ordering: %s", hipGetErrorString(e));
+    e = bfk::launch_expand(reinterpret_cast<const BfReqRec *>(static_cast<char *>(slot.host_dev) + rec_off),
+                           n_recs, reinterpret_cast<BfHeader *>(dev_blk), n_items, st);
+    if (e == hipSuccess)
+        e = launch_for_plan(p, cfg, reinterpret_cast<BfHeader *>(dev_blk), n_items, st);
     if (e != hipSuccess)
         return bf_fail(BF_ERR_DEVICE, "kernel launch: %s", hipGetErrorString(e));
     e = hipEventRecord(slot.ev, st);

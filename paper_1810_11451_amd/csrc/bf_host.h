@@ -26,6 +26,7 @@ constexpr uint32_t kSupportedMask = BF_PREC_ALL;
 // an event recorded on the caller's stream after the launch that reads it.
 struct StagingSlot {
     void *host = nullptr;
+    void *host_dev = nullptr;   // host's device-side address (kernels read records there)
     void *dev = nullptr;
     size_t cap = 0;
     hipEvent_t copied = nullptr;
@@ -78,6 +79,7 @@ struct bf_plan_s {
     bf_variant table[kPrecCount][kBucketCount];
     float tuned_us[kPrecCount][kBucketCount] = {};   // measured by autotune or loaded; 0: default
     std::vector<BfItem> sort_tmp;
+    std::vector<BfReqRec> rec_tmp;
     std::vector<int> sort_scratch;
 };
 
@@ -95,6 +97,14 @@ void order_items(const BfItem *in, BfItem *out, int n, int n_w, std::vector<int>
 bfk::LaunchCfg choose_launch(bf_plan p, bf_prec prec, int n, int max_f, bool vec16,
                              bool uniform_f, const bf_variant *force);
 bf_status reserve_staging(bf_plan p, int n);
+// Serving launches: one record per request (S, R, w_id, f, n_s; item0 is
+// set here), n_items the sum of their n_s.  The records are put in the
+// product order of the plan's variant for the batch (in place), written to
+// pinned staging and expanded into items on the device ahead of the apply
+// kernel, so the host's work grows with the requests, not with their S
+// blocks.
+bf_status enqueue_requests(bf_plan p, bf_prec prec, std::vector<BfReqRec> &recs, int n_items,
+                           hipStream_t st);
 bf_status enqueue_items(bf_plan p, bf_prec prec, int n, const FillFn &fill, hipStream_t st,
                         const bf_variant *force, int *grid_out);
 hipError_t launch_for_plan(bf_plan p, const bfk::LaunchCfg &cfg, BfHeader *blk, int n,

@@ -33,6 +33,21 @@ struct BfHeader {
 constexpr size_t kSinkBytes = 8192;
 inline size_t block_bytes(int n_items) { return 64 + kSinkBytes + (size_t)n_items * 32; }
 static_assert(sizeof(BfItem) == 32, "BfItem layout");
+
+// One request of a serving launch, as uploaded (32 bytes): n_s S blocks of
+// one W and f, block k reading S + k f 60 and writing R + k 64 60 complex
+// elements, which become items item0 .. item0 + n_s - 1 of the launch's
+// descriptor block.  The device expands them (launch_expand), so the host
+// packs one record per request instead of one item per block.
+struct BfReqRec {
+    const float2 *S;   // first S block (null when f = 0)
+    float2 *R;         // first R block
+    int32_t w_id;
+    int32_t f;
+    int32_t n_s;
+    int32_t item0;
+};
+static_assert(sizeof(BfReqRec) == 32, "BfReqRec layout");
 static_assert(sizeof(BfHeader) == 64, "BfHeader layout");
 
 namespace bfk {
@@ -111,6 +126,10 @@ struct LaunchCfg {
 
 hipError_t launch_apply(const LaunchCfg &cfg, BfHeader *blk, int n_items, const PlanDev &pd,
                         hipStream_t st);
+
+// Writes the header and the n_items items of descriptor block blk from
+// n_recs request records (their item ranges tile 0 .. n_items - 1).
+hipError_t launch_expand(const BfReqRec *recs, int n_recs, BfHeader *blk, int n_items, hipStream_t st);
 
 // Workgroups of the apply kernel that fit on one CU at once.
 int apply_occupancy(int prec, int schedule, bool vec16, bool stage);

@@ -2539,6 +2539,45 @@ hipError_t launch_apply(const LaunchCfg &cfg, BfHeader *blk, int n_items, const 
     return hipErrorNotSupported;
 }
 
+// Expansion of serving requests into items: wave r writes the items of
+// record r, lane k (and k + 64, ...) block k; thread 0 of the grid writes
+// the header.  The counters start at zero for the apply kernel that
+// follows on the same stream.
+__global__ void __launch_bounds__(256) expand_requests_kernel(const BfReqRec *recs, int n_recs, BfHeader *blk,
+                                                              BfItem *items, int n_items)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        blk->next = 0;
+        blk->done = 0;
+        blk->n_items = (uint32_t)n_items;
+    }
+    const int r = (int)((blockIdx.x * blockDim.x + threadIdx.x) / 64);
+    if (r >= n_recs)
+        return;
+    const int lane = threadIdx.x & 63;
+    const BfReqRec q = recs[r];
+    for (int k = lane; k < q.n_s; k += 64) {
+        BfItem d;
+        d.S = q.f > 0 ? q.S + (size_t)k * q.f * kB : nullptr;
+        d.R = q.R + (size_t)k * kM * kB;
+        d.w_id = q.w_id;
+        d.f = q.f;
+        d.pad0 = 0;
+        d.pad1 = 0;
+        items[q.item0 + k] = d;
+    }
+}
+
+hipError_t launch_expand(const BfReqRec *recs, int n_recs, BfHeader *blk, int n_items, hipStream_t st)
+{
+    if (n_recs <= 0)
+        return hipSuccess;
+    const int grid = (n_recs + 3) / 4;   // four records (waves) per workgroup
+    hipLaunchKernelGGL(expand_requests_kernel, dim3(grid), dim3(256), 0, st, recs, n_recs, blk,
+                       const_cast<BfItem *>(items_of(blk)), n_items);
+    return hipGetLastError();
+}
+
 template <typename K>
 static int occ_of(K kernel, int threads = kThreads)
 {

@@ -61,6 +61,7 @@ struct Server {
     // Batcher state (batcher thread only).
     std::deque<Req> pending;         // popped from the ring, not yet admitted
     std::deque<Req> admitted;        // admitted, not yet launched
+    int64_t admitted_items = 0;      // S blocks of `admitted`
     int rr = 0;
 
     // Launches in flight, one FIFO per stream.
@@ -89,8 +90,9 @@ struct Server {
     std::atomic<double> rate{0.0};
 
     // Statistics.
-    std::atomic<uint64_t> submitted{0}, n_admitted{0}, completed{0}, refused{0}, launches{0},
-        misses{0}, peak_bytes{0};
+    // (submitted requests are counted by head)
+    std::atomic<uint64_t> n_admitted{0}, completed{0}, refused{0}, launches{0}, misses{0},
+        peak_bytes{0}, launch_host_ns{0};
 
     std::thread batcher, completer;
 };
@@ -155,9 +157,11 @@ void launch_front(Server *s, size_t count, int stream_idx)
         L->reqs.push_back(q);
         s->admitted.pop_front();
     }
+    s->admitted_items -= items;
     L->t_launch = s->dev->now_ns();
     const bf_status rc = s->dev->launch(stream_idx, L->reqs, items, &L->token);
     s->launches.fetch_add(1);
+    s->launch_host_ns.fetch_add((uint64_t)std::max<int64_t>(0, s->dev->now_ns() - L->t_launch));
     if (rc != BF_OK) {
         // Nothing reached the device: report the requests as failed now.
         L->status = rc;
@@ -173,14 +177,22 @@ void launch_front(Server *s, size_t count, int stream_idx)
     s->n_inflight.fetch_add(1);
 }
 
-int free_stream(Server *s)
+// A stream with no launch in flight, else (with `deep`) one with a single
+// launch in flight; -1 if none.  Under load (deep: the admitted work fills
+// at least half a launch) the next launch is then packed and queued behind
+// the running one, so the device does not wait for the host between the
+// two; otherwise work waits for a free stream and gathers into larger
+// launches.
+int free_stream(Server *s, bool deep)
 {
     std::lock_guard<std::mutex> lk(s->fl_mu);
-    for (int k = 0; k < s->cfg.n_streams; ++k) {
-        const int i = (s->rr + k) % s->cfg.n_streams;
-        if (s->inflight[i].empty()) {
-            s->rr = (i + 1) % s->cfg.n_streams;
-            return i;
+    for (size_t depth = 1; depth <= (deep ? 2u : 1u); ++depth) {
+        for (int k = 0; k < s->cfg.n_streams; ++k) {
+            const int i = (s->rr + k) % s->cfg.n_streams;
+            if (s->inflight[i].size() < depth) {
+                s->rr = (i + 1) % s->cfg.n_streams;
+                return i;
+            }
         }
     }
     return -1;
@@ -199,25 +211,35 @@ void batcher_loop(Server *s)
         }
         s->tail.store(t, std::memory_order_release);
 
-        // 2. Admit in arrival order while the budget allows.
-        while (!s->pending.empty()) {
-            const Req &q = s->pending.front();
+        // 2. Admit in arrival order while the budget allows.  (The bytes in
+        // flight only fall behind the batcher's back, so one reading of
+        // them bounds the whole pass; the counters move once per pass.)
+        if (!s->pending.empty()) {
             const uint64_t in_use = s->inflight_bytes.load();
-            if (in_use + q.bytes > s->cfg.hbm_budget_bytes)
-                break;
-            s->inflight_bytes.fetch_add(q.bytes);
-            s->admitted.push_back(q);
-            s->pending.pop_front();
-            s->n_admitted.fetch_add(1);
-            progress = true;
-            uint64_t now_b = s->inflight_bytes.load(), peak = s->peak_bytes.load();
-            while (now_b > peak && !s->peak_bytes.compare_exchange_weak(peak, now_b)) {
+            uint64_t add = 0, n_add = 0;
+            while (!s->pending.empty()) {
+                const Req &q = s->pending.front();
+                if (in_use + add + q.bytes > s->cfg.hbm_budget_bytes)
+                    break;
+                add += q.bytes;
+                ++n_add;
+                s->admitted_items += q.r.n_s;
+                s->admitted.push_back(q);
+                s->pending.pop_front();
+            }
+            if (n_add > 0) {
+                const uint64_t now_b = s->inflight_bytes.fetch_add(add) + add;
+                s->n_admitted.fetch_add(n_add);
+                uint64_t peak = s->peak_bytes.load();
+                while (now_b > peak && !s->peak_bytes.compare_exchange_weak(peak, now_b)) {
+                }
+                progress = true;
             }
         }
 
         // 3. Launch admitted work on free streams.
         while (!s->admitted.empty()) {
-            const int si = free_stream(s);
+            const int si = free_stream(s, 2 * s->admitted_items >= s->cfg.max_batch_items);
             if (si < 0)
                 break;
             size_t count = 0;
@@ -251,7 +273,16 @@ void batcher_loop(Server *s)
         if (s->stopping.load() && s->head.load() == s->tail.load() && s->pending.empty() &&
             s->admitted.empty())
             break;
-        // 4. Nothing to do: sleep until a submission, a completion or 50 us.
+        // 4. Nothing to do now.  While requests wait for launches in flight
+        // (for a stream or for budget), the next event is a completion:
+        // poll for it, so the stream or budget it frees is used at once (a
+        // sleeping thread is woken tens to hundreds of microseconds after
+        // the notification).  Otherwise sleep until a submission, a
+        // completion or 50 us.
+        if ((!s->admitted.empty() || !s->pending.empty()) && s->n_inflight.load() > 0) {
+            std::this_thread::yield();
+            continue;
+        }
         std::unique_lock<std::mutex> lk(s->wake_mu);
         // (sequentially consistent flag and head accesses on both sides, so a
         // submission either sees the flag or is seen here)
@@ -363,44 +394,86 @@ bf_status server_create(Server **out, Device *dev, const bf_server_cfg &cfg, int
     return BF_OK;
 }
 
+namespace {
+
+// The checks of one request (index names it in the message of a batch).
+bf_status check_request(const Server *s, const bf_request &r, int index)
+{
+    if (r.w_id < 0 || r.w_id >= s->n_w)
+        return bf_fail(BF_ERR_INVALID, "request %d: w_id %d outside [0, %d)", index, r.w_id, s->n_w);
+    if (r.f < 0 || r.f > s->f_max)
+        return bf_fail(BF_ERR_INVALID, "request %d: f %d outside [0, %d]", index, r.f, s->f_max);
+    if (r.n_s < 1 || r.n_s > s->cfg.max_batch_items)
+        return bf_fail(BF_ERR_INVALID, "request %d: n_s %d outside [1, %d]", index, r.n_s,
+                       s->cfg.max_batch_items);
+    if (!r.R || (reinterpret_cast<uintptr_t>(r.R) & 15u))
+        return bf_fail(BF_ERR_INVALID, "request %d: R null or not 16-byte aligned", index);
+    if (r.f > 0 && (!r.S || (reinterpret_cast<uintptr_t>(r.S) & 7u)))
+        return bf_fail(BF_ERR_INVALID, "request %d: S null or not 8-byte aligned", index);
+    if (request_bytes(r) > s->cfg.hbm_budget_bytes)
+        return bf_fail(BF_ERR_INVALID, "request %d of %llu bytes exceeds the whole budget", index,
+                       (unsigned long long)request_bytes(r));
+    return BF_OK;
+}
+
+// Writes reqs[0 .. n) into the ring from head h on and publishes them.
+void publish(Server *s, const bf_request *reqs, int n, uint64_t h, uint64_t *first_ticket)
+{
+    const int64_t now = s->dev->now_ns();
+    if (first_ticket)
+        *first_ticket = s->next_ticket;
+    for (int i = 0; i < n; ++i) {
+        Req &slot = s->ring[(h + (uint64_t)i) & s->mask];
+        slot.r = reqs[i];
+        slot.ticket = s->next_ticket++;
+        slot.t_submit = now;
+        slot.t_arrival = reqs[i].t_arrival_ns > 0 ? reqs[i].t_arrival_ns : now;
+        slot.bytes = request_bytes(reqs[i]);
+    }
+    // (sequentially consistent, against the batcher's sleeping flag)
+    s->head.store(h + (uint64_t)n);
+    wake_batcher(s);
+}
+
+}  // namespace
+
 bf_status server_submit(Server *s, const bf_request *req, uint64_t *ticket)
 {
     if (!s || !req)
         return bf_fail(BF_ERR_INVALID, "null argument");
-    if (s->stopping.load())
+    if (s->stopping.load(std::memory_order_relaxed))
         return bf_fail(BF_ERR_INVALID, "server is shutting down");
-    const bf_request &r = *req;
-    if (r.w_id < 0 || r.w_id >= s->n_w)
-        return bf_fail(BF_ERR_INVALID, "w_id %d outside [0, %d)", r.w_id, s->n_w);
-    if (r.f < 0 || r.f > s->f_max)
-        return bf_fail(BF_ERR_INVALID, "f %d outside [0, %d]", r.f, s->f_max);
-    if (r.n_s < 1 || r.n_s > s->cfg.max_batch_items)
-        return bf_fail(BF_ERR_INVALID, "n_s %d outside [1, %d]", r.n_s, s->cfg.max_batch_items);
-    if (!r.R || (reinterpret_cast<uintptr_t>(r.R) & 15u))
-        return bf_fail(BF_ERR_INVALID, "R null or not 16-byte aligned");
-    if (r.f > 0 && (!r.S || (reinterpret_cast<uintptr_t>(r.S) & 7u)))
-        return bf_fail(BF_ERR_INVALID, "S null or not 8-byte aligned");
-    const uint64_t bytes = request_bytes(r);
-    if (bytes > s->cfg.hbm_budget_bytes)
-        return bf_fail(BF_ERR_INVALID, "request of %llu bytes exceeds the whole budget",
-                       (unsigned long long)bytes);
+    const bf_status rc = check_request(s, *req, 0);
+    if (rc != BF_OK)
+        return rc;
     const uint64_t h = s->head.load(std::memory_order_relaxed);
     if (h - s->tail.load(std::memory_order_acquire) >= s->ring.size()) {
         s->refused.fetch_add(1);
         return bf_fail(BF_ERR_BUSY, "submission queue full");
     }
-    Req &slot = s->ring[h & s->mask];
-    slot.r = r;
-    slot.ticket = s->next_ticket++;
-    slot.t_submit = s->dev->now_ns();
-    slot.t_arrival = r.t_arrival_ns > 0 ? r.t_arrival_ns : slot.t_submit;
-    slot.bytes = bytes;
-    s->head.store(h + 1);
-    s->submitted.fetch_add(1);
-    wake_batcher(s);
-    if (ticket)
-        *ticket = slot.ticket;
+    publish(s, req, 1, h, ticket);
     return BF_OK;
+}
+
+int32_t server_submit_batch(Server *s, const bf_request *reqs, int32_t n, uint64_t *first_ticket)
+{
+    if (!s || n < 0 || (n > 0 && !reqs))
+        return bf_fail(BF_ERR_INVALID, "bad bf_submit_batch arguments");
+    if (s->stopping.load(std::memory_order_relaxed))
+        return bf_fail(BF_ERR_INVALID, "server is shutting down");
+    for (int32_t i = 0; i < n; ++i) {
+        const bf_status rc = check_request(s, reqs[i], i);
+        if (rc != BF_OK)
+            return rc;
+    }
+    const uint64_t h = s->head.load(std::memory_order_relaxed);
+    const uint64_t room = s->ring.size() - (h - s->tail.load(std::memory_order_acquire));
+    const int32_t take = (int32_t)std::min<uint64_t>(room, (uint64_t)n);
+    if (take < n)
+        s->refused.fetch_add(1);
+    if (take > 0)
+        publish(s, reqs, take, h, first_ticket);
+    return take;
 }
 
 int32_t server_poll(Server *s, bf_completion *out, int32_t max, int64_t timeout_us)
@@ -429,7 +502,7 @@ bf_status server_stats(Server *s, bf_server_stats *o)
 {
     if (!s || !o)
         return bf_fail(BF_ERR_INVALID, "null argument");
-    o->submitted = s->submitted.load();
+    o->submitted = s->head.load();
     o->admitted = s->n_admitted.load();
     o->completed = s->completed.load();
     o->refused = s->refused.load();
@@ -438,6 +511,7 @@ bf_status server_stats(Server *s, bf_server_stats *o)
     o->inflight_bytes = s->inflight_bytes.load();
     o->peak_inflight_bytes = s->peak_bytes.load();
     o->queued = s->head.load() - s->tail.load();
+    o->launch_host_ns = s->launch_host_ns.load();
     return BF_OK;
 }
 

@@ -70,6 +70,10 @@ struct Server;
 // outlive the server.
 bf_status server_create(Server **out, Device *dev, const bf_server_cfg &cfg, int n_w, int f_max);
 bf_status server_submit(Server *s, const bf_request *req, uint64_t *ticket);
+// Checks all n requests (nothing is queued if one fails), then queues as
+// many as the ring has room for, in order, with consecutive tickets from
+// *first_ticket; returns that count (0 .. n) or a bf_status.
+int32_t server_submit_batch(Server *s, const bf_request *reqs, int32_t n, uint64_t *first_ticket);
 int32_t server_poll(Server *s, bf_completion *out, int32_t max, int64_t timeout_us);
 bf_status server_stats(Server *s, bf_server_stats *out);
 // Drains every submitted request, joins the threads and frees the server

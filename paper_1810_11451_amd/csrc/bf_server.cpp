@@ -58,28 +58,13 @@ public:
             if (e != hipSuccess)
                 return bf_fail(BF_ERR_DEVICE, "hipEventCreate: %s", hipGetErrorString(e));
         }
-        FillFn fill = [&](BfItem *it) {
-            FillStats fs{0, true, 0};
-            int t = 0;
-            bfs::for_each_block(reqs, [&](const void *S, void *R, int32_t w_id, int32_t f) {
-                it[t].S = static_cast<const float2 *>(S);
-                it[t].R = static_cast<float2 *>(R);
-                it[t].w_id = w_id;
-                it[t].f = f;
-                it[t].pad0 = it[t].pad1 = 0;
-                if (f > 0 && (reinterpret_cast<uintptr_t>(S) & 15u))
-                    fs.vec16 = false;
-                ++t;
-            });
-            for (const bfs::Req &q : reqs) {
-                fs.max_f = std::max(fs.max_f, (int)q.r.f);
-                fs.min_f = std::min(fs.min_f, (int)q.r.f);
-                fs.sum_f += (int64_t)q.r.f * q.r.n_s;
-            }
-            return fs;
-        };
+        // One record per request; the device expands them into items.
+        recs_.clear();
+        for (const bfs::Req &q : reqs)
+            recs_.push_back(BfReqRec{static_cast<const float2 *>(q.r.f > 0 ? q.r.S : nullptr),
+                                     static_cast<float2 *>(q.r.R), q.r.w_id, q.r.f, q.r.n_s, 0});
         const hipStream_t st = streams_[stream];
-        bf_status rc = enqueue_items(plan_, prec_, n_items, fill, st, nullptr, nullptr);
+        bf_status rc = enqueue_requests(plan_, prec_, recs_, n_items, st);
         if (rc == BF_OK) {
             const hipError_t e = hipEventRecord(ev, st);
             if (e != hipSuccess)
@@ -114,6 +99,7 @@ private:
     int n_streams_ = 0;
     std::mutex mu_;                   // guards spare_ (launch and release run on different threads)
     std::vector<hipEvent_t> spare_;
+    std::vector<BfReqRec> recs_;      // batcher thread only
 };
 
 }  // namespace
@@ -168,6 +154,13 @@ extern "C" bf_status bf_submit(bf_server s, const bf_request *req, uint64_t *tic
     if (!s)
         return bf_fail(BF_ERR_INVALID, "null argument");
     return bfs::server_submit(s->core, req, ticket);
+}
+
+extern "C" int32_t bf_submit_batch(bf_server s, const bf_request *reqs, int32_t n, uint64_t *first_ticket)
+{
+    if (!s)
+        return bf_fail(BF_ERR_INVALID, "null argument");
+    return bfs::server_submit_batch(s->core, reqs, n, first_ticket);
 }
 
 extern "C" int32_t bf_poll(bf_server s, bf_completion *out, int32_t max, int64_t timeout_us)

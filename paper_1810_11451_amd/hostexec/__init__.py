@@ -45,6 +45,7 @@ _SIGS = {
     "bfh_device_peak_unfinished": (_i32, [_vp]),
     "bfh_server_create": (_i32, [ctypes.POINTER(_vp), _vp, ctypes.POINTER(bf.bf_server_cfg), _i32, _i32]),
     "bfh_submit": (_i32, [_vp, _vp, ctypes.POINTER(ctypes.c_uint64)]),
+    "bfh_submit_batch": (_i32, [_vp, _vp, _i32, ctypes.POINTER(ctypes.c_uint64)]),
     "bfh_poll": (_i32, [_vp, _vp, _i32, _i64]),
     "bfh_server_stats_get": (_i32, [_vp, ctypes.POINTER(bf.bf_server_stats)]),
     "bfh_server_destroy": (_i32, [_vp]),
@@ -152,6 +153,14 @@ class Server:
         t = ctypes.c_uint64()
         _check(lib().bfh_submit(self.handle, req.ctypes.data, ctypes.byref(t)), "bfh_submit")
         return int(t.value)
+
+    def submit_batch(self, reqs) -> tuple:
+        """Returns (requests queued, first ticket)."""
+        reqs = np.ascontiguousarray(reqs, dtype=bf.REQUEST_DTYPE)
+        t = ctypes.c_uint64()
+        rc = lib().bfh_submit_batch(self.handle, reqs.ctypes.data, int(reqs.shape[0]), ctypes.byref(t))
+        _check(rc, "bfh_submit_batch")
+        return int(rc), int(t.value)
 
     def poll(self, max_n: int = 1024, timeout_us: int = 0) -> np.ndarray:
         out = np.zeros(max_n, bf.COMPLETION_DTYPE)

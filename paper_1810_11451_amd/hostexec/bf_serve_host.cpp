@@ -292,6 +292,13 @@ extern "C" bf_status bfh_submit(bfh_server s, const bf_request *req, uint64_t *t
     return bfs::server_submit(s->core, req, ticket);
 }
 
+extern "C" int32_t bfh_submit_batch(bfh_server s, const bf_request *reqs, int32_t n, uint64_t *first_ticket)
+{
+    if (!s)
+        return bf_fail(BF_ERR_INVALID, "null argument");
+    return bfs::server_submit_batch(s->core, reqs, n, first_ticket);
+}
+
 extern "C" int32_t bfh_poll(bfh_server s, bf_completion *out, int32_t max, int64_t timeout_us)
 {
     if (!s)

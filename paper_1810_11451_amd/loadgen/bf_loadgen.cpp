@@ -21,10 +21,14 @@ extern "C" {
  *   stall_ms        > 0: give up when requests are outstanding and no
  *                   completion has arrived for that long; returns
  *                   BF_ERR_TIMEOUT (the server still holds the requests)
+ *   submit_ns       if not null: the nanoseconds spent inside bf_submit and
+ *                   bf_submit_batch calls (accepted and refused), summed
+ * Requests with equal offsets are submitted together (bf_submit_batch,
+ * up to 4096 a call), others one by one (bf_submit).
  * Returns the number of BF_ERR_BUSY retries (>= 0), or a bf_status. */
 int64_t bf_loadgen_replay(bf_server s, bf_request *reqs, const int64_t *t_offset_ns, int64_t n,
                           bf_completion *done, int64_t progress_every, int64_t stall_ms,
-                          const char *label)
+                          const char *label, int64_t *submit_ns)
 {
     if (!s || (n > 0 && (!reqs || !t_offset_ns || !done)) || n < 0)
         return BF_ERR_INVALID;
@@ -77,26 +81,40 @@ int64_t bf_loadgen_replay(bf_server s, bf_request *reqs, const int64_t *t_offset
     });
     const int64_t t0 = bf_now_ns() + 1000000;   // start 1 ms from now
     int64_t busy = 0;
+    int64_t in_submit = 0;
     int rc = BF_OK;
-    for (int64_t i = 0; i < n && rc == BF_OK && !stop.load(); ++i) {
+    // Requests due at the same time go to the server in one bf_submit_batch
+    // call (up to 4096 at a time), others one by one.
+    constexpr int64_t kChunk = 4096;
+    for (int64_t i = 0; i < n && rc == BF_OK && !stop.load();) {
         const int64_t when = t0 + t_offset_ns[i];
+        int64_t j = i + 1;
+        while (j < n && j - i < kChunk && t_offset_ns[j] == t_offset_ns[i])
+            ++j;
         while (bf_now_ns() < when) {
         }
-        reqs[i].tag = (uint64_t)i;
-        reqs[i].t_arrival_ns = when;
-        for (;;) {
-            const bf_status st = bf_submit(s, &reqs[i], nullptr);
-            if (st == BF_OK) {
-                submitted.fetch_add(1);
+        for (int64_t k = i; k < j; ++k) {
+            reqs[k].tag = (uint64_t)k;
+            reqs[k].t_arrival_ns = when;
+        }
+        while (i < j && rc == BF_OK && !stop.load()) {
+            const int64_t ts = bf_now_ns();
+            int32_t got;
+            if (j - i == 1) {
+                const bf_status st = bf_submit(s, &reqs[i], nullptr);
+                got = st == BF_OK ? 1 : (st == BF_ERR_BUSY ? 0 : st);
+            } else {
+                got = bf_submit_batch(s, &reqs[i], (int32_t)(j - i), nullptr);
+            }
+            in_submit += bf_now_ns() - ts;
+            if (got < 0) {
+                rc = got;
                 break;
             }
-            if (st != BF_ERR_BUSY) {
-                rc = st;
-                break;
-            }
-            if (stop.load())
-                break;
-            ++busy;
+            if (got == 0)
+                ++busy;
+            i += got;
+            submitted.fetch_add(got);
         }
     }
     if (rc != BF_OK) {
@@ -104,6 +122,8 @@ int64_t bf_loadgen_replay(bf_server s, bf_request *reqs, const int64_t *t_offset
         stop.store(true);
     }
     poller.join();
+    if (submit_ns)
+        *submit_ns = in_submit;
     if (rc != BF_OK)
         return rc;
     if (poll_error.load() != 0)

@@ -54,6 +54,7 @@ struct Scenario {
     int64_t deadline_us;
     bool marks;               // distinct R per request, marks checked by the poller
     std::vector<int64_t> fail_at;
+    int batch = 1;            // requests per submit call (> 1: bfh_submit_batch)
 };
 
 int run(const Scenario &sc)
@@ -179,14 +180,31 @@ int run(const Scenario &sc)
     });
 
     int busy = 0;
-    for (int i = 0; i < sc.n_req; ++i) {
-        for (;;) {
-            const bf_status rc = bfh_submit(srv, &reqs[(size_t)i], nullptr);
-            if (rc == BF_OK)
-                break;
-            CHECK(rc == BF_ERR_BUSY, "submit %d: %s", i, bf_last_error());
-            ++busy;
-            std::this_thread::yield();
+    uint64_t next_ticket = 1;
+    for (int i = 0; i < sc.n_req;) {
+        if (sc.batch > 1) {
+            const int want = std::min(uniform(1, sc.batch), sc.n_req - i);
+            uint64_t first = 0;
+            const int32_t got = bfh_submit_batch(srv, &reqs[(size_t)i], want, &first);
+            CHECK(got >= 0 && got <= want, "batch at %d: %d (%s)", i, got, bf_last_error());
+            if (got == 0) {
+                ++busy;
+                std::this_thread::yield();
+                continue;
+            }
+            CHECK(first == next_ticket, "tickets not consecutive at %d", i);
+            next_ticket += (uint64_t)got;
+            i += got;
+        } else {
+            for (;;) {
+                const bf_status rc = bfh_submit(srv, &reqs[(size_t)i], nullptr);
+                if (rc == BF_OK)
+                    break;
+                CHECK(rc == BF_ERR_BUSY, "submit %d: %s", i, bf_last_error());
+                ++busy;
+                std::this_thread::yield();
+            }
+            ++i;
         }
         if ((i & 255) == 0)
             std::this_thread::sleep_for(std::chrono::microseconds(uniform(0, 300)));
@@ -235,7 +253,9 @@ int main(int argc, char **argv)
     Scenario c{"small budget, small queue", 3000 * scale, 4, 2, 32, 8, 2 * MB, 500, false, {}};
     Scenario d{"failures", 2000 * scale, 8, 2, 64, 512, 32 * MB, 0, false, {3, 10, 11, 40}};
     Scenario e{"one stream, one item", 1000 * scale, 1, 1, 1, 64, 8 * MB, 200, true, {}};
-    for (const Scenario *s : {&a, &b, &c, &d, &e})
+    Scenario f{"batched submits, small queue", 4000 * scale, 16, 2, 256, 64, 64 * MB, 500, true, {}, 48};
+    Scenario g{"batched submits, failures", 2000 * scale, 8, 3, 128, 256, 16 * MB, 0, false, {2, 7}, 200};
+    for (const Scenario *s : {&a, &b, &c, &d, &e, &f, &g})
         if (run(*s) != 0)
             return 1;
     fprintf(stderr, "[stress] all scenarios ok\n");

@@ -151,7 +151,7 @@ def test_server_create_rejects_null_plan(L):
 
 def test_record_layouts_match_header():
     assert ctypes.sizeof(bf.bf_server_cfg) == 32
-    assert ctypes.sizeof(bf.bf_server_stats) == 72
+    assert ctypes.sizeof(bf.bf_server_stats) == 80
     assert bf.REQUEST_DTYPE.itemsize == 48 and bf.COMPLETION_DTYPE.itemsize == 56
 
 

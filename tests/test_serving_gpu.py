@@ -94,6 +94,39 @@ def test_serve_matches_oracle():
     plan.close()
 
 
+@pytest.mark.parametrize("prec,variant", [(bf.BF_FP32, (0, 0, 1, 1)), (bf.BF_FP32, (2, 0, 0)),
+                                          (bf.BF_FP32, (1, 0, 2)), (bf.BF_FP32_3M, (0, 0, 2, 1)),
+                                          (bf.BF_FP32_3M, (3, 0, 1, 7))],
+                         ids=["fp32-single-byw", "fp32-stream-asgiven", "fp32-claim-xcd",
+                              "fp32_3m-single-xcd", "fp32_3m-ws16-byw"])
+def test_serve_under_each_product_order(prec, variant):
+    """Requests expand into items on the device in the order the variant
+    asks for (as given, by W id then f, grouped by W id modulo 8); n_s up
+    to 70 takes a record past one wave's 64 lanes.  Every request against
+    the oracle."""
+    torch = require_gpu()
+    rng = np.random.default_rng(703)
+    W = wl.unit_norm_pool(rng, 24, 36)
+    shapes = _shapes(rng, 40, 24, max_ns=70)
+    ar = Arena(torch, rng, shapes, 24)
+    plan = bf.bf_plan_create(W, bf.BF_PREC_BIT(prec))
+    for bk in range(5):
+        bf.bf_set_variant(plan, prec, bk, *variant)
+    announce(f"serve 40 requests prec={bf.PREC_NAMES[prec]} variant={variant}")
+    with bf.bf_server_create(plan, n_streams=2, prec=prec) as srv:
+        for i in range(len(shapes)):
+            bf.bf_submit(srv, ar.request(i))
+        done = _drain(srv, len(shapes))
+        assert np.all(done["status"] == bf.BF_OK)
+    for i, (w, f, n) in enumerate(shapes):
+        got = ar.result(i)
+        if f == 0:
+            assert np.all(got == 0)
+        else:
+            assert np.max(orc.rel_frobenius(got, ar.reference(W, i))) <= FP32_TOL, f"request {i}"
+    plan.close()
+
+
 @pytest.mark.parametrize("prec", [bf.BF_FP32, bf.BF_FP16X2])
 def test_alone_equals_in_mix(prec):
     torch = require_gpu()
