@@ -208,9 +208,13 @@ bf_status bf_graph_destroy(bf_graph graph);
  * it: work distribution (one product per workgroup, persistent workgroups
  * claiming products from an atomic counter, or persistent workgroups with
  * a static share that prefetch the next S), workgroups per CU, product
- * order, and the R store path.  bf_autotune times every candidate on the given batch and stores
- * the fastest for (prec, f bucket) in the plan; bf_apply uses it from
- * then on.  The table can be saved to and loaded from a text file. */
+ * order, and the R store path.  bf_autotune times every candidate on the
+ * given batch (the mean duration of reps launches of its kernel, from the
+ * start and end events the kernel records itself: host packing, upload and
+ * the queue's gaps are not timed) and stores the fastest for (prec, f
+ * bucket) in the plan, with that duration in microseconds (*best_us);
+ * bf_apply uses it from then on.  The table can be saved to and loaded
+ * from a text file. */
 typedef struct {
     int32_t schedule;      /* 0: one product per workgroup; 1: persistent, atomic claim;
                               2: persistent, static share per XCD, next S prefetched;

@@ -1158,12 +1158,27 @@ extern "C" bf_status bf_autotune(bf_plan p, int32_t batch, const int32_t *w_ids,
             for (int st = 0; st < (prec == BF_FP32_3M ? 8 : 6); ++st)
                 cands.push_back(bf_variant{3, 0, o, st});
 
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-        return bf_fail(BF_ERR_DEVICE, "hipEventCreate");
+    // Each timed launch records its kernel's own start and end (the plan's
+    // kernel events, set per launch), so the host's packing and upload and
+    // the queue's gaps stay out of the comparison.  The caller's events are
+    // put back afterwards.
+    std::vector<hipEvent_t> kev((size_t)2 * reps, nullptr);
+    for (hipEvent_t &e : kev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            s = bf_fail(BF_ERR_DEVICE, "hipEventCreate(autotune)");
+            break;
+        }
+    hipEvent_t saved[2];
+    {
+        std::lock_guard<std::mutex> lk(p->mu);
+        saved[0] = p->kev_start;
+        saved[1] = p->kev_stop;
+        p->kev_start = p->kev_stop = nullptr;
+    }
     float best_t = 1e30f;
     bf_variant best_v = cands[0];
-    for (const bf_variant &v : cands) {
+    for (size_t c = 0; c < cands.size() && s == BF_OK; ++c) {
+        const bf_variant &v = cands[c];
         FillFn fill = [&](BfItem *items) {
             FillStats fs{0, true, 0};
             for (int32_t t = 0; t < batch; ++t) {
@@ -1177,33 +1192,46 @@ extern "C" bf_status bf_autotune(bf_plan p, int32_t batch, const int32_t *w_ids,
             }
             return fs;
         };
-        for (int w = 0; w < 2; ++w) {
+        for (int w = 0; w < 2 && s == BF_OK; ++w)
             s = enqueue_items(p, prec, batch, fill, st, &v, nullptr);
-            if (s != BF_OK)
-                break;
+        for (int r = 0; r < reps && s == BF_OK; ++r) {
+            {
+                std::lock_guard<std::mutex> lk(p->mu);
+                p->kev_start = kev[(size_t)2 * r];
+                p->kev_stop = kev[(size_t)2 * r + 1];
+            }
+            s = enqueue_items(p, prec, batch, fill, st, &v, nullptr);
+        }
+        {
+            std::lock_guard<std::mutex> lk(p->mu);
+            p->kev_start = p->kev_stop = nullptr;
         }
         if (s != BF_OK)
             break;
-        (void)hipEventRecord(e0, st);
-        for (int r = 0; r < reps && s == BF_OK; ++r)
-            s = enqueue_items(p, prec, batch, fill, st, &v, nullptr);
-        (void)hipEventRecord(e1, st);
-        if (s != BF_OK)
-            break;
-        if (hipEventSynchronize(e1) != hipSuccess) {
-            s = bf_fail(BF_ERR_DEVICE, "hipEventSynchronize(autotune)");
+        if (hipStreamSynchronize(st) != hipSuccess) {
+            s = bf_fail(BF_ERR_DEVICE, "hipStreamSynchronize(autotune)");
             break;
         }
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        const float us = ms * 1000.f / (float)reps;
+        float total_ms = 0.f;
+        for (int r = 0; r < reps; ++r) {
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, kev[(size_t)2 * r], kev[(size_t)2 * r + 1]);
+            total_ms += ms;
+        }
+        const float us = total_ms * 1000.f / (float)reps;
         if (us < best_t) {
             best_t = us;
             best_v = v;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    {
+        std::lock_guard<std::mutex> lk(p->mu);
+        p->kev_start = saved[0];
+        p->kev_stop = saved[1];
+    }
+    for (hipEvent_t e : kev)
+        if (e)
+            (void)hipEventDestroy(e);
     if (s != BF_OK)
         return s;
     {

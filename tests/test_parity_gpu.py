@@ -277,13 +277,28 @@ def test_graph_launch_inside_a_captured_hip_graph(prec, variant):
 
 
 def test_autotune_and_cache(tmp_path):
-    require_gpu()
+    """The autotuner stores its pick (timed by the kernels' own events) and
+    puts back the caller's kernel events; the pick survives save and load."""
+    torch = require_gpu()
     b = wl.uneven_batch(n=2000)
     plan = bf.bf_plan_create(b.W)
     db = DeviceBatch(b)
+    st = torch.cuda.current_stream()
+    mine = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for e in mine:
+        e.record(st)
+    torch.cuda.synchronize()
+    bf.bf_plan_set_kernel_events(plan, mine[0], mine[1])
     announce("autotune")
     best, us = bf.bf_autotune(plan, b.w_ids, b.f, db.s_ptrs[0], db.r_ptrs[0], reps=2)
     assert us > 0
+    torch.cuda.synchronize()
+    before = mine[0].elapsed_time(mine[1])
+    db.apply(plan)                  # records the caller's pair again
+    torch.cuda.synchronize()
+    after = mine[0].elapsed_time(mine[1])
+    assert after > 0 and after != before
+    bf.bf_plan_set_kernel_events(plan, None, None)
     bucket = bf.batch_bucket(b.f)
     assert bf.bf_get_variant(plan, bf.BF_FP32, bucket) == best
     f_mean = int(round(float(np.mean(b.f))))
