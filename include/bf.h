@@ -173,6 +173,22 @@ bf_status bf_apply_packed(bf_plan plan, int32_t batch, const int32_t *w_ids, con
 bf_status bf_check_batch(int32_t n_w, int32_t f_max, int32_t batch, const int32_t *w_ids,
                          const int32_t *f, const void *const *S, void *const *R);
 
+/* ---- environment ------------------------------------------------------
+ * Read by bf_plan_create for the plan it makes:
+ *   BF_FORCE_VARIANT=s:w:o:t  every launch of the plan (bf_apply*, graphs,
+ *       the serving loop) uses bf_variant {s, w, o, t} instead of its tuning
+ *       table, except bf_autotune's own trials; an out-of-range value is
+ *       reported on stderr and ignored.
+ *   BF_AUTOTUNE_CACHE=path    the plan loads this tuning database (as
+ *       bf_tune_load) when the file exists, and bf_autotune saves the plan's
+ *       table to it (as bf_tune_save) after each tuning.
+ *   BF_LOG=1                  one stderr line ("[bf] ...") per plan, per
+ *       tuning result, and per launch configuration (form, variant, schedule,
+ *       grid) the first time the plan launches it.
+ * The library also marks its host-side phases (plan creation, apply calls,
+ * serving launches, tuning, graph creation, pool updates) as roctx ranges,
+ * which rocprofv3 --marker-trace records. */
+
 /* ---- kernel timing ----------------------------------------------------
  * With start and stop set (hipEvent_t, created by the caller with timing
  * enabled), the apply kernel that each later bf_apply, bf_apply_packed,

@@ -99,9 +99,12 @@ static bf_status default_variants(bf_plan p)
     return BF_OK;
 }
 
+static void read_env(bf_plan p);
+
 extern "C" bf_status bf_plan_create(bf_plan *out, const void *w_pool, int32_t n_w, int32_t f_max,
                                     uint32_t prec_mask, void *hip_stream)
 {
+    HostRange range("bf_plan_create");
     if (!out)
         return bf_fail(BF_ERR_INVALID, "out is null");
     *out = nullptr;
@@ -130,6 +133,7 @@ extern "C" bf_status bf_plan_create(bf_plan *out, const void *w_pool, int32_t n_
     p->half.assign((size_t)n_w, 0);
     p->guard.assign((size_t)n_w, nullptr);
     default_variants(p);
+    read_env(p);
 
     auto fail_dev = [&](const char *what, hipError_t e) {
         bf_status s = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? BF_ERR_OOM
@@ -237,6 +241,18 @@ extern "C" bf_status bf_plan_create(bf_plan *out, const void *w_pool, int32_t n_
     e = hipStreamSynchronize(p->copy_stream);
     if (e != hipSuccess)
         return fail_dev("hipStreamSynchronize(staging)", e);
+    if (!p->tune_cache.empty()) {
+        if (FILE *fp = fopen(p->tune_cache.c_str(), "r")) {
+            fclose(fp);
+            if (bf_tune_load(p, p->tune_cache.c_str()) != BF_OK)
+                fprintf(stderr, "[bf] BF_AUTOTUNE_CACHE %s not loaded: %s\n", p->tune_cache.c_str(),
+                        bf_last_error());
+        }
+    }
+    if (p->log)
+        fprintf(stderr, "[bf] plan: %d W of 64 x %d, forms 0x%x, device %d (%d CUs)%s%s%s\n", n_w, f_max,
+                prec_mask, p->device, p->n_cu, p->env_force_set ? ", BF_FORCE_VARIANT set" : "",
+                p->tune_cache.empty() ? "" : ", tune cache ", p->tune_cache.c_str());
     *out = p;
     return BF_OK;
 }
@@ -314,6 +330,7 @@ extern "C" bf_status bf_plan_set_kernel_events(bf_plan p, void *start, void *sto
 
 extern "C" bf_status bf_plan_update(bf_plan p, int32_t w_id, const void *w, void *hip_stream)
 {
+    HostRange range("bf_plan_update");
     if (!p)
         return bf_fail(BF_ERR_INVALID, "plan is null");
     if (!w)
@@ -424,6 +441,57 @@ int batch_bucket(int64_t sum_f, int n)
     if (n <= 0)
         return 0;
     return bf_f_bucket((int32_t)((sum_f + n / 2) / n));
+}
+
+bf_variant pick_variant(bf_plan p, bf_prec prec, int bucket, const bf_variant *force)
+{
+    if (force)
+        return *force;
+    if (p->env_force_set)
+        return p->env_force;
+    return p->table[prec][bucket];
+}
+
+static const char *const kPrecNames[kPrecCount] = {"fp32", "fp16", "bf16", "fp16x2", "bf16x2", "fp32_3m"};
+
+void log_launch(bf_plan p, bf_prec prec, int n, const bfk::LaunchCfg &cfg, const bf_variant &v,
+                const char *path)
+{
+    if (!p->log || p->tuning)
+        return;
+    char key[160];
+    snprintf(key, sizeof key, "%s %s variant %d:%d:%d:%d -> schedule %d grid %d%s%s%s", path,
+             kPrecNames[prec], v.schedule, v.wg_per_cu, v.order, v.store, cfg.schedule, cfg.grid,
+             cfg.vec16 ? " vec16" : "", cfg.stage ? " staged" : "", cfg.tile16 ? " 16x16" : "");
+    if (p->logged.insert(key).second)
+        fprintf(stderr, "[bf] launch %s (first: %d items)\n", key, n);
+}
+
+// BF_FORCE_VARIANT, BF_AUTOTUNE_CACHE and BF_LOG, read when a plan is made.
+static void read_env(bf_plan p)
+{
+    const char *lg = getenv("BF_LOG");
+    p->log = lg && *lg && strcmp(lg, "0") != 0 ? 1 : 0;
+    const char *fv = getenv("BF_FORCE_VARIANT");
+    if (fv && *fv) {
+        bf_variant v{};
+        char tail = 0;
+        const int got = sscanf(fv, "%d:%d:%d:%d%c", &v.schedule, &v.wg_per_cu, &v.order, &v.store, &tail);
+        const bool ok = got == 4 && v.schedule >= 0 && v.schedule <= 3 && v.wg_per_cu >= 0 &&
+                        v.wg_per_cu <= 64 && v.order >= 0 && v.order <= 2 && v.store >= 0 &&
+                        v.store <= (v.schedule == 3 ? 7 : 1);
+        if (ok) {
+            p->env_force_set = true;
+            p->env_force = v;
+        } else {
+            // (a bad setting must not go unnoticed, logging or not)
+            fprintf(stderr, "[bf] BF_FORCE_VARIANT=\"%s\" ignored: expected schedule:wg_per_cu:order:store "
+                    "within the ranges of bf_variant\n", fv);
+        }
+    }
+    const char *tc = getenv("BF_AUTOTUNE_CACHE");
+    if (tc && *tc)
+        p->tune_cache = tc;
 }
 
 // Orders items longest f first and, for equal f, by W id (so that a
@@ -611,7 +679,7 @@ static bf_status upload_and_launch(bf_plan p, bf_prec prec, int n, const FillSta
     BfItem *items = reinterpret_cast<BfItem *>(static_cast<char *>(slot.host) + sizeof(BfHeader) +
                                                kSinkBytes);
     const bool uniform_f = fs.min_f == fs.max_f;
-    bf_variant chosen = force ? *force : p->table[prec][batch_bucket(fs.sum_f, n)];
+    bf_variant chosen = pick_variant(p, prec, batch_bucket(fs.sum_f, n), force);
     if (chosen.order >= 1 && n > 1 && may_order) {
         p->sort_tmp.resize((size_t)n);
         order_items(items, p->sort_tmp.data(), n, p->n_w, p->sort_scratch, chosen.order);
@@ -620,6 +688,7 @@ static bf_status upload_and_launch(bf_plan p, bf_prec prec, int n, const FillSta
     bfk::LaunchCfg cfg = choose_launch(p, prec, n, fs.max_f, fs.vec16, uniform_f, &chosen);
     cfg.ev_start = p->kev_start;
     cfg.ev_stop = p->kev_stop;
+    log_launch(p, prec, n, cfg, chosen, "apply");
     if (grid_out)
         *grid_out = cfg.grid;
     map_slots(p, items, n);
@@ -676,6 +745,7 @@ static void order_records(std::vector<BfReqRec> &recs, std::vector<BfReqRec> &tm
 bf_status enqueue_requests(bf_plan p, bf_prec prec, std::vector<BfReqRec> &recs, int n_items,
                            hipStream_t st)
 {
+    HostRange range("bf_serve_launch");
     const int n_recs = (int)recs.size();
     if (n_items == 0)
         return BF_OK;
@@ -697,12 +767,13 @@ bf_status enqueue_requests(bf_plan p, bf_prec prec, std::vector<BfReqRec> &recs,
     bf_status s = ensure_slot(slot, rec_off + (size_t)n_recs * sizeof(BfReqRec));
     if (s != BF_OK)
         return s;
-    bf_variant chosen = p->table[prec][batch_bucket(fs.sum_f, n_items)];
+    bf_variant chosen = pick_variant(p, prec, batch_bucket(fs.sum_f, n_items), nullptr);
     if (chosen.order >= 1 && n_recs > 1)
         order_records(recs, p->rec_tmp, chosen.order);
     bfk::LaunchCfg cfg = choose_launch(p, prec, n_items, fs.max_f, fs.vec16, fs.min_f == fs.max_f, &chosen);
     cfg.ev_start = p->kev_start;
     cfg.ev_stop = p->kev_stop;
+    log_launch(p, prec, n_items, cfg, chosen, "serve");
     BfReqRec *dst = reinterpret_cast<BfReqRec *>(static_cast<char *>(slot.host) + rec_off);
     int item0 = 0;
     for (int k = 0; k < n_recs; ++k) {
@@ -797,6 +868,7 @@ static bf_status check_plan_prec(bf_plan p, bf_prec prec)
 extern "C" bf_status bf_apply(bf_plan p, int32_t batch, const int32_t *w_ids, const int32_t *f,
                               const void *const *S, void *const *R, bf_prec prec, void *hip_stream)
 {
+    HostRange range("bf_apply");
     bf_status s = check_plan_prec(p, prec);
     if (s != BF_OK)
         return s;
@@ -867,6 +939,7 @@ static bf_status scratch_on(int dev, void **out)
 extern "C" bf_status bf_apply_noalloc(bf_plan p, int32_t batch, const int32_t *w_ids, const int32_t *f,
                                       const void *const *S, void *const *R, bf_prec prec, void *hip_stream)
 {
+    HostRange range("bf_apply_noalloc");
     bf_status s = check_plan_prec(p, prec);
     if (s != BF_OK)
         return s;
@@ -928,6 +1001,7 @@ extern "C" bf_status bf_apply_packed(bf_plan p, int32_t batch, const int32_t *w_
                                      const int32_t *f, const void *S_base, const int64_t *s_off,
                                      void *R_base, bf_prec prec, void *hip_stream)
 {
+    HostRange range("bf_apply_packed");
     bf_status s = check_plan_prec(p, prec);
     if (s != BF_OK)
         return s;
@@ -988,6 +1062,7 @@ extern "C" bf_status bf_graph_create(bf_graph *out, bf_plan p, int32_t batch, co
                                      const int32_t *f, const void *const *S, void *const *R,
                                      bf_prec prec, void *hip_stream)
 {
+    HostRange range("bf_graph_create");
     if (!out)
         return bf_fail(BF_ERR_INVALID, "out is null");
     *out = nullptr;
@@ -1015,12 +1090,20 @@ extern "C" bf_status bf_graph_create(bf_graph *out, bf_plan p, int32_t batch, co
             vec16 = false;
     }
     std::vector<int> scratch;
-    const bf_variant v = p->table[prec][batch_bucket(sum_f, batch)];
+    bf_variant v;
+    {
+        std::lock_guard<std::mutex> lk(p->mu);
+        v = pick_variant(p, prec, batch_bucket(sum_f, batch), nullptr);
+    }
     if (v.order >= 1)
         order_items(raw.data(), items.data(), batch, p->n_w, scratch, v.order);
     else
         items = raw;
     bfk::LaunchCfg cfg = choose_launch(p, prec, batch, max_f, vec16, min_f == max_f, &v);
+    {
+        std::lock_guard<std::mutex> lk(p->mu);
+        log_launch(p, prec, batch, cfg, v, "graph");
+    }
 
     bool after_update = false;
     {
@@ -1162,6 +1245,7 @@ extern "C" bf_status bf_autotune(bf_plan p, int32_t batch, const int32_t *w_ids,
     // kernel events, set per launch), so the host's packing and upload and
     // the queue's gaps stay out of the comparison.  The caller's events are
     // put back afterwards.
+    HostRange range("bf_autotune");
     std::vector<hipEvent_t> kev((size_t)2 * reps, nullptr);
     for (hipEvent_t &e : kev)
         if (hipEventCreate(&e) != hipSuccess) {
@@ -1174,6 +1258,7 @@ extern "C" bf_status bf_autotune(bf_plan p, int32_t batch, const int32_t *w_ids,
         saved[0] = p->kev_start;
         saved[1] = p->kev_stop;
         p->kev_start = p->kev_stop = nullptr;
+        p->tuning = true;
     }
     float best_t = 1e30f;
     bf_variant best_v = cands[0];
@@ -1228,6 +1313,7 @@ extern "C" bf_status bf_autotune(bf_plan p, int32_t batch, const int32_t *w_ids,
         std::lock_guard<std::mutex> lk(p->mu);
         p->kev_start = saved[0];
         p->kev_stop = saved[1];
+        p->tuning = false;
     }
     for (hipEvent_t e : kev)
         if (e)
@@ -1239,6 +1325,12 @@ extern "C" bf_status bf_autotune(bf_plan p, int32_t batch, const int32_t *w_ids,
         p->table[prec][batch_bucket(sum_f, batch)] = best_v;
         p->tuned_us[prec][batch_bucket(sum_f, batch)] = best_t;
     }
+    if (p->log)
+        fprintf(stderr, "[bf] autotune %s bucket %d: %d:%d:%d:%d, %.2f us (%zu candidates)\n",
+                kPrecNames[prec], batch_bucket(sum_f, batch), best_v.schedule, best_v.wg_per_cu,
+                best_v.order, best_v.store, best_t, cands.size());
+    if (!p->tune_cache.empty() && bf_tune_save(p, p->tune_cache.c_str()) != BF_OK)
+        fprintf(stderr, "[bf] BF_AUTOTUNE_CACHE %s not written: %s\n", p->tune_cache.c_str(), bf_last_error());
     if (best)
         *best = best_v;
     if (best_us)

@@ -3,8 +3,12 @@
 
 #include <hip/hip_runtime.h>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <functional>
 #include <mutex>
+#include <set>
+#include <string>
 #include <vector>
 
 #include "bf_internal.h"
@@ -71,9 +75,17 @@ struct bf_plan_s {
     bool any_update = false;
 
     hipStream_t copy_stream = nullptr;   // descriptor uploads (overlap the previous launch)
-    std::mutex mu;              // guards the ring, the tables, the sort buffers and kev_*
+    std::mutex mu;              // guards the ring, the tables, the sort buffers, kev_* and logged
     hipEvent_t kev_start = nullptr;   // kernel timing events (bf_plan_set_kernel_events)
     hipEvent_t kev_stop = nullptr;
+
+    // Environment at creation (include/bf.h, "Environment").
+    bool env_force_set = false;  // BF_FORCE_VARIANT
+    bf_variant env_force{};
+    std::string tune_cache;      // BF_AUTOTUNE_CACHE
+    int log = 0;                 // BF_LOG
+    bool tuning = false;         // bf_autotune is running (its launches are not logged)
+    std::set<std::string> logged;   // launch configurations already logged
     std::vector<StagingSlot> ring;
     size_t ring_next = 0;
     bf_variant table[kPrecCount][kBucketCount];
@@ -91,6 +103,22 @@ struct FillStats {
 };
 // Tuning-table bucket of a batch: bf_f_bucket of its mean f, rounded.
 int batch_bucket(int64_t sum_f, int n);
+// The variant a launch of the plan takes: the caller's, else BF_FORCE_VARIANT,
+// else the plan's table.  Caller holds p->mu.
+bf_variant pick_variant(bf_plan p, bf_prec prec, int bucket, const bf_variant *force);
+// With BF_LOG set, one stderr line for each launch configuration the first
+// time the plan launches it.  Caller holds p->mu.
+void log_launch(bf_plan p, bf_prec prec, int n, const bfk::LaunchCfg &cfg, const bf_variant &v,
+                const char *path);
+
+// A roctx range over a host-side phase (shown by rocprofv3 --marker-trace).
+class HostRange {
+public:
+    explicit HostRange(const char *name) { roctxRangePushA(name); }
+    ~HostRange() { roctxRangePop(); }
+    HostRange(const HostRange &) = delete;
+    HostRange &operator=(const HostRange &) = delete;
+};
 using FillFn = std::function<FillStats(BfItem *)>;
 
 void order_items(const BfItem *in, BfItem *out, int n, int n_w, std::vector<int> &scratch, int mode);
