@@ -16,7 +16,10 @@ Prints one JSON line: whole-job complex GFLOP/s (8 real flops per complex
 multiply-add, 8*64*60*f per product), the roofline of the apply kernel
 (kernel time from HIP events on the launch stream, algorithmic flops or
 bytes per launch), and the FP64 oracle timed on the host on a bounded
-sample of the same workload.
+sample of the same workload.  The default line also carries the uneven
+batch, the gain workload in the four 16-bit forms, and the serving
+workload (closed-loop capacity, p50/p99 at half of it); --no-compare
+leaves all of these out, --no-serving only the serving workload.
 """
 from __future__ import annotations
 
@@ -585,6 +588,8 @@ def main(argv=None) -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="tune the variant before timing")
     ap.add_argument("--requests", type=int, default=200000, help="serving: requests replayed")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="full-width line: leave out the serving workload")
     ap.add_argument("--budget-gib", type=int, default=16, help="serving: HBM budget")
     ap.add_argument("--streams", type=int, default=2, help="serving: device streams")
     ap.add_argument("--serve-split", default="fp16x2", choices=["fp16x2", "bf16x2", "fp16", "bf16"],
@@ -693,8 +698,15 @@ def main(argv=None) -> int:
                  "variant": list(vs)}
 
     side = None
+    serving = None
     if args.workload == "full-width" and prec == bf.BF_FP32_3M and not args.no_compare:
         side = side_workloads(args, torch, stream)
+        if not args.no_serving:
+            # The serving workload (Poisson requests against a pool of 1024 W)
+            # in the same run: closed-loop capacity, then p50/p99 of the
+            # three-product FP32 and split forms at half of it.
+            serving = serve_bench(args, torch)
+            torch.cuda.empty_cache()
 
     flops = batch.flops()
     nbytes = batch.bytes_moved()
@@ -804,6 +816,11 @@ def main(argv=None) -> int:
         side["gain_workload"].pop("_batch", None)
         out["uneven_batch"] = side["uneven_batch"]
         out["gain_workload"] = side["gain_workload"]
+    if serving is not None:
+        serving["workload"] = ("serving: Poisson requests, pool 1024 W 64x36, f~U{1..36}, 1..64 S of "
+                               f"256-QAM, 0.5 ms deadline, {args.budget_gib} GiB budget, "
+                               f"{args.streams} streams")
+        out["serving_workload"] = serving
     plan.close()
     print(json.dumps(out), flush=True)
     return 0
