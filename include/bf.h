@@ -255,8 +255,11 @@ typedef struct {
                               3 = (8, 3), 4 = (12, 1), 5 = (12, 2); the
                               three-product form uses at most 8 producers, and
                               with 6 = (8, 1) or 7 = (8, 2) runs 8 matrix-core
-                              waves on 16 x 16 tiles instead of 4 on 32 x 32
-                              (6 and 7 read as 0 for the other forms); the
+                              waves on 16 x 16 tiles instead of 4 on 32 x 32,
+                              and with 8 = (8, 2) the same with the
+                              matrix-core waves copying W into LDS by direct
+                              global-to-LDS loads, the producers moving S and
+                              R only (6 to 8 read as 0 for the other forms); the
                               16-bit forms prefetch at least 2 products, and 3
                               only with 8 producers */
 } bf_variant;

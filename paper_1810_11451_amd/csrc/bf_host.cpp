@@ -87,7 +87,8 @@ static bf_status default_variants(bf_plan p)
             if (!full)
                 v = bf_variant{0, 0, 2, 1};   // one per workgroup, grouped by W id mod 8, staged
             else if (pr == BF_FP32_3M)
-                v = bf_variant{3, 0, 0, 7};   // wave-specialised, 16 x 16 tiles, depth 2, as given
+                v = bf_variant{3, 0, 0, 8};   // wave-specialised, 16 x 16 tiles, W copied by the
+                                              // matrix-core waves, depth 2, as given
             else if (fp32)
                 v = bf_variant{3, 0, 0, 5};   // wave-specialised, 12 producers, depth 2, as given
             else if (pr == BF_FP16 || pr == BF_BF16)
@@ -479,7 +480,7 @@ static void read_env(bf_plan p)
         const int got = sscanf(fv, "%d:%d:%d:%d%c", &v.schedule, &v.wg_per_cu, &v.order, &v.store, &tail);
         const bool ok = got == 4 && v.schedule >= 0 && v.schedule <= 3 && v.wg_per_cu >= 0 &&
                         v.wg_per_cu <= 64 && v.order >= 0 && v.order <= 2 && v.store >= 0 &&
-                        v.store <= (v.schedule == 3 ? 7 : 1);
+                        v.store <= (v.schedule == 3 ? 8 : 1);
         if (ok) {
             p->env_force_set = true;
             p->env_force = v;
@@ -573,13 +574,15 @@ bfk::LaunchCfg choose_launch(bf_plan p, bf_prec prec, int n, int max_f, bool vec
     cfg.depth = kDepths[ws];
     if (prec == BF_FP32_3M && cfg.producers > 8)
         cfg.producers = 8;   // its two accumulator sets leave registers for 12 waves only
-    // Store fields 6 and 7 (three-product form): 8 matrix-core waves on
-    // 16 x 16 tiles and 8 producers at prefetch depth 1 or 2.  Other forms
-    // read them as 0.
+    // Store fields 6, 7 and 8 (three-product form): 8 matrix-core waves on
+    // 16 x 16 tiles and 8 producers at prefetch depth 1, 2, and 2 with the
+    // matrix-core waves copying W into LDS themselves.  Other forms read
+    // them as 0.
     cfg.tile16 = prec == BF_FP32_3M && cfg.schedule == 3 && v.store >= 6;
     if (cfg.tile16) {
         cfg.producers = 8;
-        cfg.depth = v.store == 7 ? 2 : 1;
+        cfg.depth = v.store >= 7 ? 2 : 1;
+        cfg.w_dma = v.store == 8;
     }
     if (v.schedule == 0) {
         cfg.grid = n;
@@ -1172,7 +1175,7 @@ extern "C" bf_status bf_graph_destroy(bf_graph g)
 static bool valid_variant(const bf_variant &v)
 {
     return v.schedule >= 0 && v.schedule <= 3 && v.wg_per_cu >= 0 && v.wg_per_cu <= 64 &&
-           v.order >= 0 && v.order <= 2 && v.store >= 0 && v.store <= (v.schedule == 3 ? 7 : 1);
+           v.order >= 0 && v.order <= 2 && v.store >= 0 && v.store <= (v.schedule == 3 ? 8 : 1);
 }
 
 extern "C" bf_status bf_set_variant(bf_plan p, bf_prec prec, int32_t bucket, const bf_variant *v)
@@ -1235,10 +1238,10 @@ extern "C" bf_status bf_autotune(bf_plan p, int32_t batch, const int32_t *w_ids,
             for (int o = 0; o < 2; ++o)
                 cands.push_back(bf_variant{2, w, o, st});
     // (the 16-bit wave-specialised kernel takes batches of one f only; store
-    // fields 6 and 7 exist for the three-product form only)
+    // fields 6 to 8 exist for the three-product form only)
     if (!lp || min_f == max_f)
         for (int o = 0; o < 3; ++o)
-            for (int st = 0; st < (prec == BF_FP32_3M ? 8 : 6); ++st)
+            for (int st = 0; st < (prec == BF_FP32_3M ? 9 : 6); ++st)
                 cands.push_back(bf_variant{3, 0, o, st});
 
     // Each timed launch records its kernel's own start and end (the plan's

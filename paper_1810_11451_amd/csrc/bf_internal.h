@@ -120,6 +120,7 @@ struct LaunchCfg {
     int producers;   // schedule 3: producer waves per workgroup (4, 8 or 12)
     int depth;       // schedule 3: products of S prefetched in producer registers (1..3)
     bool tile16;     // schedule 3, three-product form: 8 matrix-core waves on 16 x 16 tiles
+    bool w_dma;      // tile16: the matrix-core waves copy W into LDS (global-to-LDS loads)
     hipEvent_t ev_start = nullptr;   // if set, recorded at the kernel's own start and end
     hipEvent_t ev_stop = nullptr;    // (hipExtLaunchKernel), for timing the kernel alone
 };

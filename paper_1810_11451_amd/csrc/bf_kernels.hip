@@ -1028,7 +1028,7 @@ __device__ __forceinline__ void p_put_s(f2v *__restrict__ lds, const PRegs<kProd
             *reinterpret_cast<f4v *>(lds + row * kLdsCols + 2 * col2) = r.v[u];
         }
     }
-    if constexpr (kW == 2) {
+    if constexpr (kW >= 2) {
         const int gap = ((f + 3) & ~3) - f;
         if (ptid < gap * kLdsCols)
             lds[f * kLdsCols + ptid] = f2v{0.f, 0.f};
@@ -1168,7 +1168,8 @@ __device__ __forceinline__ void ws_produce_step(PRegs<kProd, kW> (&sr)[kDepth], 
 // barrier of the consumers.  The consumers stage R(t) during iteration t
 // (four-product and 16-bit forms) or t + 1 (three-product form, epilogue
 // folded into the next chain), so iteration t writes R(t - kLag).  kW selects the W layout the
-// producers stage (0: none).
+// producers stage (0: none; 3: none, with S cleared to the 16 x 16 tiles' granularity, for the
+// kernel whose matrix-core waves copy W themselves).
 template <int kProd, int kDepth, int kW, bool kMax, int kCons = kWaves>
 __device__ __forceinline__ void ws_producer(c_item *my, int stride, int n_my, float2 *sink,
                                             WsLds<kW != 0, kProd> &L, const void *apool, int a_w_stride,
@@ -1480,17 +1481,71 @@ __device__ __forceinline__ void chain_3m16_any(const f2v *__restrict__ s_lds, co
 // the R of product k is staged during iteration k + 1 and written out by the
 // producers in iteration k + 2.  f of product k + 1 is read at the end of
 // product k, where the barrier waits for it anyway.
-template <int kProd>
+// Direct global-to-LDS copy (global_load_lds_dwordx4) of the 16 x 16 layout
+// W of one pool entry, the steps a product of f flows reads, into the LDS
+// buffer dst, by matrix-core wave cw: instruction k of the wave copies the
+// 16-byte units 512 k + 64 cw + lane.  Such a load writes LDS at its
+// wave-uniform base (M0) plus 16 bytes per lane, so each instruction covers
+// 64 consecutive units; the units of unused steps are left out lane by lane.
+// No registers hold the data and no LDS write instruction is issued: the
+// copy costs the matrix-core waves three load instructions per product.
+constexpr int kW16DmaRounds = (kW16ChunksMax + 64 * kCons16 - 1) / (64 * kCons16);
+
+__device__ __forceinline__ void dma_w16(float *__restrict__ dst, const float *__restrict__ wsrc,
+                                        int plan_steps, int f, int cw, int lane)
+{
+    typedef __attribute__((address_space(1))) const void g_cv;
+    typedef __attribute__((address_space(3))) void l_v;
+    const int units = plan_steps * 128;
+    const int need = max((f + 3) >> 2, 1);
+#pragma unroll
+    for (int k = 0; k < kW16DmaRounds; ++k) {
+        const int base = 512 * k + 64 * cw;   // wave-uniform
+        if (base < units) {
+            const int u = base + lane;
+            if (((u >> 5) % plan_steps) < need)
+                __builtin_amdgcn_global_load_lds((g_cv *)(wsrc + 4 * u), (l_v *)(dst + 4 * base), 16, 0, 0);
+        }
+    }
+}
+
+// Waits for this wave's outstanding vector-memory loads (here only the W
+// copies) and nothing else: s_waitcnt vmcnt(0) with expcnt and lgkmcnt at
+// their maximum.
+__device__ __forceinline__ void dma_wait()
+{
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+}
+
+template <int kProd, bool kDma>
 __device__ __forceinline__ void ws_3m16_consumer(c_item *my, int stride, int n_my, WsLds<true, kProd> &L,
-                                                 int pairs, int cw, int lane)
+                                                 const float *__restrict__ apool, int a_w_stride, int pairs,
+                                                 int cw, int lane)
 {
     const int plan_steps = fp32_3m16_steps(pairs);
+    const float *w16 = apool + fp32_3m16_offset(pairs);
     floatx4 accA[2][3], accB[2][3];
-    int f = item_at(my, 0, stride).f;
+    // With kDma the matrix-core waves copy each product's W themselves: W of
+    // product k + 1 into buffer (k + 1) & 1 while chain k runs (that buffer
+    // held W of product k - 1, which every matrix-core wave finished before
+    // the barrier that opened iteration k), complete before the barrier
+    // that closes iteration k.
+    BfItem d = item_at(my, 0, stride);
+    int f = d.f;
+    if constexpr (kDma) {
+        dma_w16(L.a_buf.v[0], w16 + (size_t)d.w_id * a_w_stride, plan_steps, d.f, cw, lane);
+        dma_wait();
+    }
     __syncthreads();
+    if constexpr (kDma) {
+        d = item_at(my, min(1, n_my - 1), stride);
+        dma_w16(L.a_buf.v[1], w16 + (size_t)d.w_id * a_w_stride, plan_steps, d.f, cw, lane);
+    }
     chain_3m16_any<false>(L.s_buf[0], L.a_buf.v[0], plan_steps, f, cw, lane, accA, accA, nullptr);
     __builtin_amdgcn_sched_barrier(0);
     f = item_at(my, min(1, n_my - 1), stride).f;
+    if constexpr (kDma)
+        dma_wait();
     __syncthreads();
     int k = 1;
     while (true) {
@@ -1501,10 +1556,16 @@ __device__ __forceinline__ void ws_3m16_consumer(c_item *my, int stride, int n_m
             __syncthreads();
             break;
         }
+        if constexpr (kDma) {
+            d = item_at(my, min(k + 1, n_my - 1), stride);
+            dma_w16(L.a_buf.v[(k + 1) & 1], w16 + (size_t)d.w_id * a_w_stride, plan_steps, d.f, cw, lane);
+        }
         chain_3m16_any<true>(L.s_buf[k & 1], L.a_buf.v[k & 1], plan_steps, f, cw, lane, accB, accA,
                              L.r_buf[(k - 1) & 1]);
         __builtin_amdgcn_sched_barrier(0);
         f = item_at(my, min(k + 1, n_my - 1), stride).f;
+        if constexpr (kDma)
+            dma_wait();
         __syncthreads();
         ++k;
         if (k >= n_my) {
@@ -1514,10 +1575,16 @@ __device__ __forceinline__ void ws_3m16_consumer(c_item *my, int stride, int n_m
             __syncthreads();
             break;
         }
+        if constexpr (kDma) {
+            d = item_at(my, min(k + 1, n_my - 1), stride);
+            dma_w16(L.a_buf.v[(k + 1) & 1], w16 + (size_t)d.w_id * a_w_stride, plan_steps, d.f, cw, lane);
+        }
         chain_3m16_any<true>(L.s_buf[k & 1], L.a_buf.v[k & 1], plan_steps, f, cw, lane, accA, accB,
                              L.r_buf[(k - 1) & 1]);
         __builtin_amdgcn_sched_barrier(0);
         f = item_at(my, min(k + 1, n_my - 1), stride).f;
+        if constexpr (kDma)
+            dma_wait();
         __syncthreads();
         ++k;
     }
@@ -1526,7 +1593,7 @@ __device__ __forceinline__ void ws_3m16_consumer(c_item *my, int stride, int n_m
 // kSched 3, three-product form on 16 x 16 tiles: 8 matrix-core waves and
 // kProd producer waves.  S must be 16-byte aligned and the plan's f_max at
 // least 1 (the host routes other batches elsewhere).
-template <int kProd, int kDepth>
+template <int kProd, int kDepth, bool kDma>
 __global__ __launch_bounds__(64 * (kCons16 + kProd)) void apply_fp32_3m16_ws(
     BfHeader *__restrict__ blk, const BfItem *__restrict__ items, int n_items,
     const void *__restrict__ apool, int a_w_stride, int pairs)
@@ -1542,9 +1609,11 @@ __global__ __launch_bounds__(64 * (kCons16 + kProd)) void apply_fp32_3m16_ws(
 
     c_item *my = (c_item *)items + start;
     if (wave < kCons16)
-        ws_3m16_consumer<kProd>(my, stride, n_my, L, pairs, wave, lane);
+        ws_3m16_consumer<kProd, kDma>(my, stride, n_my, L, static_cast<const float *>(apool), a_w_stride,
+                                      pairs, wave, lane);
     else
-        ws_producer<kProd, kDepth, 2, false, kCons16>(my, stride, n_my, sink, L, apool, a_w_stride, pairs);
+        ws_producer<kProd, kDepth, kDma ? 3 : 2, false, kCons16>(my, stride, n_my, sink, L, apool,
+                                                                 a_w_stride, pairs);
 }
 
 // ---------------------------------------------------------------------------
@@ -2396,11 +2465,14 @@ static hipError_t launch_ws(const LaunchCfg &cfg, BfHeader *blk, int n_items, co
     const BfItem *items = items_of(blk);
     const dim3 grid(cfg.grid);
     if (k3M && cfg.tile16) {
-        if (cfg.depth >= 2)
-            BF_LAUNCH(cfg, (apply_fp32_3m16_ws<8, 2>), grid, dim3(64 * (kCons16 + 8)), st, blk,
+        if (cfg.w_dma)
+            BF_LAUNCH(cfg, (apply_fp32_3m16_ws<8, 2, true>), grid, dim3(64 * (kCons16 + 8)), st, blk,
+                      items, n_items, apool, a_stride, pairs);
+        else if (cfg.depth >= 2)
+            BF_LAUNCH(cfg, (apply_fp32_3m16_ws<8, 2, false>), grid, dim3(64 * (kCons16 + 8)), st, blk,
                       items, n_items, apool, a_stride, pairs);
         else
-            BF_LAUNCH(cfg, (apply_fp32_3m16_ws<8, 1>), grid, dim3(64 * (kCons16 + 8)), st, blk,
+            BF_LAUNCH(cfg, (apply_fp32_3m16_ws<8, 1, false>), grid, dim3(64 * (kCons16 + 8)), st, blk,
                       items, n_items, apool, a_stride, pairs);
         return hipGetLastError();
     }
