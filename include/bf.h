@@ -259,7 +259,9 @@ typedef struct {
                               and with 8 = (8, 2) the same with the
                               matrix-core waves copying W into LDS by direct
                               global-to-LDS loads, the producers moving S and
-                              R only (6 to 8 read as 0 for the other forms); the
+                              R only, 9 = 8 with the producers also copying S
+                              that way into three LDS buffers (6 to 9 read as
+                              0 for the other forms); the
                               16-bit forms prefetch at least 2 products, and 3
                               only with 8 producers */
 } bf_variant;

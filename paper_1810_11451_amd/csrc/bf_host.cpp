@@ -480,7 +480,7 @@ static void read_env(bf_plan p)
         const int got = sscanf(fv, "%d:%d:%d:%d%c", &v.schedule, &v.wg_per_cu, &v.order, &v.store, &tail);
         const bool ok = got == 4 && v.schedule >= 0 && v.schedule <= 3 && v.wg_per_cu >= 0 &&
                         v.wg_per_cu <= 64 && v.order >= 0 && v.order <= 2 && v.store >= 0 &&
-                        v.store <= (v.schedule == 3 ? 8 : 1);
+                        v.store <= (v.schedule == 3 ? 9 : 1);
         if (ok) {
             p->env_force_set = true;
             p->env_force = v;
@@ -582,7 +582,8 @@ bfk::LaunchCfg choose_launch(bf_plan p, bf_prec prec, int n, int max_f, bool vec
     if (cfg.tile16) {
         cfg.producers = 8;
         cfg.depth = v.store >= 7 ? 2 : 1;
-        cfg.w_dma = v.store == 8;
+        cfg.w_dma = v.store >= 8;
+        cfg.s_dma = v.store == 9;
     }
     if (v.schedule == 0) {
         cfg.grid = n;
@@ -1175,7 +1176,7 @@ extern "C" bf_status bf_graph_destroy(bf_graph g)
 static bool valid_variant(const bf_variant &v)
 {
     return v.schedule >= 0 && v.schedule <= 3 && v.wg_per_cu >= 0 && v.wg_per_cu <= 64 &&
-           v.order >= 0 && v.order <= 2 && v.store >= 0 && v.store <= (v.schedule == 3 ? 8 : 1);
+           v.order >= 0 && v.order <= 2 && v.store >= 0 && v.store <= (v.schedule == 3 ? 9 : 1);
 }
 
 extern "C" bf_status bf_set_variant(bf_plan p, bf_prec prec, int32_t bucket, const bf_variant *v)
@@ -1238,10 +1239,10 @@ extern "C" bf_status bf_autotune(bf_plan p, int32_t batch, const int32_t *w_ids,
             for (int o = 0; o < 2; ++o)
                 cands.push_back(bf_variant{2, w, o, st});
     // (the 16-bit wave-specialised kernel takes batches of one f only; store
-    // fields 6 to 8 exist for the three-product form only)
+    // fields 6 to 9 exist for the three-product form only)
     if (!lp || min_f == max_f)
         for (int o = 0; o < 3; ++o)
-            for (int st = 0; st < (prec == BF_FP32_3M ? 9 : 6); ++st)
+            for (int st = 0; st < (prec == BF_FP32_3M ? 10 : 6); ++st)
                 cands.push_back(bf_variant{3, 0, o, st});
 
     // Each timed launch records its kernel's own start and end (the plan's

@@ -121,6 +121,7 @@ struct LaunchCfg {
     int depth;       // schedule 3: products of S prefetched in producer registers (1..3)
     bool tile16;     // schedule 3, three-product form: 8 matrix-core waves on 16 x 16 tiles
     bool w_dma;      // tile16: the matrix-core waves copy W into LDS (global-to-LDS loads)
+    bool s_dma;      // w_dma, and the producers copy S into three LDS buffers the same way
     hipEvent_t ev_start = nullptr;   // if set, recorded at the kernel's own start and end
     hipEvent_t ev_stop = nullptr;    // (hipExtLaunchKernel), for timing the kernel alone
 };

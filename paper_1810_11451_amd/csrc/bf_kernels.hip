@@ -1517,8 +1517,8 @@ __device__ __forceinline__ void dma_wait()
     __builtin_amdgcn_s_waitcnt(0x0F70);
 }
 
-template <int kProd, bool kDma>
-__device__ __forceinline__ void ws_3m16_consumer(c_item *my, int stride, int n_my, WsLds<true, kProd> &L,
+template <int kProd, bool kDma, int kSBufs, class Lds>
+__device__ __forceinline__ void ws_3m16_consumer(c_item *my, int stride, int n_my, Lds &L,
                                                  const float *__restrict__ apool, int a_w_stride, int pairs,
                                                  int cw, int lane)
 {
@@ -1542,6 +1542,7 @@ __device__ __forceinline__ void ws_3m16_consumer(c_item *my, int stride, int n_m
         dma_w16(L.a_buf.v[1], w16 + (size_t)d.w_id * a_w_stride, plan_steps, d.f, cw, lane);
     }
     chain_3m16_any<false>(L.s_buf[0], L.a_buf.v[0], plan_steps, f, cw, lane, accA, accA, nullptr);
+    int sb = 0;   // S buffer of product k: k % kSBufs
     __builtin_amdgcn_sched_barrier(0);
     f = item_at(my, min(1, n_my - 1), stride).f;
     if constexpr (kDma)
@@ -1560,7 +1561,8 @@ __device__ __forceinline__ void ws_3m16_consumer(c_item *my, int stride, int n_m
             d = item_at(my, min(k + 1, n_my - 1), stride);
             dma_w16(L.a_buf.v[(k + 1) & 1], w16 + (size_t)d.w_id * a_w_stride, plan_steps, d.f, cw, lane);
         }
-        chain_3m16_any<true>(L.s_buf[k & 1], L.a_buf.v[k & 1], plan_steps, f, cw, lane, accB, accA,
+        sb = sb + 1 == kSBufs ? 0 : sb + 1;
+        chain_3m16_any<true>(L.s_buf[sb], L.a_buf.v[k & 1], plan_steps, f, cw, lane, accB, accA,
                              L.r_buf[(k - 1) & 1]);
         __builtin_amdgcn_sched_barrier(0);
         f = item_at(my, min(k + 1, n_my - 1), stride).f;
@@ -1579,7 +1581,8 @@ __device__ __forceinline__ void ws_3m16_consumer(c_item *my, int stride, int n_m
             d = item_at(my, min(k + 1, n_my - 1), stride);
             dma_w16(L.a_buf.v[(k + 1) & 1], w16 + (size_t)d.w_id * a_w_stride, plan_steps, d.f, cw, lane);
         }
-        chain_3m16_any<true>(L.s_buf[k & 1], L.a_buf.v[k & 1], plan_steps, f, cw, lane, accA, accB,
+        sb = sb + 1 == kSBufs ? 0 : sb + 1;
+        chain_3m16_any<true>(L.s_buf[sb], L.a_buf.v[k & 1], plan_steps, f, cw, lane, accA, accB,
                              L.r_buf[(k - 1) & 1]);
         __builtin_amdgcn_sched_barrier(0);
         f = item_at(my, min(k + 1, n_my - 1), stride).f;
@@ -1588,6 +1591,149 @@ __device__ __forceinline__ void ws_3m16_consumer(c_item *my, int stride, int n_m
         __syncthreads();
         ++k;
     }
+}
+
+// LDS of the 16 x 16 three-product kernel whose producers copy S with
+// direct global-to-LDS loads: three S buffers (S of product t + 2 is copied
+// while the matrix-core waves work on t and t + 1 waits), W and R double
+// buffered.
+template <int kProd>
+struct WsLds3 {
+    alignas(16) f2v r_buf[2][kM * kB];
+    alignas(16) f2v s_buf[3][kFMax * kLdsCols];
+    alignas(16) WBuf<true> a_buf;
+    alignas(16) uint32_t smax[2][kProd];
+};
+
+// Direct global-to-LDS copy of one product's S (f rows of 60 complex,
+// contiguous, 16-byte aligned) into an S buffer (rows of kLdsCols complex) by
+// producer wave pw: 16-byte unit v of the buffer (row v / 32, complex columns
+// 2 (v % 32) and 2 (v % 32) + 1) comes from S + 60 row + 2 (v % 32).
+// Instruction k of the wave covers units 512 k + 64 pw .. + 63 (the load
+// writes LDS at its wave-uniform base plus 16 bytes per lane); the padding
+// columns 60..63 and rows from f on are left out lane by lane.
+constexpr int kSDmaRounds = (kFMax * 32 + 64 * 8 - 1) / (64 * 8);
+
+__device__ __forceinline__ void dma_s(f2v *__restrict__ dst, const float2 *__restrict__ S, int f, int pw,
+                                      int lane)
+{
+    typedef __attribute__((address_space(1))) const void g_cv;
+    typedef __attribute__((address_space(3))) void l_v;
+    const int units = f * 32;
+#pragma unroll
+    for (int k = 0; k < kSDmaRounds; ++k) {
+        const int base = 512 * k + 64 * pw;   // wave-uniform
+        if (base < units) {
+            const int v = base + lane;
+            const int row = v >> 5;
+            const int c2 = v & 31;
+            if (v < units && c2 < kB / 2)
+                __builtin_amdgcn_global_load_lds((g_cv *)(S + kB * row + 2 * c2), (l_v *)(dst + 2 * base), 16,
+                                                 0, 0);
+        }
+    }
+}
+
+// Clears S rows f .. 4 ceil(f / 4) - 1 of an S buffer (the last step's
+// flows past f), with plain LDS writes, before that buffer's copy is issued.
+__device__ __forceinline__ void clear_s_tail(f2v *__restrict__ dst, int f, int ptid)
+{
+    const int gap = ((f + 3) & ~3) - f;
+    if (ptid < gap * kLdsCols)
+        dst[f * kLdsCols + ptid] = f2v{0.f, 0.f};
+}
+
+// Barrier of the S-copying producers.  __syncthreads releases at workgroup
+// scope, and with a global-to-LDS load in flight that release waits for
+// every outstanding vector-memory operation: the copy of S(t + 2) just
+// issued, and the R stores.  Here the LDS writes are completed explicitly
+// (lgkmcnt(0)) and the copy the next chain needs was waited for before the
+// next one was issued, so the barrier itself waits for nothing more; the
+// compiler fences keep LDS accesses on their side of it (LDS has no cache
+// to invalidate).
+__device__ __forceinline__ void producer_barrier()
+{
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0), vmcnt and expcnt at their maximum
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// The producer role of the 16 x 16 kernel with S copied by direct loads
+// (kProd = 8 waves).  Iteration t (between the barriers that open and close
+// product t's chain) writes R(t - 2), waits for its vector-memory operations
+// older than those stores (the copy of S(t + 1), issued at the end of
+// iteration t - 1), then clears the tail rows of S(t + 2)'s buffer and
+// issues its copy: the copy has the whole next iteration to land.  The
+// barrier count matches the matrix-core waves' (n_my + 2).
+template <int kProd>
+__device__ __forceinline__ void ws_producer_sdma(c_item *my, int stride, int n_my, float2 *sink,
+                                                 WsLds3<kProd> &L)
+{
+    static_assert(kProd == 8, "the S copy covers a product with 8 waves");
+    const int ptid = threadIdx.x - 64 * kCons16;
+    const int pw = __builtin_amdgcn_readfirstlane(ptid >> 6);
+    const int lane = ptid & 63;
+    {
+        const BfItem d0 = item_at(my, 0, stride);
+        clear_s_tail(L.s_buf[0], d0.f, ptid);
+        if (d0.f > 0)
+            dma_s(L.s_buf[0], d0.S, d0.f, pw, lane);
+        if (n_my > 1) {
+            const BfItem d1 = item_at(my, 1, stride);
+            clear_s_tail(L.s_buf[1], d1.f, ptid);
+            if (d1.f > 0)
+                dma_s(L.s_buf[1], d1.S, d1.f, pw, lane);
+        }
+        dma_wait();
+    }
+    producer_barrier();
+    int sb = 2;   // S buffer of product t + 2
+    for (int t = 0; t < n_my; ++t) {
+        if (t >= 2)
+            p_store_r<kProd>(item_at(my, t - 2, stride).R, L.r_buf[t & 1], ptid);
+        else
+            prime_store_count<kPStoreRounds<kProd>>(sink, lane);
+        // (every lane issued exactly kPStoreRounds stores since the copy of
+        // S(t + 1): waiting until at most that many remain completes it)
+        __builtin_amdgcn_s_waitcnt(0x0F70 | kPStoreRounds<kProd>);
+        if (t + 2 < n_my) {
+            const BfItem d = item_at(my, t + 2, stride);
+            clear_s_tail(L.s_buf[sb], d.f, ptid);
+            if (d.f > 0)
+                dma_s(L.s_buf[sb], d.S, d.f, pw, lane);
+        }
+        sb = sb + 1 == 3 ? 0 : sb + 1;
+        producer_barrier();
+    }
+    if (n_my >= 2)
+        p_store_r<kProd>(item_at(my, n_my - 2, stride).R, L.r_buf[n_my & 1], ptid);
+    producer_barrier();
+    p_store_r<kProd>(item_at(my, n_my - 1, stride).R, L.r_buf[(n_my - 1) & 1], ptid);
+}
+
+// The 16 x 16 three-product kernel with both operands copied by direct
+// global-to-LDS loads: the matrix-core waves copy W (as in
+// apply_fp32_3m16_ws<.., true>), the 8 producer waves copy S and write R.
+__global__ __launch_bounds__(64 * (kCons16 + 8)) void apply_fp32_3m16_ws_sdma(
+    BfHeader *__restrict__ blk, const BfItem *__restrict__ items, int n_items,
+    const void *__restrict__ apool, int a_w_stride, int pairs)
+{
+    __shared__ WsLds3<8> L;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    float2 *sink = sink_of(blk);
+    int start, stride;
+    const int n_my = ws_share(n_items, &start, &stride);
+    if (n_my <= 0)
+        return;
+
+    c_item *my = (c_item *)items + start;
+    if (wave < kCons16)
+        ws_3m16_consumer<8, true, 3>(my, stride, n_my, L, static_cast<const float *>(apool), a_w_stride, pairs,
+                                     wave, lane);
+    else
+        ws_producer_sdma<8>(my, stride, n_my, sink, L);
 }
 
 // kSched 3, three-product form on 16 x 16 tiles: 8 matrix-core waves and
@@ -1609,8 +1755,8 @@ __global__ __launch_bounds__(64 * (kCons16 + kProd)) void apply_fp32_3m16_ws(
 
     c_item *my = (c_item *)items + start;
     if (wave < kCons16)
-        ws_3m16_consumer<kProd, kDma>(my, stride, n_my, L, static_cast<const float *>(apool), a_w_stride,
-                                      pairs, wave, lane);
+        ws_3m16_consumer<kProd, kDma, 2>(my, stride, n_my, L, static_cast<const float *>(apool), a_w_stride,
+                                         pairs, wave, lane);
     else
         ws_producer<kProd, kDepth, kDma ? 3 : 2, false, kCons16>(my, stride, n_my, sink, L, apool,
                                                                  a_w_stride, pairs);
@@ -2465,7 +2611,10 @@ static hipError_t launch_ws(const LaunchCfg &cfg, BfHeader *blk, int n_items, co
     const BfItem *items = items_of(blk);
     const dim3 grid(cfg.grid);
     if (k3M && cfg.tile16) {
-        if (cfg.w_dma)
+        if (cfg.s_dma)
+            BF_LAUNCH(cfg, apply_fp32_3m16_ws_sdma, grid, dim3(64 * (kCons16 + 8)), st, blk, items, n_items,
+                      apool, a_stride, pairs);
+        else if (cfg.w_dma)
             BF_LAUNCH(cfg, (apply_fp32_3m16_ws<8, 2, true>), grid, dim3(64 * (kCons16 + 8)), st, blk,
                       items, n_items, apool, a_stride, pairs);
         else if (cfg.depth >= 2)

@@ -241,8 +241,9 @@ def test_graph_replay_matches_direct():
 
 
 @pytest.mark.parametrize("prec,variant", [(bf.BF_FP32, (1, 0, 1)), (bf.BF_FP32_3M, (3, 0, 0, 7)),
-                                          (bf.BF_FP32_3M, (3, 0, 0, 8))],
-                         ids=["fp32-claim", "fp32_3m-ws16", "fp32_3m-ws16-w-copied"])
+                                          (bf.BF_FP32_3M, (3, 0, 0, 8)), (bf.BF_FP32_3M, (3, 0, 0, 9))],
+                         ids=["fp32-claim", "fp32_3m-ws16", "fp32_3m-ws16-w-copied",
+                              "fp32_3m-ws16-w-and-s-copied"])
 def test_graph_launch_inside_a_captured_hip_graph(prec, variant):
     """bf_graph_launch captured into the caller's own hipGraph (torch's
     CUDAGraph): every replay, with eager work between replays, gives the
