@@ -39,13 +39,13 @@ def test_force_variant_and_log(monkeypatch, capfd):
 
 def test_bad_force_variant_is_reported_and_ignored(monkeypatch, capfd):
     require_gpu()
-    monkeypatch.setenv("BF_FORCE_VARIANT", "3:0:0:9")   # store 9 does not exist
+    monkeypatch.setenv("BF_FORCE_VARIANT", "3:0:0:10")   # store 10 does not exist
     monkeypatch.delenv("BF_LOG", raising=False)
     b = wl.uneven_batch(n=300)
     plan = bf.bf_plan_create(b.W)
     R = _apply(plan, b)
     plan.close()
-    assert 'BF_FORCE_VARIANT="3:0:0:9" ignored' in capfd.readouterr().err
+    assert 'BF_FORCE_VARIANT="3:0:0:10" ignored' in capfd.readouterr().err
     e, _ = rel_errors(b, R)
     assert np.max(e) <= FP32_TOL
 
