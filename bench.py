@@ -348,10 +348,12 @@ def launched_schedule(prec: int, schedule: int) -> int:
 def kernel_symbol(prec: int, schedule: int, store: int = 0) -> str:
     """Name (as rocprofv3 lists it, without template arguments) of the apply
     kernel that a precision form, launched schedule and variant store field
-    run (store 6 and 7: the three-product form on 16 x 16 tiles)."""
+    run (store 6 to 9: the FP32 forms on 16 x 16 tiles)."""
     if prec in (bf.BF_FP32, bf.BF_FP32_3M):
         if schedule == 3:
-            return "apply_fp32_3m16_ws" if prec == bf.BF_FP32_3M and store >= 6 else "apply_fp32_ws"
+            if store >= 6:
+                return "apply_fp32_3m16_ws" if prec == bf.BF_FP32_3M else "apply_fp32_4m16_ws"
+            return "apply_fp32_ws"
         if prec == bf.BF_FP32_3M:
             return "apply_fp32_3m_single"
         return {0: "apply_fp32_single", 1: "apply_fp32_claim", 2: "apply_fp32_stream"}[schedule]
@@ -681,10 +683,11 @@ def main(argv=None) -> int:
         v4 = bf.bf_get_variant(plan4, bf.BF_FP32, bf.batch_bucket(batch.f))
         plan4.close()
         t4 = float(np.mean(k4)) / 1e3
-        compare = {"prec": "fp32", "kernel_us_mean": round(t4 * 1e6, 2),
+        sym4 = kernel_symbol(bf.BF_FP32, launched_schedule(bf.BF_FP32, v4[0]), v4[3])
+        compare = {"prec": "fp32", "kernel": sym4, "kernel_us_mean": round(t4 * 1e6, 2),
                    "tflops": round(batch.flops() / t4 / 1e12, 2),
                    "frac": round(batch.flops() / t4 / 1e12 / PEAK_FP32_TFLOPS, 4),
-                   "variant": list(v4)}
+                   "variant": list(v4), "traffic": load_traffic("full-width-fp32", sym4, v4)}
     split = None
     if prec == bf.BF_FP32_3M and not args.no_compare:
         # The 2-term split FP16 form (FP32-class accuracy from 16-bit matrix

@@ -253,15 +253,15 @@ typedef struct {
                               workgroup and products prefetched in their
                               registers, 0 = (4, 1), 1 = (8, 1), 2 = (8, 2),
                               3 = (8, 3), 4 = (12, 1), 5 = (12, 2); the
-                              three-product form uses at most 8 producers, and
-                              with 6 = (8, 1) or 7 = (8, 2) runs 8 matrix-core
-                              waves on 16 x 16 tiles instead of 4 on 32 x 32,
-                              and with 8 = (8, 2) the same with the
+                              three-product form uses at most 8 producers; the
+                              FP32 forms with 6 = (8, 1) or 7 = (8, 2) run 8
+                              matrix-core waves on 16 x 16 tiles instead of 4
+                              on 32 x 32, and with 8 = (8, 2) the same with the
                               matrix-core waves copying W into LDS by direct
                               global-to-LDS loads, the producers moving S and
                               R only, 9 = 8 with the producers also copying S
                               that way into three LDS buffers (6 to 9 read as
-                              0 for the other forms); the
+                              0 for the 16-bit forms); the
                               16-bit forms prefetch at least 2 products, and 3
                               only with 8 producers */
 } bf_variant;

@@ -69,9 +69,11 @@ static void release_slot(StagingSlot &s)
 }
 
 // Defaults measured on MI355X at steady state.  Full-width batches (mean f
-// 36) run the wave-specialised schedule (the three-product form on 16 x 16
-// tiles; the split 16-bit forms with 12 producers, 168 against 178 us for
-// the streaming schedule on the gain workload).  Batches of mixed or
+// 36) run the wave-specialised schedule (both FP32 forms on 16 x 16 tiles,
+// the four-product form with W and S copied straight to LDS: 191 against
+// 222 us for 32 x 32 tiles and 12 producers; the split 16-bit forms with 12
+// producers, 168 against 178 us for the streaming schedule on the gain
+// workload).  Batches of mixed or
 // smaller f run one product per workgroup, grouped by W id modulo 8 so that
 // each XCD's L2 holds an eighth of the pool, with staged R stores: on the
 // uneven batch (8192 products, f ~ U{1..36}, 256 W) this took the forms
@@ -90,7 +92,8 @@ static bf_status default_variants(bf_plan p)
                 v = bf_variant{3, 0, 0, 8};   // wave-specialised, 16 x 16 tiles, W copied by the
                                               // matrix-core waves, depth 2, as given
             else if (fp32)
-                v = bf_variant{3, 0, 0, 5};   // wave-specialised, 12 producers, depth 2, as given
+                v = bf_variant{3, 0, 0, 9};   // wave-specialised, 16 x 16 tiles, W copied by the
+                                              // matrix-core waves and S by the producers, as given
             else if (pr == BF_FP16 || pr == BF_BF16)
                 v = bf_variant{3, 0, 0, 4};   // plain 16-bit: wave-specialised, 12 producers
             else
@@ -178,7 +181,9 @@ extern "C" bf_status bf_plan_create(bf_plan *out, const void *w_pool, int32_t n_
             return fail_dev("FP32 W layout", e);
         }
     }
-    if (prec_mask & BF_PREC_BIT(BF_FP32_3M)) {
+    // The three-product layout serves both FP32 forms: the 16 x 16 kernels
+    // of the four-product form read its Wr and Wi as well.
+    if (prec_mask & (BF_PREC_BIT(BF_FP32_3M) | BF_PREC_BIT(BF_FP32))) {
         p->a_3m_stride = bfk::fp32_3m_w_stride(p->pairs);
         const size_t bytes = std::max<size_t>(16, 2 * (size_t)n_w * p->a_3m_stride * sizeof(float));
         e = hipMalloc(&p->a_3m, bytes);
@@ -574,11 +579,11 @@ bfk::LaunchCfg choose_launch(bf_plan p, bf_prec prec, int n, int max_f, bool vec
     cfg.depth = kDepths[ws];
     if (prec == BF_FP32_3M && cfg.producers > 8)
         cfg.producers = 8;   // its two accumulator sets leave registers for 12 waves only
-    // Store fields 6, 7 and 8 (three-product form): 8 matrix-core waves on
-    // 16 x 16 tiles and 8 producers at prefetch depth 1, 2, and 2 with the
-    // matrix-core waves copying W into LDS themselves.  Other forms read
-    // them as 0.
-    cfg.tile16 = prec == BF_FP32_3M && cfg.schedule == 3 && v.store >= 6;
+    // Store fields 6 to 9 (both FP32 forms): 8 matrix-core waves on 16 x 16
+    // tiles and 8 producers at prefetch depth 1 (6) or 2 (7); 8 adds the
+    // matrix-core waves copying W into LDS themselves, 9 the producers
+    // copying S the same way.  The 16-bit forms read them as 0.
+    cfg.tile16 = (prec == BF_FP32_3M || prec == BF_FP32) && cfg.schedule == 3 && v.store >= 6;
     if (cfg.tile16) {
         cfg.producers = 8;
         cfg.depth = v.store >= 7 ? 2 : 1;
@@ -1239,10 +1244,10 @@ extern "C" bf_status bf_autotune(bf_plan p, int32_t batch, const int32_t *w_ids,
             for (int o = 0; o < 2; ++o)
                 cands.push_back(bf_variant{2, w, o, st});
     // (the 16-bit wave-specialised kernel takes batches of one f only; store
-    // fields 6 to 9 exist for the three-product form only)
+    // fields 6 to 9 exist for the FP32 forms only)
     if (!lp || min_f == max_f)
         for (int o = 0; o < 3; ++o)
-            for (int st = 0; st < (prec == BF_FP32_3M ? 10 : 6); ++st)
+            for (int st = 0; st < (lp ? 6 : 10); ++st)
                 cands.push_back(bf_variant{3, 0, o, st});
 
     // Each timed launch records its kernel's own start and end (the plan's

@@ -1369,7 +1369,7 @@ __global__ __launch_bounds__(64 * (kWaves + kProd)) void apply_fp32_ws(
 }
 
 // ---------------------------------------------------------------------------
-// Three-product FP32 form on 16 x 16 tiles (v_mfma_f32_16x16x4_f32, the same
+// FP32 forms on 16 x 16 tiles (v_mfma_f32_16x16x4_f32, the same
 // matrix-core rate as the 32 x 32 x 2 form), with eight matrix-core waves,
 // two per SIMD: a single wave per SIMD loses about a quarter of the matrix
 // core to its own LDS reads and epilogue, which a second wave on the SIMD
@@ -1378,7 +1378,13 @@ __global__ __launch_bounds__(64 * (kWaves + kProd)) void apply_fp32_ws(
 // tiles that share their A operands.  For v_mfma_f32_16x16x4_f32 lane l
 // supplies A[l % 16][l / 16] and B[l / 16][l % 16] (K = 4 flows per step)
 // and receives column l % 16, rows 4 (l / 16) + v of the tile in register v.
+// Both forms read the same operands, Wr and Wi from the 16 x 16 W layout
+// and S as staged; the three-product form keeps three accumulators per
+// tile (Wr Sr, Wi Si, (Wr + Wi)(Sr + Si)), the four-product form (k4) two
+// (Re R, Im R).
 constexpr int kCons16 = 8;
+template <bool k4>
+constexpr int kAcc16 = k4 ? 2 : 3;
 
 __device__ __forceinline__ void mfma3_16(float ar, float ai, float as, f2v b, floatx4 &t1, floatx4 &t2,
                                          floatx4 &t3)
@@ -1388,36 +1394,60 @@ __device__ __forceinline__ void mfma3_16(float ar, float ai, float as, f2v b, fl
     t3 = __builtin_amdgcn_mfma_f32_16x16x4f32(as, b.x + b.y, t3, 0, 0, 0);
 }
 
+// One step of the four-product form on both tiles: Re R += Wr Sr - Wi Si,
+// Im R += Wr Si + Wi Sr (the complex product of Section III written as four
+// real ones).  Each accumulator's second update comes four instructions
+// after its first, so no instruction waits for the one before it.
+__device__ __forceinline__ void mfma4_16(float ar, float ai, f2v b0, f2v b1, floatx4 (&acc)[2][2])
+{
+    acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, b0.x, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, b0.y, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, b1.x, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, b1.y, acc[1][1], 0, 0, 0);
+    acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, b0.y, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, b0.x, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, b1.y, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, b1.x, acc[1][1], 0, 0, 0);
+}
+
 // Row (t, v) of the epilogue of wave cw's two tiles, e = 4 t + v (0..7):
-// Re R = T1 - T2, Im R = (T3 - T1) - T2 into the staged R tile (64 x 60
+// Re R = T1 - T2, Im R = (T3 - T1) - T2 (three-product form) or the two
+// accumulators as they are (k4) into the staged R tile (64 x 60
 // row-major) at antenna 16 rb + 4 (lane / 16) + v, column 32 cb + 16 t +
 // lane % 16; columns 60..63 are not written.
-__device__ __forceinline__ void stage_row_3m16(const floatx4 (&acc)[2][3], int e, int cw, int lane,
-                                               f2v *__restrict__ tile)
+template <bool k4>
+__device__ __forceinline__ void stage_row_16(const floatx4 (&acc)[2][kAcc16<k4>], int e, int cw, int lane,
+                                             f2v *__restrict__ tile)
 {
     const int t = e >> 2;
     const int v = e & 3;
     const int j = 32 * (cw & 1) + 16 * t + (lane & 15);
     const int i = 16 * (cw >> 1) + 4 * (lane >> 4) + v;
-    const floatx4 &t1 = acc[t][0], &t2 = acc[t][1], &t3 = acc[t][2];
-    if (j < kB)
-        tile[i * kB + j] = f2v{t1[v] - t2[v], (t3[v] - t1[v]) - t2[v]};
+    if (j < kB) {
+        if constexpr (k4) {
+            tile[i * kB + j] = f2v{acc[t][0][v], acc[t][1][v]};
+        } else {
+            const floatx4 &t1 = acc[t][0], &t2 = acc[t][1], &t3 = acc[t][2];
+            tile[i * kB + j] = f2v{t1[v] - t2[v], (t3[v] - t1[v]) - t2[v]};
+        }
+    }
 }
 
 // One product's chain for wave cw: `steps` blocks of 4 flows (kFull: all
 // kSteps16Max), operands read from the staged S (row pitch kLdsCols) and
 // the staged W (16 x 16 layout, `plan_steps` steps per block), each step's
 // reads issued three steps ahead of its matrix-core work.  acc[t][m] is the
-// m-th product (Wr Sr, Wi Si, (Wr + Wi)(Sr + Si)) of tile t.  With kEpi, the
+// m-th accumulator of tile t.  With kEpi, the
 // previous product's accumulators `prev` are staged to `prev_tile` one row
 // per step during the chain, so that this wave's epilogue falls between its
 // own matrix-core steps (where the other wave of the SIMD fills the matrix
 // core) instead of after the chain, where both waves of a SIMD would reach
 // it together.
-template <bool kFull, bool kEpi>
-__device__ __forceinline__ void chain_3m16(const f2v *__restrict__ s_lds, const float *__restrict__ w_lds,
-                                           int plan_steps, int steps, int cw, int lane, floatx4 (&acc)[2][3],
-                                           const floatx4 (&prev)[2][3], f2v *__restrict__ prev_tile)
+template <bool k4, bool kFull, bool kEpi>
+__device__ __forceinline__ void chain_16(const f2v *__restrict__ s_lds, const float *__restrict__ w_lds,
+                                         int plan_steps, int steps, int cw, int lane,
+                                         floatx4 (&acc)[2][kAcc16<k4>], const floatx4 (&prev)[2][kAcc16<k4>],
+                                         f2v *__restrict__ prev_tile)
 {
     constexpr int kAhead = 3;
     const int rb = cw >> 1;
@@ -1427,7 +1457,7 @@ __device__ __forceinline__ void chain_3m16(const f2v *__restrict__ s_lds, const 
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
-        for (int m = 0; m < 3; ++m)
+        for (int m = 0; m < kAcc16<k4>; ++m)
             acc[t][m] = floatx4{};
     float ar[kSteps16Max], ai[kSteps16Max];
     f2v b0[kSteps16Max], b1[kSteps16Max];
@@ -1451,31 +1481,36 @@ __device__ __forceinline__ void chain_3m16(const f2v *__restrict__ s_lds, const 
             b1[qn] = col[4 * qn * kLdsCols + 16];
         }
         if (kFull || q < steps) {
-            const float as = ar[q] + ai[q];
-            mfma3_16(ar[q], ai[q], as, b0[q], acc[0][0], acc[0][1], acc[0][2]);
-            mfma3_16(ar[q], ai[q], as, b1[q], acc[1][0], acc[1][1], acc[1][2]);
+            if constexpr (k4) {
+                mfma4_16(ar[q], ai[q], b0[q], b1[q], acc);
+            } else {
+                const float as = ar[q] + ai[q];
+                mfma3_16(ar[q], ai[q], as, b0[q], acc[0][0], acc[0][1], acc[0][2]);
+                mfma3_16(ar[q], ai[q], as, b1[q], acc[1][0], acc[1][1], acc[1][2]);
+            }
         }
         if constexpr (kEpi) {
             if (q < 8)
-                stage_row_3m16(prev, q, cw, lane, prev_tile);
+                stage_row_16<k4>(prev, q, cw, lane, prev_tile);
         }
         __builtin_amdgcn_sched_barrier(0);
     }
 }
 
-template <bool kEpi>
-__device__ __forceinline__ void chain_3m16_any(const f2v *__restrict__ s_lds, const float *__restrict__ w_lds,
-                                               int plan_steps, int f, int cw, int lane, floatx4 (&acc)[2][3],
-                                               const floatx4 (&prev)[2][3], f2v *__restrict__ prev_tile)
+template <bool k4, bool kEpi>
+__device__ __forceinline__ void chain_16_any(const f2v *__restrict__ s_lds, const float *__restrict__ w_lds,
+                                             int plan_steps, int f, int cw, int lane,
+                                             floatx4 (&acc)[2][kAcc16<k4>], const floatx4 (&prev)[2][kAcc16<k4>],
+                                             f2v *__restrict__ prev_tile)
 {
     const int steps = (f + 3) >> 2;
     if (steps == kSteps16Max)
-        chain_3m16<true, kEpi>(s_lds, w_lds, plan_steps, steps, cw, lane, acc, prev, prev_tile);
+        chain_16<k4, true, kEpi>(s_lds, w_lds, plan_steps, steps, cw, lane, acc, prev, prev_tile);
     else
-        chain_3m16<false, kEpi>(s_lds, w_lds, plan_steps, steps, cw, lane, acc, prev, prev_tile);
+        chain_16<k4, false, kEpi>(s_lds, w_lds, plan_steps, steps, cw, lane, acc, prev, prev_tile);
 }
 
-// The matrix-core role of apply_fp32_3m16_ws.  Product k's chain runs with
+// The matrix-core role of the 16 x 16 kernels.  Product k's chain runs with
 // product k - 1's epilogue folded in (two accumulator sets, A for even k, B
 // for odd k); the last product's epilogue gets an iteration of its own, so
 // the R of product k is staged during iteration k + 1 and written out by the
@@ -1517,14 +1552,14 @@ __device__ __forceinline__ void dma_wait()
     __builtin_amdgcn_s_waitcnt(0x0F70);
 }
 
-template <int kProd, bool kDma, int kSBufs, class Lds>
-__device__ __forceinline__ void ws_3m16_consumer(c_item *my, int stride, int n_my, Lds &L,
-                                                 const float *__restrict__ apool, int a_w_stride, int pairs,
-                                                 int cw, int lane)
+template <bool k4, int kProd, bool kDma, int kSBufs, class Lds>
+__device__ __forceinline__ void ws16_consumer(c_item *my, int stride, int n_my, Lds &L,
+                                              const float *__restrict__ apool, int a_w_stride, int pairs, int cw,
+                                              int lane)
 {
     const int plan_steps = fp32_3m16_steps(pairs);
     const float *w16 = apool + fp32_3m16_offset(pairs);
-    floatx4 accA[2][3], accB[2][3];
+    floatx4 accA[2][kAcc16<k4>], accB[2][kAcc16<k4>];
     // With kDma the matrix-core waves copy each product's W themselves: W of
     // product k + 1 into buffer (k + 1) & 1 while chain k runs (that buffer
     // held W of product k - 1, which every matrix-core wave finished before
@@ -1541,7 +1576,7 @@ __device__ __forceinline__ void ws_3m16_consumer(c_item *my, int stride, int n_m
         d = item_at(my, min(1, n_my - 1), stride);
         dma_w16(L.a_buf.v[1], w16 + (size_t)d.w_id * a_w_stride, plan_steps, d.f, cw, lane);
     }
-    chain_3m16_any<false>(L.s_buf[0], L.a_buf.v[0], plan_steps, f, cw, lane, accA, accA, nullptr);
+    chain_16_any<k4, false>(L.s_buf[0], L.a_buf.v[0], plan_steps, f, cw, lane, accA, accA, nullptr);
     int sb = 0;   // S buffer of product k: k % kSBufs
     __builtin_amdgcn_sched_barrier(0);
     f = item_at(my, min(1, n_my - 1), stride).f;
@@ -1553,7 +1588,7 @@ __device__ __forceinline__ void ws_3m16_consumer(c_item *my, int stride, int n_m
         if (k >= n_my) {
 #pragma unroll
             for (int e = 0; e < 8; ++e)
-                stage_row_3m16(accA, e, cw, lane, L.r_buf[(k - 1) & 1]);
+                stage_row_16<k4>(accA, e, cw, lane, L.r_buf[(k - 1) & 1]);
             __syncthreads();
             break;
         }
@@ -1562,8 +1597,8 @@ __device__ __forceinline__ void ws_3m16_consumer(c_item *my, int stride, int n_m
             dma_w16(L.a_buf.v[(k + 1) & 1], w16 + (size_t)d.w_id * a_w_stride, plan_steps, d.f, cw, lane);
         }
         sb = sb + 1 == kSBufs ? 0 : sb + 1;
-        chain_3m16_any<true>(L.s_buf[sb], L.a_buf.v[k & 1], plan_steps, f, cw, lane, accB, accA,
-                             L.r_buf[(k - 1) & 1]);
+        chain_16_any<k4, true>(L.s_buf[sb], L.a_buf.v[k & 1], plan_steps, f, cw, lane, accB, accA,
+                               L.r_buf[(k - 1) & 1]);
         __builtin_amdgcn_sched_barrier(0);
         f = item_at(my, min(k + 1, n_my - 1), stride).f;
         if constexpr (kDma)
@@ -1573,7 +1608,7 @@ __device__ __forceinline__ void ws_3m16_consumer(c_item *my, int stride, int n_m
         if (k >= n_my) {
 #pragma unroll
             for (int e = 0; e < 8; ++e)
-                stage_row_3m16(accB, e, cw, lane, L.r_buf[(k - 1) & 1]);
+                stage_row_16<k4>(accB, e, cw, lane, L.r_buf[(k - 1) & 1]);
             __syncthreads();
             break;
         }
@@ -1582,8 +1617,8 @@ __device__ __forceinline__ void ws_3m16_consumer(c_item *my, int stride, int n_m
             dma_w16(L.a_buf.v[(k + 1) & 1], w16 + (size_t)d.w_id * a_w_stride, plan_steps, d.f, cw, lane);
         }
         sb = sb + 1 == kSBufs ? 0 : sb + 1;
-        chain_3m16_any<true>(L.s_buf[sb], L.a_buf.v[k & 1], plan_steps, f, cw, lane, accA, accB,
-                             L.r_buf[(k - 1) & 1]);
+        chain_16_any<k4, true>(L.s_buf[sb], L.a_buf.v[k & 1], plan_steps, f, cw, lane, accA, accB,
+                               L.r_buf[(k - 1) & 1]);
         __builtin_amdgcn_sched_barrier(0);
         f = item_at(my, min(k + 1, n_my - 1), stride).f;
         if constexpr (kDma)
@@ -1712,14 +1747,14 @@ __device__ __forceinline__ void ws_producer_sdma(c_item *my, int stride, int n_m
     p_store_r<kProd>(item_at(my, n_my - 1, stride).R, L.r_buf[(n_my - 1) & 1], ptid);
 }
 
-// The 16 x 16 three-product kernel with both operands copied by direct
-// global-to-LDS loads: the matrix-core waves copy W (as in
-// apply_fp32_3m16_ws<.., true>), the 8 producer waves copy S and write R.
-__global__ __launch_bounds__(64 * (kCons16 + 8)) void apply_fp32_3m16_ws_sdma(
-    BfHeader *__restrict__ blk, const BfItem *__restrict__ items, int n_items,
-    const void *__restrict__ apool, int a_w_stride, int pairs)
+// The 16 x 16 kernels with both operands copied by direct global-to-LDS
+// loads: the matrix-core waves copy W (as in the kDma kernels below), the 8
+// producer waves copy S and write R.
+template <bool k4>
+__device__ __forceinline__ void ws16_sdma_body(WsLds3<8> &L, BfHeader *__restrict__ blk,
+                                               const BfItem *__restrict__ items, int n_items,
+                                               const void *__restrict__ apool, int a_w_stride, int pairs)
 {
-    __shared__ WsLds3<8> L;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     float2 *sink = sink_of(blk);
@@ -1730,36 +1765,74 @@ __global__ __launch_bounds__(64 * (kCons16 + 8)) void apply_fp32_3m16_ws_sdma(
 
     c_item *my = (c_item *)items + start;
     if (wave < kCons16)
-        ws_3m16_consumer<8, true, 3>(my, stride, n_my, L, static_cast<const float *>(apool), a_w_stride, pairs,
-                                     wave, lane);
+        ws16_consumer<k4, 8, true, 3>(my, stride, n_my, L, static_cast<const float *>(apool), a_w_stride, pairs,
+                                      wave, lane);
     else
         ws_producer_sdma<8>(my, stride, n_my, sink, L);
 }
 
-// kSched 3, three-product form on 16 x 16 tiles: 8 matrix-core waves and
-// kProd producer waves.  S must be 16-byte aligned and the plan's f_max at
-// least 1 (the host routes other batches elsewhere).
+// kSched 3 on 16 x 16 tiles: 8 matrix-core waves and kProd producer waves
+// (with kDma the matrix-core waves copy W themselves).  S must be 16-byte
+// aligned and the plan's f_max at least 1 (the host routes other batches
+// elsewhere).
+template <bool k4, int kProd, int kDepth, bool kDma>
+__device__ __forceinline__ void ws16_body(WsLds<true, kProd> &L, BfHeader *__restrict__ blk,
+                                          const BfItem *__restrict__ items, int n_items,
+                                          const void *__restrict__ apool, int a_w_stride, int pairs)
+{
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    float2 *sink = sink_of(blk);
+    int start, stride;
+    const int n_my = ws_share(n_items, &start, &stride);
+    if (n_my <= 0)
+        return;
+
+    c_item *my = (c_item *)items + start;
+    if (wave < kCons16)
+        ws16_consumer<k4, kProd, kDma, 2>(my, stride, n_my, L, static_cast<const float *>(apool), a_w_stride,
+                                          pairs, wave, lane);
+    else
+        ws_producer<kProd, kDepth, kDma ? 3 : 2, false, kCons16>(my, stride, n_my, sink, L, apool,
+                                                                 a_w_stride, pairs);
+}
+
+// The three-product form (Section III's complex product with three real
+// ones) on 16 x 16 tiles.
+__global__ __launch_bounds__(64 * (kCons16 + 8)) void apply_fp32_3m16_ws_sdma(
+    BfHeader *__restrict__ blk, const BfItem *__restrict__ items, int n_items,
+    const void *__restrict__ apool, int a_w_stride, int pairs)
+{
+    __shared__ WsLds3<8> L;
+    ws16_sdma_body<false>(L, blk, items, n_items, apool, a_w_stride, pairs);
+}
+
 template <int kProd, int kDepth, bool kDma>
 __global__ __launch_bounds__(64 * (kCons16 + kProd)) void apply_fp32_3m16_ws(
     BfHeader *__restrict__ blk, const BfItem *__restrict__ items, int n_items,
     const void *__restrict__ apool, int a_w_stride, int pairs)
 {
     __shared__ WsLds<true, kProd> L;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    float2 *sink = sink_of(blk);
-    int start, stride;
-    const int n_my = ws_share(n_items, &start, &stride);
-    if (n_my <= 0)
-        return;
+    ws16_body<false, kProd, kDepth, kDma>(L, blk, items, n_items, apool, a_w_stride, pairs);
+}
 
-    c_item *my = (c_item *)items + start;
-    if (wave < kCons16)
-        ws_3m16_consumer<kProd, kDma, 2>(my, stride, n_my, L, static_cast<const float *>(apool), a_w_stride,
-                                         pairs, wave, lane);
-    else
-        ws_producer<kProd, kDepth, kDma ? 3 : 2, false, kCons16>(my, stride, n_my, sink, L, apool,
-                                                                 a_w_stride, pairs);
+// The four-product FP32 form on 16 x 16 tiles, reading the W layout of the
+// three-product form (Wr and Wi per lane).
+__global__ __launch_bounds__(64 * (kCons16 + 8)) void apply_fp32_4m16_ws_sdma(
+    BfHeader *__restrict__ blk, const BfItem *__restrict__ items, int n_items,
+    const void *__restrict__ apool, int a_w_stride, int pairs)
+{
+    __shared__ WsLds3<8> L;
+    ws16_sdma_body<true>(L, blk, items, n_items, apool, a_w_stride, pairs);
+}
+
+template <int kProd, int kDepth, bool kDma>
+__global__ __launch_bounds__(64 * (kCons16 + kProd)) void apply_fp32_4m16_ws(
+    BfHeader *__restrict__ blk, const BfItem *__restrict__ items, int n_items,
+    const void *__restrict__ apool, int a_w_stride, int pairs)
+{
+    __shared__ WsLds<true, kProd> L;
+    ws16_body<true, kProd, kDepth, kDma>(L, blk, items, n_items, apool, a_w_stride, pairs);
 }
 
 // ---------------------------------------------------------------------------
@@ -2603,6 +2676,45 @@ static const BfItem *items_of(BfHeader *blk)
    hipLaunchKernelGGL(kernel, grid, block, 0, st, __VA_ARGS__);                      \
     } while (0)
 
+// Schedule 3 on 16 x 16 tiles, both FP32 forms (k4: four products), both
+// reading the three-product W layout.
+template <bool k4>
+static hipError_t launch_ws16(const LaunchCfg &cfg, BfHeader *blk, int n_items, const void *apool,
+                              int a_stride, int pairs, hipStream_t st)
+{
+    const BfItem *items = items_of(blk);
+    const dim3 grid(cfg.grid);
+    const dim3 block(64 * (kCons16 + 8));
+    if (cfg.s_dma) {
+        if constexpr (k4)
+            BF_LAUNCH(cfg, apply_fp32_4m16_ws_sdma, grid, block, st, blk, items, n_items, apool, a_stride, pairs);
+        else
+            BF_LAUNCH(cfg, apply_fp32_3m16_ws_sdma, grid, block, st, blk, items, n_items, apool, a_stride, pairs);
+    } else if (cfg.w_dma) {
+        if constexpr (k4)
+            BF_LAUNCH(cfg, (apply_fp32_4m16_ws<8, 2, true>), grid, block, st, blk, items, n_items, apool,
+                      a_stride, pairs);
+        else
+            BF_LAUNCH(cfg, (apply_fp32_3m16_ws<8, 2, true>), grid, block, st, blk, items, n_items, apool,
+                      a_stride, pairs);
+    } else if (cfg.depth >= 2) {
+        if constexpr (k4)
+            BF_LAUNCH(cfg, (apply_fp32_4m16_ws<8, 2, false>), grid, block, st, blk, items, n_items, apool,
+                      a_stride, pairs);
+        else
+            BF_LAUNCH(cfg, (apply_fp32_3m16_ws<8, 2, false>), grid, block, st, blk, items, n_items, apool,
+                      a_stride, pairs);
+    } else {
+        if constexpr (k4)
+            BF_LAUNCH(cfg, (apply_fp32_4m16_ws<8, 1, false>), grid, block, st, blk, items, n_items, apool,
+                      a_stride, pairs);
+        else
+            BF_LAUNCH(cfg, (apply_fp32_3m16_ws<8, 1, false>), grid, block, st, blk, items, n_items, apool,
+                      a_stride, pairs);
+    }
+    return hipGetLastError();
+}
+
 // Schedule 3 launch: producer waves and S prefetch depth from the variant.
 template <bool k3M>
 static hipError_t launch_ws(const LaunchCfg &cfg, BfHeader *blk, int n_items, const void *apool,
@@ -2610,21 +2722,8 @@ static hipError_t launch_ws(const LaunchCfg &cfg, BfHeader *blk, int n_items, co
 {
     const BfItem *items = items_of(blk);
     const dim3 grid(cfg.grid);
-    if (k3M && cfg.tile16) {
-        if (cfg.s_dma)
-            BF_LAUNCH(cfg, apply_fp32_3m16_ws_sdma, grid, dim3(64 * (kCons16 + 8)), st, blk, items, n_items,
-                      apool, a_stride, pairs);
-        else if (cfg.w_dma)
-            BF_LAUNCH(cfg, (apply_fp32_3m16_ws<8, 2, true>), grid, dim3(64 * (kCons16 + 8)), st, blk,
-                      items, n_items, apool, a_stride, pairs);
-        else if (cfg.depth >= 2)
-            BF_LAUNCH(cfg, (apply_fp32_3m16_ws<8, 2, false>), grid, dim3(64 * (kCons16 + 8)), st, blk,
-                      items, n_items, apool, a_stride, pairs);
-        else
-            BF_LAUNCH(cfg, (apply_fp32_3m16_ws<8, 1, false>), grid, dim3(64 * (kCons16 + 8)), st, blk,
-                      items, n_items, apool, a_stride, pairs);
-        return hipGetLastError();
-    }
+    if (k3M && cfg.tile16)
+        return launch_ws16<false>(cfg, blk, n_items, apool, a_stride, pairs, st);
     if (cfg.producers == 4)
         BF_LAUNCH(cfg, (apply_fp32_ws<k3M, 4, 1>), grid, dim3(64 * 8), st, blk, items,
                   n_items, apool, a_stride, pairs);
@@ -2663,6 +2762,8 @@ static hipError_t launch_fp32_t(const LaunchCfg &cfg, BfHeader *blk, int n_items
                   items, n_items, pd.a_fp32, pd.a_fp32_stride, pd.pairs);
         break;
     case 3:
+        if (cfg.tile16)
+            return launch_ws16<true>(cfg, blk, n_items, (const void *)pd.a_3m, pd.a_3m_stride, pd.pairs, st);
         return launch_ws<false>(cfg, blk, n_items, (const void *)pd.a_fp32, pd.a_fp32_stride, pd.pairs, st);
     default:
         BF_LAUNCH(cfg, (apply_fp32_stream<kVec16, kStage>), dim3(cfg.grid), dim3(kThreads), st, blk,

@@ -15,7 +15,9 @@ def test_launched_schedule_and_symbol():
             "apply_fp32_ws"
         assert bench.kernel_symbol(bf.BF_FP32_3M, bench.launched_schedule(bf.BF_FP32_3M, s), 7) == \
             "apply_fp32_3m16_ws"
-    assert bench.kernel_symbol(bf.BF_FP32, 3, 7) == "apply_fp32_ws"
+    # store fields 6 to 9 run the FP32 forms on 16 x 16 tiles
+    assert bench.kernel_symbol(bf.BF_FP32, 3, 7) == "apply_fp32_4m16_ws"
+    assert bench.kernel_symbol(bf.BF_FP32, 3, 5) == "apply_fp32_ws"
     # the 16-bit forms have no claim schedule
     for p in (bf.BF_FP16, bf.BF_BF16, bf.BF_FP16X2, bf.BF_BF16X2):
         assert bench.kernel_symbol(p, bench.launched_schedule(p, 1)) == "apply_lp_stream"

@@ -75,7 +75,8 @@ def test_four_times_full_width_all_items(form):
     plan.close()
 
 
-@pytest.mark.parametrize("variant", [None, (3, 0, 0, 2), (3, 0, 0, 5), (2, 2, 0, 0), (1, 2, 1, 0)])
+@pytest.mark.parametrize("variant", [None, (3, 0, 0, 2), (3, 0, 0, 5), (3, 0, 0, 8), (3, 0, 0, 9), (2, 2, 0, 0),
+                                     (1, 2, 1, 0)])
 @pytest.mark.parametrize("form", sorted(FORMS))
 def test_pool_without_columns(form, variant):
     """A pool with f_max = 0 (every product is the empty sum): the plan is

@@ -19,7 +19,7 @@ pytestmark = pytest.mark.gpu
 
 CASES = [
     (bf.BF_FP32, (0, 0, 0)), (bf.BF_FP32, (1, 0, 1)), (bf.BF_FP32, (2, 0, 1, 1)),
-    (bf.BF_FP32, (3, 0, 1, 5)),
+    (bf.BF_FP32, (3, 0, 1, 5)), (bf.BF_FP32, (3, 0, 0, 8)), (bf.BF_FP32, (3, 0, 0, 9)),
     (bf.BF_FP32_3M, (0, 0, 2, 1)), (bf.BF_FP32_3M, (3, 0, 0, 1)), (bf.BF_FP32_3M, (3, 0, 0, 7)),
     (bf.BF_FP32_3M, (3, 0, 0, 8)), (bf.BF_FP32_3M, (3, 0, 0, 9)),
     (bf.BF_FP16, (0, 0, 0)), (bf.BF_FP16X2, (2, 0, 1)), (bf.BF_BF16X2, (3, 0, 0, 5)),

@@ -39,9 +39,17 @@ VARIANTS = {
     "ws-xcd-grouped": (3, 0, 2, 1),
     "stream-xcd-grouped": (2, 2, 2),
     "one-per-wg-xcd-grouped": (0, 0, 2),
+    "ws16": (3, 0, 0, 6),
+    "ws16-sorted-depth-2": (3, 0, 1, 7),
+    "ws16-w-copied": (3, 0, 0, 8),
+    "ws16-w-copied-xcd-grouped": (3, 0, 2, 8),
+    "ws16-w-and-s-copied": (3, 0, 0, 9),
 }
+# 16 x 16 tiles, four products per step (store fields 6 to 9)
+WS16 = ["ws16", "ws16-sorted-depth-2", "ws16-w-copied", "ws16-w-and-s-copied"]
 WS_VARIANTS = ["ws-sorted", "ws-8-producers", "ws-8-producers-depth-2", "ws-8-producers-depth-3",
-               "ws-12-producers-asgiven", "ws-12-producers-depth-2"]
+               "ws-12-producers-asgiven", "ws-12-producers-depth-2", "ws16", "ws16-w-copied",
+               "ws16-w-and-s-copied"]
 
 
 @pytest.mark.parametrize("vname", sorted(VARIANTS))
@@ -68,13 +76,15 @@ def test_ragged_all_f(vname, seed):
     assert np.all(R[~nz] == 0), "f = 0 items must be all zeros"
 
 
+@pytest.mark.parametrize("vname", [None] + WS16)
 @pytest.mark.parametrize("f_max", [1, 2, 7, 36])
-def test_small_pools(f_max):
-    """Pools narrower than 36 (odd and even f_max)."""
+def test_small_pools(f_max, vname):
+    """Pools narrower than 36 (odd and even f_max); the 16 x 16 kernels
+    read the three-product W layout, whose offsets follow from f_max."""
     rng = np.random.default_rng(200 + f_max)
     b = wl.random_batch(rng, 50, 3, f_max=f_max)
-    announce(f"pool f_max={f_max} n={b.n}")
-    R = run_batch(b)
+    announce(f"pool f_max={f_max} n={b.n} variant={vname}")
+    R = run_batch(b, variant=VARIANTS[vname] if vname else None)
     err, _ = rel_errors(b, R)
     nz = b.f > 0
     assert np.max(err[nz], initial=0) <= FP32_TOL
@@ -118,13 +128,33 @@ def test_identity_is_exact():
         assert np.all(R[t, f[t]:] == 0)
 
 
-def test_exact_integers_bitwise():
+@pytest.mark.parametrize("vname", [None] + WS16)
+def test_exact_integers_bitwise(vname):
     rng = np.random.default_rng(402)
     b = wl.exact_integer_batch(rng, 200, 5)
-    announce(f"exact integers n={b.n}")
-    R = run_batch(b)
+    announce(f"exact integers n={b.n} variant={vname}")
+    R = run_batch(b, variant=VARIANTS[vname] if vname else None)
     ref = orc.apply(b)
     assert np.array_equal(R.astype(np.complex128), ref)
+
+
+def test_16x16_variants_agree_bitwise():
+    """The four-product 16 x 16 kernels (store fields 6 to 9, every
+    product order) run the same chain, so they agree bit for bit; the
+    32 x 32 kernels group the flows differently and agree within the bar
+    only."""
+    require_gpu()
+    n = bf.bf_device_cu_count() * 3 + 5
+    rng = np.random.default_rng(433)
+    b = wl.random_batch(rng, n, 9, f_values=np.arange(0, 37))
+    announce(f"fp32 16x16 variants bitwise n={n}")
+    ref = run_batch(b, variant=VARIANTS["ws16"])
+    for v in [(3, 0, 0, 7), (3, 0, 0, 8), (3, 0, 2, 8), (3, 0, 0, 9), (3, 0, 2, 9)]:
+        R = run_batch(b, variant=v)
+        assert np.array_equal(R.view(np.uint32), ref.view(np.uint32)), v
+    err, _ = rel_errors(b, ref)
+    nz = b.f > 0
+    assert np.max(err[nz]) <= FP32_TOL and np.all(ref[~nz] == 0)
 
 
 def test_dft_closed_form():
@@ -240,9 +270,10 @@ def test_graph_replay_matches_direct():
     assert np.max(err) <= FP32_TOL
 
 
-@pytest.mark.parametrize("prec,variant", [(bf.BF_FP32, (1, 0, 1)), (bf.BF_FP32_3M, (3, 0, 0, 7)),
-                                          (bf.BF_FP32_3M, (3, 0, 0, 8)), (bf.BF_FP32_3M, (3, 0, 0, 9))],
-                         ids=["fp32-claim", "fp32_3m-ws16", "fp32_3m-ws16-w-copied",
+@pytest.mark.parametrize("prec,variant", [(bf.BF_FP32, (1, 0, 1)), (bf.BF_FP32, (3, 0, 0, 8)),
+                                          (bf.BF_FP32_3M, (3, 0, 0, 7)), (bf.BF_FP32_3M, (3, 0, 0, 8)),
+                                          (bf.BF_FP32_3M, (3, 0, 0, 9))],
+                         ids=["fp32-claim", "fp32-ws16-w-copied", "fp32_3m-ws16", "fp32_3m-ws16-w-copied",
                               "fp32_3m-ws16-w-and-s-copied"])
 def test_graph_launch_inside_a_captured_hip_graph(prec, variant):
     """bf_graph_launch captured into the caller's own hipGraph (torch's
