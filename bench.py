@@ -137,6 +137,20 @@ def probe_copy(mib: int = 1024) -> dict | None:
 
 
 GROUP = 10   # launches per event pair in the kernel timing
+MALL_BYTES = 256 << 20   # the device's memory-side cache (Infinity Cache)
+
+
+def buffer_sets(batch, requested: int) -> int:
+    """Disjoint S/R buffer sets to rotate: at least `requested`, and enough
+    that the S of all sets is twice the memory-side cache, so that no launch
+    reads S an earlier launch left there.  (With three sets the uneven
+    batch's 219 MB of S was largely served from that cache: 64 against 78 us
+    per launch with eight sets.)  At most 16: a batch too small for that is
+    launch-bound anyway."""
+    s_bytes = int(batch.f.astype(np.int64).sum()) * wl.B * 8
+    if s_bytes == 0:
+        return requested
+    return max(requested, min(16, -(-2 * MALL_BYTES // s_bytes)))
 
 
 def settle(step, ms: float, torch) -> int:
@@ -253,7 +267,7 @@ def workload_kernel(batch, prec: int, torch, stream, copies: int, settle_ms: flo
     nbytes = batch.bytes_moved()
     sched = launched_schedule(prec, variant[0])
     return {"prec": bf.PREC_NAMES[prec], "kernel": kernel_symbol(prec, sched, variant[3]),
-            "variant": list(variant), "kernel_us_mean": round(us, 2),
+            "variant": list(variant), "buffer_sets": copies, "kernel_us_mean": round(us, 2),
             "kernel_us_p50": round(float(np.median(ms)) * 1e3, 2),
             "kernel_us_own_events": round(float(np.mean(own)) * 1e3, 2),
             "hbm_gbs": round(nbytes / (us * 1e-6) / 1e9, 1),
@@ -269,7 +283,7 @@ def side_workloads(args, torch, stream) -> dict:
     with per-product gains 10^U(-3, 3)) in the four 16-bit forms."""
     out = {}
     ub = wl.uneven_batch()
-    e = workload_kernel(ub, bf.BF_FP32_3M, torch, stream, args.copies, 200.0, 200)
+    e = workload_kernel(ub, bf.BF_FP32_3M, torch, stream, buffer_sets(ub, args.copies), 200.0, 200)
     e["traffic"] = load_traffic("uneven-fp32_3m", e["kernel"], e["variant"])
     e["workload"] = ub.name
     e["_batch"] = ub
@@ -277,7 +291,7 @@ def side_workloads(args, torch, stream) -> dict:
     gb = wl.gain_batch()
     forms = {}
     for name in ("fp16x2", "bf16x2", "fp16", "bf16"):
-        r = workload_kernel(gb, PRECS[name], torch, stream, args.copies, 200.0, 200)
+        r = workload_kernel(gb, PRECS[name], torch, stream, buffer_sets(gb, args.copies), 200.0, 200)
         r["traffic"] = load_traffic(f"gain-{name}", r["kernel"], r["variant"])
         forms[name] = r
         print(f"[bench] gain workload {name}: {r['kernel_us_mean']} us", file=sys.stderr, flush=True)
@@ -585,7 +599,9 @@ def main(argv=None) -> int:
                     help="arithmetic form (default: FP32, three real products per complex one)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip timing the four-product FP32 kernel alongside")
-    ap.add_argument("--copies", type=int, default=3, help="disjoint S/R buffer sets rotated")
+    ap.add_argument("--copies", type=int, default=3,
+                    help="disjoint S/R buffer sets rotated (at least; more where that many would hold "
+                         "less S than twice the memory-side cache)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="tune the variant before timing")
@@ -634,7 +650,8 @@ def main(argv=None) -> int:
     batch = WORKLOADS[args.workload]()
     print(f"[bench] {args.workload}: {batch.name}, prec {args.prec}", file=sys.stderr, flush=True)
     plan = bf.bf_plan_create(batch.W, bf.BF_PREC_BIT(prec))
-    db = DeviceBatch(batch, copies=args.copies, fill_r=None)
+    copies = buffer_sets(batch, args.copies)
+    db = DeviceBatch(batch, copies=copies, fill_r=None)
     stream = torch.cuda.current_stream()
     tuned = None
     if args.variant:
@@ -645,9 +662,9 @@ def main(argv=None) -> int:
         tuned = bf.bf_autotune(plan, batch.w_ids, batch.f, db.s_ptrs[0], db.r_ptrs[0], prec, reps=5)
     variant = bf.bf_get_variant(plan, prec, bf.batch_bucket(batch.f))
 
-    settle_steps = settle(lambda i: db.apply(plan, prec, copy=i % args.copies), args.settle_ms, torch)
+    settle_steps = settle(lambda i: db.apply(plan, prec, copy=i % copies), args.settle_ms, torch)
     for i in range(args.warmup):
-        db.apply(plan, prec, copy=i % args.copies)
+        db.apply(plan, prec, copy=i % copies)
     torch.cuda.synchronize()
 
     K = args.steps
@@ -656,7 +673,7 @@ def main(argv=None) -> int:
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(K):
-        db.apply(plan, prec, copy=i % args.copies)
+        db.apply(plan, prec, copy=i % copies)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     if torch.distributed.is_available() and torch.distributed.is_initialized():
@@ -668,18 +685,18 @@ def main(argv=None) -> int:
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
     for i in range(K):
         ev[i][0].record(stream)
-        db.apply(plan, prec, copy=i % args.copies)
+        db.apply(plan, prec, copy=i % copies)
         ev[i][1].record(stream)
     torch.cuda.synchronize()
     step_ms = np.array([a.elapsed_time(b) for a, b in ev])
-    kern_ms, kern_own = kernel_time(plan, db, batch, prec, K, args.copies, torch, stream)
+    kern_ms, kern_own = kernel_time(plan, db, batch, prec, K, copies, torch, stream)
     kern_s = float(np.mean(kern_ms)) / 1e3
 
     compare = None
     if prec == bf.BF_FP32_3M and not args.no_compare:
         # The four-product FP32 form on the same workload, kernel time only.
         plan4 = bf.bf_plan_create(batch.W, bf.BF_PREC_BIT(bf.BF_FP32))
-        k4, _ = kernel_time(plan4, db, batch, bf.BF_FP32, K, args.copies, torch, stream)
+        k4, _ = kernel_time(plan4, db, batch, bf.BF_FP32, K, copies, torch, stream)
         v4 = bf.bf_get_variant(plan4, bf.BF_FP32, bf.batch_bucket(batch.f))
         plan4.close()
         t4 = float(np.mean(k4)) / 1e3
@@ -693,7 +710,7 @@ def main(argv=None) -> int:
         # The 2-term split FP16 form (FP32-class accuracy from 16-bit matrix
         # cores) on the same workload, kernel time only, against this form.
         plans = bf.bf_plan_create(batch.W, bf.BF_PREC_BIT(bf.BF_FP16X2))
-        ks, _ = kernel_time(plans, db, batch, bf.BF_FP16X2, K, args.copies, torch, stream)
+        ks, _ = kernel_time(plans, db, batch, bf.BF_FP16X2, K, copies, torch, stream)
         vs = bf.bf_get_variant(plans, bf.BF_FP16X2, bf.batch_bucket(batch.f))
         plans.close()
         split = {"prec": "fp16x2", "kernel_us_mean": round(float(np.mean(ks)) * 1e3, 2),
@@ -787,7 +804,7 @@ def main(argv=None) -> int:
                    "f": int(batch.f.max()) if batch.f.min() == batch.f.max() else "U{1..36}",
                    "prec": args.prec, "variant": {"schedule": variant[0], "wg_per_cu": variant[1],
                                                   "order": variant[2], "store": variant[3]},
-                   "buffer_sets": args.copies,
+                   "buffer_sets": copies,
                    "settle": {"ms": args.settle_ms, "steps": settle_steps}},
         "latency_us": {"p50": round(float(np.percentile(step_ms, 50)) * 1e3, 2),
                        "p99": round(float(np.percentile(step_ms, 99)) * 1e3, 2)},

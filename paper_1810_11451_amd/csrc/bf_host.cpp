@@ -68,17 +68,20 @@ static void release_slot(StagingSlot &s)
     s = StagingSlot{};
 }
 
-// Defaults measured on MI355X at steady state.  Full-width batches (mean f
-// 36) run the wave-specialised schedule (both FP32 forms on 16 x 16 tiles,
-// the four-product form with W and S copied straight to LDS: 191 against
-// 222 us for 32 x 32 tiles and 12 producers; the split 16-bit forms with 12
+// Defaults measured on MI355X at steady state, with S not left in the
+// memory-side cache by earlier launches.  Full-width batches (mean f 36) run
+// the wave-specialised schedule (both FP32 forms on 16 x 16 tiles, the
+// four-product form with W and S copied straight to LDS: 191 against 222 us
+// for 32 x 32 tiles and 12 producers; the split 16-bit forms with 12
 // producers, 168 against 178 us for the streaming schedule on the gain
-// workload).  Batches of mixed or
-// smaller f run one product per workgroup, grouped by W id modulo 8 so that
-// each XCD's L2 holds an eighth of the pool, with staged R stores: on the
-// uneven batch (8192 products, f ~ U{1..36}, 256 W) this took the forms
-// from 66.7 / 90.2 / 74.9 / 82.7 us (three-product, four-product, FP16x2,
-// FP16; caller order, direct stores) to 65.4 / 75.6 / 61.3 / 54.1 us.
+// workload).  Batches of mixed or smaller f: the FP32 forms run the same
+// 16 x 16 kernel with items grouped by W id modulo 8, so that each XCD's L2
+// holds an eighth of the pool (uneven batch, 8192 products, f ~ U{1..36},
+// 256 W: 69.0 against 77.4 us for one product per workgroup, grouped; the
+// serving loop's closed-loop capacity 3.54-3.57 M against 3.14-3.22 M
+// requests/s); the 16-bit forms, whose wave-specialised kernel takes one f
+// per batch, run one product per workgroup, grouped the same way, with
+// staged R stores (FP16x2 74.4 us on the uneven batch).
 static bf_status default_variants(bf_plan p)
 {
     for (int pr = 0; pr < kPrecCount; ++pr)
@@ -86,7 +89,10 @@ static bf_status default_variants(bf_plan p)
             bf_variant v{};
             const bool full = b == kBucketCount - 1;
             const bool fp32 = pr == BF_FP32 || pr == BF_FP32_3M;
-            if (!full)
+            if (!full && fp32)
+                v = bf_variant{3, 0, 2, 9};   // wave-specialised, 16 x 16 tiles, W and S copied
+                                              // to LDS, grouped by W id mod 8
+            else if (!full)
                 v = bf_variant{0, 0, 2, 1};   // one per workgroup, grouped by W id mod 8, staged
             else if (pr == BF_FP32_3M)
                 v = bf_variant{3, 0, 0, 8};   // wave-specialised, 16 x 16 tiles, W copied by the
