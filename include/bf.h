@@ -229,8 +229,12 @@ bf_status bf_graph_destroy(bf_graph graph);
  * start and end events the kernel records itself: host packing, upload and
  * the queue's gaps are not timed) and stores the fastest for (prec, f
  * bucket) in the plan, with that duration in microseconds (*best_us);
- * bf_apply uses it from then on.  The table can be saved to and loaded
- * from a text file. */
+ * bf_apply uses it from then on.  The trials launch the same batch again
+ * and again: where its S is small enough for the device's memory-side
+ * cache (256 MB on MI355X) to keep between launches, they time S read from
+ * that cache, which can favour other variants than S read from HBM does
+ * (tune on a batch whose S exceeds it, or on several, for streaming use).
+ * The table can be saved to and loaded from a text file. */
 typedef struct {
     int32_t schedule;      /* 0: one product per workgroup; 1: persistent, atomic claim;
                               2: persistent, static share per XCD, next S prefetched;

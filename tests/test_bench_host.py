@@ -71,3 +71,22 @@ def test_roof_follows_issued_work():
     assert fl[bf.BF_FP32]["compute_us"] > fl[bf.BF_FP32]["hbm_us"]
     assert fl[bf.BF_FP32_3M]["compute_us"] < fl[bf.BF_FP32_3M]["hbm_us"]
     assert fl[bf.BF_FP16X2]["compute_us"] < fl[bf.BF_FP16X2]["hbm_us"]
+
+
+def test_buffer_sets_keep_s_out_of_the_memory_side_cache():
+    """The timed workloads rotate enough disjoint buffer sets that their S
+    is at least twice the 256 MB memory-side cache (at most 16 sets), so no
+    launch reads S an earlier launch left there."""
+    from paper_1810_11451_amd import workloads as wl
+
+    def s_bytes(b):
+        return int(b.f.astype("int64").sum()) * wl.B * 8
+
+    for b in (wl.full_width_batch(), wl.uneven_batch(), wl.gain_batch()):
+        n = bench.buffer_sets(b, 3)
+        assert n >= 3 and n * s_bytes(b) >= 2 * bench.MALL_BYTES, (b.name, n)
+        assert (n - 1) * s_bytes(b) < 2 * bench.MALL_BYTES or n == 3
+    assert bench.buffer_sets(wl.uneven_batch(), 3) == 8
+    assert bench.buffer_sets(wl.full_width_batch(), 3) == 3
+    assert bench.buffer_sets(wl.single_w_batch(), 3) == 16     # capped: launch-bound anyway
+    assert bench.buffer_sets(wl.uneven_batch(), 10) == 10      # never fewer than asked
