@@ -88,7 +88,7 @@ typedef struct bf_filter_s *bf_filter;
  * entry at f_max = 36 the FP32 form takes 36,864 bytes and the
  * three-product layout 36,864 (built for BF_FP32 as well, whose 16 x 16
  * kernels read it), the 16-bit forms 20,480 (plain) plus 10,240 per part
- * of the compact layout. */
+ * of the compact layout.
  *   out       receives the plan handle
  *   w_pool    host complex64 [n_w][64][f_max]; may be freed on return
  *   n_w       number of pool entries, >= 1

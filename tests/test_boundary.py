@@ -31,6 +31,20 @@ def L():
     return bf.lib()
 
 
+@pytest.mark.parametrize("header", ["bf.h", "bf_serve_host.h"])
+@pytest.mark.parametrize("lang,std,compiler", [("c", "-std=c99", "gcc"), ("c++", "-std=c++17", "g++")])
+def test_headers_compile_on_their_own(header, lang, std, compiler):
+    """Each public header is valid C and C++ by itself (a stray comment end
+    or a missing include shows up here, not only in the library build)."""
+    import shutil
+    import subprocess
+    if shutil.which(compiler) is None:
+        pytest.skip(f"no {compiler}")
+    r = subprocess.run([compiler, std, "-fsyntax-only", "-Wall", "-Werror", "-x", lang,
+                        str(ROOT / "include" / header)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
 def test_header_declares_entry_points():
     names = declared_functions()
     for must in ("bf_plan_create", "bf_plan_destroy", "bf_apply", "bf_status_str", "bf_last_error",
