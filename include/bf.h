@@ -254,7 +254,13 @@ typedef struct {
     int32_t order;         /* 0: as given; 1: longest f first, then by W id;
                               2: grouped by W id modulo 8 (each of the 8 XCDs
                               then works on an eighth of the pool), caller order
-                              within a group */
+                              within a group; 3: grouped by W id modulo 8 and
+                              by W id within a group, and on schedule 3 dealt
+                              to the workgroups in contiguous blocks, so that
+                              a workgroup's consecutive products mostly share
+                              their W (the kernels that copy W themselves,
+                              store 8 and 9, then copy it once per run);
+                              bf_apply_noalloc keeps the caller's order */
     int32_t store;         /* schedules 0 and 2: 0 = lanes write their accumulators
                               directly, 1 = each wave stages its 16 rows of R in LDS
                               and writes them as contiguous 16-byte stores;

@@ -59,6 +59,8 @@ static void release_slot(StagingSlot &s)
         (void)hipEventSynchronize(s.ev);
     if (s.host)
         (void)hipHostFree(s.host);
+    if (s.sorted)
+        (void)hipHostFree(s.sorted);
     if (s.dev)
         (void)hipFree(s.dev);
     if (s.ev)
@@ -70,17 +72,24 @@ static void release_slot(StagingSlot &s)
 
 // Defaults measured on MI355X at steady state, with S not left in the
 // memory-side cache by earlier launches.  Full-width batches (mean f 36) run
-// the wave-specialised schedule (both FP32 forms on 16 x 16 tiles, the
-// four-product form with W and S copied straight to LDS: 191 against 222 us
-// for 32 x 32 tiles and 12 producers; the split 16-bit forms with 12
-// producers, 168 against 178 us for the streaming schedule on the gain
+// the wave-specialised schedule: both FP32 forms on 16 x 16 tiles with the
+// matrix-core waves copying W into LDS, the items sorted by W id (order 1;
+// at one f it sorts by W only), so that a workgroup's consecutive products
+// mostly share W and copy it once (three-product kernel 163.8-166.9 against
+// 167.4-171.4 us in the caller's order; whole-job throughput the same or
+// better, where order 3 lost 4% to per-step costs of the apply path; the
+// four-product form, with S copied to LDS too, 187.3-189.7 us, against 222
+// us for 32 x 32 tiles and 12 producers); the split 16-bit forms with 12
+// producers (168 against 178 us for the streaming schedule on the gain
 // workload).  Batches of mixed or smaller f: the FP32 forms run the same
-// 16 x 16 kernel with items grouped by W id modulo 8, so that each XCD's L2
-// holds an eighth of the pool (uneven batch, 8192 products, f ~ U{1..36},
-// 256 W: 69.0 against 77.4 us for one product per workgroup, grouped; the
-// serving loop's closed-loop capacity 3.54-3.57 M against 3.14-3.22 M
-// requests/s); the 16-bit forms, whose wave-specialised kernel takes one f
-// per batch, run one product per workgroup, grouped the same way, with
+// 16 x 16 kernels with W and S copied; the three-product form with the items
+// grouped by W id modulo 8, so that each XCD's L2 holds an eighth of the
+// pool (uneven batch, 8192 products, f ~ U{1..36}, 256 W: 69.0 against 77.4
+// us for one product per workgroup, and serving capacity 3.54-3.57 M
+// against 3.14-3.22 M requests/s; order 3 gains under 1% there), the
+// four-product form dealt in W blocks (order 3: 81.0 against 85.1 us for
+// order 2); the 16-bit forms, whose wave-specialised kernel takes one f per
+// batch, run one product per workgroup, grouped by W id modulo 8, with
 // staged R stores (FP16x2 74.4 us on the uneven batch).
 static bf_status default_variants(bf_plan p)
 {
@@ -89,17 +98,19 @@ static bf_status default_variants(bf_plan p)
             bf_variant v{};
             const bool full = b == kBucketCount - 1;
             const bool fp32 = pr == BF_FP32 || pr == BF_FP32_3M;
-            if (!full && fp32)
+            if (!full && pr == BF_FP32_3M)
                 v = bf_variant{3, 0, 2, 9};   // wave-specialised, 16 x 16 tiles, W and S copied
                                               // to LDS, grouped by W id mod 8
+            else if (!full && fp32)
+                v = bf_variant{3, 0, 3, 9};   // the same, dealt to the workgroups in W blocks
             else if (!full)
                 v = bf_variant{0, 0, 2, 1};   // one per workgroup, grouped by W id mod 8, staged
             else if (pr == BF_FP32_3M)
-                v = bf_variant{3, 0, 0, 8};   // wave-specialised, 16 x 16 tiles, W copied by the
-                                              // matrix-core waves, depth 2, as given
+                v = bf_variant{3, 0, 1, 8};   // wave-specialised, 16 x 16 tiles, W copied by the
+                                              // matrix-core waves, depth 2, sorted by W id
             else if (fp32)
-                v = bf_variant{3, 0, 0, 9};   // wave-specialised, 16 x 16 tiles, W copied by the
-                                              // matrix-core waves and S by the producers, as given
+                v = bf_variant{3, 0, 1, 9};   // wave-specialised, 16 x 16 tiles, W copied by the
+                                              // matrix-core waves and S by the producers, by W id
             else if (pr == BF_FP16 || pr == BF_BF16)
                 v = bf_variant{3, 0, 0, 4};   // plain 16-bit: wave-specialised, 12 producers
             else
@@ -246,7 +257,10 @@ extern "C" bf_status bf_plan_create(bf_plan *out, const void *w_pool, int32_t n_
     // than later ones, which the first launches of a fresh plan paid.
     for (StagingSlot &slot : p->ring) {
         std::memset(slot.host, 0, slot.cap);
+        std::memset(slot.sorted, 0, slot.sorted_cap);
         e = hipMemcpyAsync(slot.dev, slot.host, slot.cap, hipMemcpyHostToDevice, p->copy_stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(slot.dev, slot.sorted, slot.sorted_cap, hipMemcpyHostToDevice, p->copy_stream);
         if (e != hipSuccess)
             return fail_dev("hipMemcpyAsync(staging)", e);
     }
@@ -490,7 +504,7 @@ static void read_env(bf_plan p)
         char tail = 0;
         const int got = sscanf(fv, "%d:%d:%d:%d%c", &v.schedule, &v.wg_per_cu, &v.order, &v.store, &tail);
         const bool ok = got == 4 && v.schedule >= 0 && v.schedule <= 3 && v.wg_per_cu >= 0 &&
-                        v.wg_per_cu <= 64 && v.order >= 0 && v.order <= 2 && v.store >= 0 &&
+                        v.wg_per_cu <= 64 && v.order >= 0 && v.order <= 3 && v.store >= 0 &&
                         v.store <= (v.schedule == 3 ? 9 : 1);
         if (ok) {
             p->env_force_set = true;
@@ -506,17 +520,50 @@ static void read_env(bf_plan p)
         p->tune_cache = tc;
 }
 
-// Orders items longest f first and, for equal f, by W id (so that a
-// persistent workgroup keeps its W operands across consecutive items).
-// Two stable counting sorts: by W id, then by f descending.
 // Product orders of the variants (items carry pool W ids at this point):
 //   1: longest f first, then by W id (counting sorts; stable);
 //   2: grouped by W id modulo 8, caller order within each group.  The
 //      kernels give each of the 8 XCDs one contiguous eighth of the item
 //      list, so this lets each XCD's L2 hold the operands of an eighth of
-//      the pool only.
-void order_items(const BfItem *in, BfItem *out, int n, int n_w, std::vector<int> &scratch, int mode)
+//      the pool only;
+//   3: grouped by W id modulo 8 and by W id within each group (one stable
+//      counting sort), and given `deal` (ws_deal's table for the
+//      wave-specialised schedule's grid) dealt to its workgroups in
+//      contiguous blocks in the same pass, so that consecutive products of
+//      a workgroup mostly share their W and copy it into LDS once.
+// The sort key of order 3: W ids of one residue modulo 8 together, in
+// increasing order within it.
+static inline int order3_key(int w, int g8) { return (w % 8) * g8 + w / 8; }
+
+// ws_deal's table for n items on a grid of G, rebuilt only when n or G
+// change (a caller that launches batches of one size builds it once).
+static const int *deal_table(DealTable &t, int n, int G)
 {
+    if (t.n != n || t.g != G) {
+        t.pos.resize((size_t)n);
+        ws_deal_table(t.pos.data(), n, G);
+        t.n = n;
+        t.g = G;
+    }
+    return t.pos.data();
+}
+
+void order_items(const BfItem *in, BfItem *out, int n, int n_w, std::vector<int> &scratch, int mode,
+                 const int *deal)
+{
+    if (mode == 3) {
+        const int g8 = (n_w + 7) / 8;
+        scratch.assign((size_t)8 * g8 + 1, 0);
+        for (int t = 0; t < n; ++t)
+            scratch[(size_t)order3_key(in[t].w_id, g8) + 1]++;
+        for (int k = 0; k < 8 * g8; ++k)
+            scratch[(size_t)k + 1] += scratch[(size_t)k];
+        for (int t = 0; t < n; ++t) {
+            const int s = scratch[(size_t)order3_key(in[t].w_id, g8)]++;
+            out[deal ? deal[s] : s] = in[t];
+        }
+        return;
+    }
     if (mode == 2) {
         constexpr int kGroups = 8;
         int cnt[kGroups + 1] = {0};
@@ -666,6 +713,15 @@ bf_status reserve_staging(bf_plan p, int n)
         bf_status s = ensure_slot(slot, block_bytes(n) + (size_t)n * sizeof(BfReqRec));
         if (s != BF_OK)
             return s;
+        if (slot.sorted_cap < slot.cap) {   // where ordered blocks are written
+            if (slot.sorted)
+                (void)hipHostFree(slot.sorted);
+            slot.sorted = nullptr;
+            slot.sorted_cap = 0;
+            if (hipHostMalloc(&slot.sorted, slot.cap, hipHostMallocDefault) != hipSuccess)
+                return bf_fail(BF_ERR_OOM, "pinned staging of %zu bytes", slot.cap);
+            slot.sorted_cap = slot.cap;
+        }
     }
     return BF_OK;
 }
@@ -695,12 +751,29 @@ static bf_status upload_and_launch(bf_plan p, bf_prec prec, int n, const FillSta
                                                kSinkBytes);
     const bool uniform_f = fs.min_f == fs.max_f;
     bf_variant chosen = pick_variant(p, prec, batch_bucket(fs.sum_f, n), force);
-    if (chosen.order >= 1 && n > 1 && may_order) {
-        p->sort_tmp.resize((size_t)n);
-        order_items(items, p->sort_tmp.data(), n, p->n_w, p->sort_scratch, chosen.order);
-        std::memcpy(items, p->sort_tmp.data(), (size_t)n * sizeof(BfItem));
-    }
     bfk::LaunchCfg cfg = choose_launch(p, prec, n, fs.max_f, fs.vec16, uniform_f, &chosen);
+    // The ordered block goes to the slot's second pinned buffer (header
+    // copied, items written in order there) and is uploaded from it: no copy
+    // back into the first one.
+    const void *upload = slot.host;
+    if (chosen.order >= 1 && n > 1 && may_order) {
+        if (slot.sorted_cap < bytes) {
+            if (slot.sorted)
+                (void)hipHostFree(slot.sorted);
+            slot.sorted = nullptr;
+            slot.sorted_cap = 0;
+            if (hipHostMalloc(&slot.sorted, slot.cap, hipHostMallocDefault) != hipSuccess)
+                return bf_fail(BF_ERR_OOM, "pinned staging of %zu bytes", slot.cap);
+            slot.sorted_cap = slot.cap;
+        }
+        std::memcpy(slot.sorted, slot.host, sizeof(BfHeader));
+        BfItem *dst = reinterpret_cast<BfItem *>(static_cast<char *>(slot.sorted) + sizeof(BfHeader) + kSinkBytes);
+        const bool deal = chosen.order == 3 && cfg.schedule == 3;
+        order_items(items, dst, n, p->n_w, p->sort_scratch, chosen.order,
+                    deal ? deal_table(p->deal, n, cfg.grid) : nullptr);
+        items = dst;
+        upload = slot.sorted;
+    }
     cfg.ev_start = p->kev_start;
     cfg.ev_stop = p->kev_stop;
     log_launch(p, prec, n, cfg, chosen, "apply");
@@ -708,7 +781,7 @@ static bf_status upload_and_launch(bf_plan p, bf_prec prec, int n, const FillSta
         *grid_out = cfg.grid;
     map_slots(p, items, n);
 
-    hipError_t e = hipMemcpyAsync(dev_blk, slot.host, bytes, hipMemcpyHostToDevice, copy_st);
+    hipError_t e = hipMemcpyAsync(dev_blk, upload, bytes, hipMemcpyHostToDevice, copy_st);
     if (e != hipSuccess)
         return bf_fail(BF_ERR_DEVICE, "hipMemcpyAsync(descriptors): %s", hipGetErrorString(e));
     if (copy_st != st) {
@@ -734,9 +807,11 @@ static bf_status upload_and_launch(bf_plan p, bf_prec prec, int n, const FillSta
 }
 
 // Record-level form of order_items (mode 1: by W id, then f descending;
-// mode 2: grouped by W id modulo 8).  Every item of a record shares its W id
-// and f, so the items come out in the order order_items gives them.
-static void order_records(std::vector<BfReqRec> &recs, std::vector<BfReqRec> &tmp, int mode)
+// mode 2: grouped by W id modulo 8; mode 3: grouped by W id modulo 8, by W
+// id within a group, the dealing to workgroups left to the expansion
+// kernel).  Every item of a record shares its W id and f, so the items come
+// out in the order order_items gives them.
+static void order_records(std::vector<BfReqRec> &recs, std::vector<BfReqRec> &tmp, int mode, int n_w)
 {
     const size_t n = recs.size();
     tmp.resize(n);
@@ -750,6 +825,13 @@ static void order_records(std::vector<BfReqRec> &recs, std::vector<BfReqRec> &tm
         for (const BfReqRec &q : recs)
             tmp[cnt[q.w_id % kGroups]++] = q;
         recs.swap(tmp);
+        return;
+    }
+    if (mode == 3) {
+        const int g8 = (n_w + 7) / 8;
+        std::stable_sort(recs.begin(), recs.end(), [g8](const BfReqRec &a, const BfReqRec &b) {
+            return order3_key(a.w_id, g8) < order3_key(b.w_id, g8);
+        });
         return;
     }
     std::stable_sort(recs.begin(), recs.end(), [](const BfReqRec &a, const BfReqRec &b) {
@@ -784,8 +866,9 @@ bf_status enqueue_requests(bf_plan p, bf_prec prec, std::vector<BfReqRec> &recs,
         return s;
     bf_variant chosen = pick_variant(p, prec, batch_bucket(fs.sum_f, n_items), nullptr);
     if (chosen.order >= 1 && n_recs > 1)
-        order_records(recs, p->rec_tmp, chosen.order);
+        order_records(recs, p->rec_tmp, chosen.order, p->n_w);
     bfk::LaunchCfg cfg = choose_launch(p, prec, n_items, fs.max_f, fs.vec16, fs.min_f == fs.max_f, &chosen);
+    const int deal_grid = chosen.order == 3 && cfg.schedule == 3 ? cfg.grid : 0;
     cfg.ev_start = p->kev_start;
     cfg.ev_stop = p->kev_stop;
     log_launch(p, prec, n_items, cfg, chosen, "serve");
@@ -812,7 +895,7 @@ bf_status enqueue_requests(bf_plan p, bf_prec prec, std::vector<BfReqRec> &recs,
     if (e != hipSuccess)
         return bf_fail(BF_ERR_DEVICE, "update ordering: %s", hipGetErrorString(e));
     e = bfk::launch_expand(reinterpret_cast<const BfReqRec *>(static_cast<char *>(slot.host_dev) + rec_off),
-                           n_recs, reinterpret_cast<BfHeader *>(dev_blk), n_items, st);
+                           n_recs, reinterpret_cast<BfHeader *>(dev_blk), n_items, deal_grid, st);
     if (e == hipSuccess)
         e = launch_for_plan(p, cfg, reinterpret_cast<BfHeader *>(dev_blk), n_items, st);
     if (e != hipSuccess)
@@ -1110,11 +1193,13 @@ extern "C" bf_status bf_graph_create(bf_graph *out, bf_plan p, int32_t batch, co
         std::lock_guard<std::mutex> lk(p->mu);
         v = pick_variant(p, prec, batch_bucket(sum_f, batch), nullptr);
     }
+    bfk::LaunchCfg cfg = choose_launch(p, prec, batch, max_f, vec16, min_f == max_f, &v);
+    DealTable dt;
     if (v.order >= 1)
-        order_items(raw.data(), items.data(), batch, p->n_w, scratch, v.order);
+        order_items(raw.data(), items.data(), batch, p->n_w, scratch, v.order,
+                    v.order == 3 && cfg.schedule == 3 ? deal_table(dt, batch, cfg.grid) : nullptr);
     else
         items = raw;
-    bfk::LaunchCfg cfg = choose_launch(p, prec, batch, max_f, vec16, min_f == max_f, &v);
     {
         std::lock_guard<std::mutex> lk(p->mu);
         log_launch(p, prec, batch, cfg, v, "graph");
@@ -1187,7 +1272,7 @@ extern "C" bf_status bf_graph_destroy(bf_graph g)
 static bool valid_variant(const bf_variant &v)
 {
     return v.schedule >= 0 && v.schedule <= 3 && v.wg_per_cu >= 0 && v.wg_per_cu <= 64 &&
-           v.order >= 0 && v.order <= 2 && v.store >= 0 && v.store <= (v.schedule == 3 ? 9 : 1);
+           v.order >= 0 && v.order <= 3 && v.store >= 0 && v.store <= (v.schedule == 3 ? 9 : 1);
 }
 
 extern "C" bf_status bf_set_variant(bf_plan p, bf_prec prec, int32_t bucket, const bf_variant *v)
@@ -1240,7 +1325,7 @@ extern "C" bf_status bf_autotune(bf_plan p, int32_t batch, const int32_t *w_ids,
 
     std::vector<bf_variant> cands;
     for (int st = 0; st < 2; ++st)
-        for (int o = 0; o < 3; ++o)
+        for (int o = 0; o < 4; ++o)
             cands.push_back(bf_variant{0, 0, o, st});
     const int per_cu[] = {1, 2, 3, 4, 6};
     for (int w : per_cu)
@@ -1252,7 +1337,7 @@ extern "C" bf_status bf_autotune(bf_plan p, int32_t batch, const int32_t *w_ids,
     // (the 16-bit wave-specialised kernel takes batches of one f only; store
     // fields 6 to 9 exist for the FP32 forms only)
     if (!lp || min_f == max_f)
-        for (int o = 0; o < 3; ++o)
+        for (int o = 0; o < 4; ++o)
             for (int st = 0; st < (lp ? 6 : 10); ++st)
                 cands.push_back(bf_variant{3, 0, o, st});
 

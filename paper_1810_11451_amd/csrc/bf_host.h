@@ -33,9 +33,17 @@ struct StagingSlot {
     void *host_dev = nullptr;   // host's device-side address (kernels read records there)
     void *dev = nullptr;
     size_t cap = 0;
+    void *sorted = nullptr;     // pinned block the ordered items are written to and uploaded from
+    size_t sorted_cap = 0;
     hipEvent_t copied = nullptr;
     hipEvent_t ev = nullptr;
     bool launched = false;   // ev has been recorded after a launch
+};
+
+// Dealt positions of order 3 (ws_deal) for n items on a grid of g.
+struct DealTable {
+    int n = -1, g = -1;
+    std::vector<int> pos;
 };
 
 struct bf_plan_s {
@@ -90,9 +98,9 @@ struct bf_plan_s {
     size_t ring_next = 0;
     bf_variant table[kPrecCount][kBucketCount];
     float tuned_us[kPrecCount][kBucketCount] = {};   // measured by autotune or loaded; 0: default
-    std::vector<BfItem> sort_tmp;
     std::vector<BfReqRec> rec_tmp;
     std::vector<int> sort_scratch;
+    DealTable deal;
 };
 
 struct FillStats {
@@ -121,7 +129,8 @@ public:
 };
 using FillFn = std::function<FillStats(BfItem *)>;
 
-void order_items(const BfItem *in, BfItem *out, int n, int n_w, std::vector<int> &scratch, int mode);
+void order_items(const BfItem *in, BfItem *out, int n, int n_w, std::vector<int> &scratch, int mode,
+                 const int *deal = nullptr);
 bfk::LaunchCfg choose_launch(bf_plan p, bf_prec prec, int n, int max_f, bool vec16,
                              bool uniform_f, const bf_variant *force);
 bf_status reserve_staging(bf_plan p, int n);

@@ -50,6 +50,66 @@ struct BfReqRec {
 static_assert(sizeof(BfReqRec) == 32, "BfReqRec layout");
 static_assert(sizeof(BfHeader) == 64, "BfHeader layout");
 
+// Position in the item list of the i-th of n items when the items are dealt
+// to the G workgroups of a wave-specialised launch in contiguous blocks.
+// That schedule splits the list into min(G, 8) contiguous parts, one per
+// XCD (workgroup b runs on XCD b % 8), and workgroup j of part x, one of nb
+// in that part, takes positions lo + j, lo + j + nb, lo + j + 2 nb, ...
+// (bfk::ws_share).  Dealing the part's items in order to its workgroups,
+// the first ones to workgroup 0, the next to workgroup 1 and so on, puts
+// items that are consecutive in the list, for instance of one W, in
+// consecutive products of one workgroup.  A bijection of 0 .. n - 1.
+__host__ __device__ inline int ws_deal(int i, int n, int G)
+{
+    const int X = G < 8 ? G : 8;
+    if (X <= 0)
+        return i;
+    const int q = n / X, r = n % X;
+    // part x holds positions lo .. lo + cnt - 1
+    const int x = i < (q + 1) * r ? i / (q + 1) : r + (q > 0 ? (i - (q + 1) * r) / q : 0);
+    const int lo = x * q + (x < r ? x : r);
+    const int cnt = q + (x < r ? 1 : 0);
+    const int nb = G / X + (x < G % X ? 1 : 0);
+    const int s = i - lo;
+    const int a = cnt / nb, b = cnt % nb;   // workgroups j < b take a + 1 items, the others a
+    int j, k;
+    if (s < b * (a + 1)) {
+        j = s / (a + 1);
+        k = s % (a + 1);
+    } else {
+        const int s2 = s - b * (a + 1);
+        j = b + s2 / a;
+        k = s2 % a;
+    }
+    return lo + j + k * nb;
+}
+
+// ws_deal as a table on the host: pos[i] = ws_deal(i, n, G) for every i,
+// walking the parts and workgroup blocks with running offsets instead of
+// ws_deal's divisions per item.
+inline void ws_deal_table(int *pos, int n, int G)
+{
+    const int X = G < 8 ? G : 8;
+    if (X <= 0) {
+        for (int i = 0; i < n; ++i)
+            pos[i] = i;
+        return;
+    }
+    const int q = n / X, r = n % X;
+    int i = 0;
+    for (int x = 0; x < X; ++x) {
+        const int lo = x * q + (x < r ? x : r);
+        const int cnt = q + (x < r ? 1 : 0);
+        const int nb = G / X + (x < G % X ? 1 : 0);
+        const int a = cnt / nb, b = cnt % nb;
+        for (int j = 0; j < nb; ++j) {
+            const int nj = a + (j < b ? 1 : 0);
+            for (int k = 0; k < nj; ++k)
+                pos[i++] = lo + j + k * nb;
+        }
+    }
+}
+
 namespace bfk {
 
 constexpr int kM = BF_M;
@@ -130,8 +190,10 @@ hipError_t launch_apply(const LaunchCfg &cfg, BfHeader *blk, int n_items, const 
                         hipStream_t st);
 
 // Writes the header and the n_items items of descriptor block blk from
-// n_recs request records (their item ranges tile 0 .. n_items - 1).
-hipError_t launch_expand(const BfReqRec *recs, int n_recs, BfHeader *blk, int n_items, hipStream_t st);
+// n_recs request records (their item ranges tile 0 .. n_items - 1).  With
+// deal_grid > 0, item i goes to position ws_deal(i, n_items, deal_grid).
+hipError_t launch_expand(const BfReqRec *recs, int n_recs, BfHeader *blk, int n_items, int deal_grid,
+                         hipStream_t st);
 
 // Workgroups of the apply kernel that fit on one CU at once.
 int apply_occupancy(int prec, int schedule, bool vec16, bool stage);

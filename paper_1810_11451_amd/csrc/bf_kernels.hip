@@ -1544,6 +1544,39 @@ __device__ __forceinline__ void dma_w16(float *__restrict__ dst, const float *__
     }
 }
 
+// The pool entry and the number of 4-flow steps of W that each of the two
+// LDS W buffers holds, for matrix-core waves that copy W themselves.
+struct W16Held {
+    int id0 = -1, id1 = -1;
+    int st0 = 0, st1 = 0;
+};
+
+// The W buffer that the product with descriptor dn reads, given that the
+// product before it reads buffer cur: cur again when that buffer holds the
+// same pool entry with at least the steps dn needs (consecutive products
+// of one W, as a W-sorted order gives them, copy it once); otherwise the
+// other buffer, into which dn's W copy is issued here.  Every matrix-core
+// wave takes the same decision (the descriptors are wave-uniform scalar
+// loads) and copies its own part of the buffer.
+__device__ __forceinline__ int w16_take(int cur, const BfItem &dn, W16Held &h, float *b0, float *b1,
+                                        const float *__restrict__ w16, int a_w_stride, int plan_steps, int cw,
+                                        int lane)
+{
+    const int need = max((dn.f + 3) >> 2, 1);
+    if (dn.w_id == (cur ? h.id1 : h.id0) && need <= (cur ? h.st1 : h.st0))
+        return cur;
+    const int o = cur ^ 1;
+    dma_w16(o ? b1 : b0, w16 + (size_t)dn.w_id * a_w_stride, plan_steps, dn.f, cw, lane);
+    if (o) {
+        h.id1 = dn.w_id;
+        h.st1 = need;
+    } else {
+        h.id0 = dn.w_id;
+        h.st0 = need;
+    }
+    return o;
+}
+
 // Waits for this wave's outstanding vector-memory loads (here only the W
 // copies) and nothing else: s_waitcnt vmcnt(0) with expcnt and lgkmcnt at
 // their maximum.
@@ -1561,20 +1594,27 @@ __device__ __forceinline__ void ws16_consumer(c_item *my, int stride, int n_my, 
     const float *w16 = apool + fp32_3m16_offset(pairs);
     floatx4 accA[2][kAcc16<k4>], accB[2][kAcc16<k4>];
     // With kDma the matrix-core waves copy each product's W themselves: W of
-    // product k + 1 into buffer (k + 1) & 1 while chain k runs (that buffer
-    // held W of product k - 1, which every matrix-core wave finished before
-    // the barrier that opened iteration k), complete before the barrier
-    // that closes iteration k.
+    // product k + 1, unless the buffer of product k already holds it, into
+    // the other buffer while chain k runs (that buffer was last read by an
+    // earlier chain, which every matrix-core wave finished before the
+    // barrier that opened iteration k), complete before the barrier that
+    // closes iteration k.  Without kDma the producers stage W of product k
+    // in buffer k & 1.
     BfItem d = item_at(my, 0, stride);
     int f = d.f;
+    W16Held held;
+    int wb = 0;      // W buffer of the chain that runs next (kDma)
+    int wn = 0;      // W buffer of the product after it (kDma)
     if constexpr (kDma) {
         dma_w16(L.a_buf.v[0], w16 + (size_t)d.w_id * a_w_stride, plan_steps, d.f, cw, lane);
+        held.id0 = d.w_id;
+        held.st0 = max((d.f + 3) >> 2, 1);
         dma_wait();
     }
     __syncthreads();
     if constexpr (kDma) {
         d = item_at(my, min(1, n_my - 1), stride);
-        dma_w16(L.a_buf.v[1], w16 + (size_t)d.w_id * a_w_stride, plan_steps, d.f, cw, lane);
+        wn = w16_take(wb, d, held, L.a_buf.v[0], L.a_buf.v[1], w16, a_w_stride, plan_steps, cw, lane);
     }
     chain_16_any<k4, false>(L.s_buf[0], L.a_buf.v[0], plan_steps, f, cw, lane, accA, accA, nullptr);
     int sb = 0;   // S buffer of product k: k % kSBufs
@@ -1583,6 +1623,7 @@ __device__ __forceinline__ void ws16_consumer(c_item *my, int stride, int n_my, 
     if constexpr (kDma)
         dma_wait();
     __syncthreads();
+    wb = wn;
     int k = 1;
     while (true) {
         if (k >= n_my) {
@@ -1594,16 +1635,17 @@ __device__ __forceinline__ void ws16_consumer(c_item *my, int stride, int n_my, 
         }
         if constexpr (kDma) {
             d = item_at(my, min(k + 1, n_my - 1), stride);
-            dma_w16(L.a_buf.v[(k + 1) & 1], w16 + (size_t)d.w_id * a_w_stride, plan_steps, d.f, cw, lane);
+            wn = w16_take(wb, d, held, L.a_buf.v[0], L.a_buf.v[1], w16, a_w_stride, plan_steps, cw, lane);
         }
         sb = sb + 1 == kSBufs ? 0 : sb + 1;
-        chain_16_any<k4, true>(L.s_buf[sb], L.a_buf.v[k & 1], plan_steps, f, cw, lane, accB, accA,
-                               L.r_buf[(k - 1) & 1]);
+        chain_16_any<k4, true>(L.s_buf[sb], L.a_buf.v[kDma ? wb : (k & 1)], plan_steps, f, cw, lane, accB,
+                               accA, L.r_buf[(k - 1) & 1]);
         __builtin_amdgcn_sched_barrier(0);
         f = item_at(my, min(k + 1, n_my - 1), stride).f;
         if constexpr (kDma)
             dma_wait();
         __syncthreads();
+        wb = wn;
         ++k;
         if (k >= n_my) {
 #pragma unroll
@@ -1614,16 +1656,17 @@ __device__ __forceinline__ void ws16_consumer(c_item *my, int stride, int n_my, 
         }
         if constexpr (kDma) {
             d = item_at(my, min(k + 1, n_my - 1), stride);
-            dma_w16(L.a_buf.v[(k + 1) & 1], w16 + (size_t)d.w_id * a_w_stride, plan_steps, d.f, cw, lane);
+            wn = w16_take(wb, d, held, L.a_buf.v[0], L.a_buf.v[1], w16, a_w_stride, plan_steps, cw, lane);
         }
         sb = sb + 1 == kSBufs ? 0 : sb + 1;
-        chain_16_any<k4, true>(L.s_buf[sb], L.a_buf.v[k & 1], plan_steps, f, cw, lane, accA, accB,
-                               L.r_buf[(k - 1) & 1]);
+        chain_16_any<k4, true>(L.s_buf[sb], L.a_buf.v[kDma ? wb : (k & 1)], plan_steps, f, cw, lane, accA,
+                               accB, L.r_buf[(k - 1) & 1]);
         __builtin_amdgcn_sched_barrier(0);
         f = item_at(my, min(k + 1, n_my - 1), stride).f;
         if constexpr (kDma)
             dma_wait();
         __syncthreads();
+        wb = wn;
         ++k;
     }
 }
@@ -2866,7 +2909,7 @@ hipError_t launch_apply(const LaunchCfg &cfg, BfHeader *blk, int n_items, const 
 // the header.  The counters start at zero for the apply kernel that
 // follows on the same stream.
 __global__ void __launch_bounds__(256) expand_requests_kernel(const BfReqRec *recs, int n_recs, BfHeader *blk,
-                                                              BfItem *items, int n_items)
+                                                              BfItem *items, int n_items, int deal_grid)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         blk->next = 0;
@@ -2886,17 +2929,19 @@ __global__ void __launch_bounds__(256) expand_requests_kernel(const BfReqRec *re
         d.f = q.f;
         d.pad0 = 0;
         d.pad1 = 0;
-        items[q.item0 + k] = d;
+        const int i = q.item0 + k;
+        items[deal_grid > 0 ? ws_deal(i, n_items, deal_grid) : i] = d;
     }
 }
 
-hipError_t launch_expand(const BfReqRec *recs, int n_recs, BfHeader *blk, int n_items, hipStream_t st)
+hipError_t launch_expand(const BfReqRec *recs, int n_recs, BfHeader *blk, int n_items, int deal_grid,
+                         hipStream_t st)
 {
     if (n_recs <= 0)
         return hipSuccess;
     const int grid = (n_recs + 3) / 4;   // four records (waves) per workgroup
     hipLaunchKernelGGL(expand_requests_kernel, dim3(grid), dim3(256), 0, st, recs, n_recs, blk,
-                       const_cast<BfItem *>(items_of(blk)), n_items);
+                       const_cast<BfItem *>(items_of(blk)), n_items, deal_grid);
     return hipGetLastError();
 }
 

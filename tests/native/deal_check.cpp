@@ -1,0 +1,81 @@
+// Exhaustive host check of ws_deal and ws_deal_table (bf_internal.h): for item counts and
+// grids of every size class, the map is a bijection of 0 .. n - 1, and
+// items that are consecutive within one workgroup's block land in
+// consecutive products of that workgroup, i.e. nb positions apart, where
+// the wave-specialised schedule's share (lo + j + k nb) puts them.
+#include <cstdio>
+#include <vector>
+
+#include "bf_internal.h"
+
+static int check(int n, int G)
+{
+    std::vector<int> hit((size_t)n, 0);
+    for (int i = 0; i < n; ++i) {
+        const int p = ws_deal(i, n, G);
+        if (p < 0 || p >= n) {
+            std::fprintf(stderr, "n=%d G=%d: item %d -> %d out of range\n", n, G, i, p);
+            return 1;
+        }
+        hit[(size_t)p]++;
+    }
+    for (int p = 0; p < n; ++p)
+        if (hit[(size_t)p] != 1) {
+            std::fprintf(stderr, "n=%d G=%d: position %d hit %d times\n", n, G, p, hit[(size_t)p]);
+            return 1;
+        }
+    // The host table agrees with the per-item map.
+    std::vector<int> tab((size_t)n + 1, -7);
+    ws_deal_table(tab.data(), n, G);
+    if (tab[(size_t)n] != -7) {
+        std::fprintf(stderr, "n=%d G=%d: ws_deal_table wrote past its end\n", n, G);
+        return 1;
+    }
+    for (int i = 0; i < n; ++i)
+        if (tab[(size_t)i] != ws_deal(i, n, G)) {
+            std::fprintf(stderr, "n=%d G=%d: ws_deal_table[%d] = %d, ws_deal %d\n", n, G, i, tab[(size_t)i],
+                         ws_deal(i, n, G));
+            return 1;
+        }
+    // The share of workgroup b (as the kernel computes it) must be a run of
+    // consecutive item indices.
+    const int X = G < 8 ? G : 8;
+    std::vector<int> inv((size_t)n);
+    for (int i = 0; i < n; ++i)
+        inv[(size_t)ws_deal(i, n, G)] = i;
+    for (int b = 0; b < G; ++b) {
+        const int x = b % X, j = b / X;
+        const int nb = G / X + (x < G % X ? 1 : 0);
+        const int q = n / X, r = n % X;
+        const int lo = x * q + (x < r ? x : r);
+        const int cnt = q + (x < r ? 1 : 0);
+        const int n_my = j < cnt ? (cnt - j + nb - 1) / nb : 0;
+        for (int k = 1; k < n_my; ++k) {
+            const int a = inv[(size_t)(lo + j + (k - 1) * nb)], c = inv[(size_t)(lo + j + k * nb)];
+            if (c != a + 1) {
+                std::fprintf(stderr, "n=%d G=%d: workgroup %d products %d, %d are items %d, %d\n", n, G, b,
+                             k - 1, k, a, c);
+                return 1;
+            }
+        }
+    }
+    return 0;
+}
+
+int main()
+{
+    const int grids[] = {1, 2, 3, 7, 8, 9, 15, 16, 17, 31, 64, 255, 256, 257, 512, 1000};
+    long cases = 0;
+    for (int G : grids)
+        for (int n = 0; n <= 3000; n += (n < 600 ? 1 : 37)) {
+            if (check(n, G))
+                return 1;
+            ++cases;
+        }
+    for (int n : {8192, 16384, 16383, 65536})
+        for (int G : {256, 255, 248})
+            if (check(n, G))
+                return 1;
+    std::fprintf(stderr, "ws_deal ok (%ld cases)\n", cases);
+    return 0;
+}
