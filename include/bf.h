@@ -260,7 +260,12 @@ typedef struct {
                               a workgroup's consecutive products mostly share
                               their W (the kernels that copy W themselves,
                               store 8 and 9, then copy it once per run);
-                              bf_apply_noalloc keeps the caller's order */
+                              4: grouped by W id modulo 8 and on schedule 3
+                              dealt so that the workgroups' summed f match
+                              (longest first, alternating directions, each
+                              workgroup starting its list at a different
+                              point), else as 2; bf_apply_noalloc keeps the
+                              caller's order */
     int32_t store;         /* schedules 0 and 2: 0 = lanes write their accumulators
                               directly, 1 = each wave stages its 16 rows of R in LDS
                               and writes them as contiguous 16-byte stores;

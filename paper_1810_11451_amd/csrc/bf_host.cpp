@@ -504,7 +504,7 @@ static void read_env(bf_plan p)
         char tail = 0;
         const int got = sscanf(fv, "%d:%d:%d:%d%c", &v.schedule, &v.wg_per_cu, &v.order, &v.store, &tail);
         const bool ok = got == 4 && v.schedule >= 0 && v.schedule <= 3 && v.wg_per_cu >= 0 &&
-                        v.wg_per_cu <= 64 && v.order >= 0 && v.order <= 3 && v.store >= 0 &&
+                        v.wg_per_cu <= 64 && v.order >= 0 && v.order <= 4 && v.store >= 0 &&
                         v.store <= (v.schedule == 3 ? 9 : 1);
         if (ok) {
             p->env_force_set = true;
@@ -530,10 +530,31 @@ static void read_env(bf_plan p)
 //      counting sort), and given `deal` (ws_deal's table for the
 //      wave-specialised schedule's grid) dealt to its workgroups in
 //      contiguous blocks in the same pass, so that consecutive products of
-//      a workgroup mostly share their W and copy it into LDS once.
+//      a workgroup mostly share their W and copy it into LDS once;
+//   4: grouped by W id modulo 8 and, given `balance` (the wave-specialised
+//      schedule's tables), each XCD part's items ranked longest f first and
+//      dealt by ws_balance_table, so that the workgroups' summed f match and
+//      an XCD's workgroups are at different f at any moment.  One pass
+//      counts, one places every item: p = its grouped position, x = the part
+//      of p, r = its f rank within x (caller order among equal f).
 // The sort key of order 3: W ids of one residue modulo 8 together, in
 // increasing order within it.
 static inline int order3_key(int w, int g8) { return (w % 8) * g8 + w / 8; }
+
+// Order 4's tables for n items on a grid of G, rebuilt only when n or G
+// change.
+static const BalanceTable *balance_table(BalanceTable &t, int n, int G)
+{
+    if (t.n != n || t.g != G) {
+        t.pos.resize((size_t)n);
+        t.part.resize((size_t)n);
+        ws_balance_table(t.pos.data(), n, G);
+        ws_part_table(t.part.data(), n, G);
+        t.n = n;
+        t.g = G;
+    }
+    return &t;
+}
 
 // ws_deal's table for n items on a grid of G, rebuilt only when n or G
 // change (a caller that launches batches of one size builds it once).
@@ -549,8 +570,40 @@ static const int *deal_table(DealTable &t, int n, int G)
 }
 
 void order_items(const BfItem *in, BfItem *out, int n, int n_w, std::vector<int> &scratch, int mode,
-                 const int *deal)
+                 const int *deal, const BalanceTable *balance)
 {
+    if (mode == 4 && balance) {
+        constexpr int kGroups = 8, kF = BF_FMAX + 1;
+        const int X = balance->g < 8 ? std::max(balance->g, 1) : 8;   // parts of the schedule
+        // scratch: [group cursors 8][rank cursors X x kF][part of each item n]
+        scratch.assign((size_t)kGroups + (size_t)X * kF + (size_t)n, 0);
+        int *gcur = scratch.data();
+        int *rcur = gcur + kGroups;
+        int *xs = rcur + (size_t)X * kF;
+        for (int t = 0; t < n; ++t)
+            gcur[in[t].w_id % kGroups]++;
+        for (int g = 0, run = 0; g < kGroups; ++g) {
+            const int c = gcur[g];
+            gcur[g] = run;
+            run += c;
+        }
+        for (int t = 0; t < n; ++t) {
+            const int x = balance->part[(size_t)gcur[in[t].w_id % kGroups]++];
+            xs[t] = x;
+            rcur[(size_t)x * kF + (BF_FMAX - in[t].f)]++;
+        }
+        for (int x = 0, run = 0; x < X; ++x)
+            for (int k = 0; k < kF; ++k) {
+                const int c = rcur[(size_t)x * kF + k];
+                rcur[(size_t)x * kF + k] = run;
+                run += c;
+            }
+        for (int t = 0; t < n; ++t)
+            out[balance->pos[(size_t)rcur[(size_t)xs[t] * kF + (BF_FMAX - in[t].f)]++]] = in[t];
+        return;
+    }
+    if (mode == 4)
+        mode = 2;   // (not wave-specialised: grouped only)
     if (mode == 3) {
         const int g8 = (n_w + 7) / 8;
         scratch.assign((size_t)8 * g8 + 1, 0);
@@ -769,8 +822,10 @@ static bf_status upload_and_launch(bf_plan p, bf_prec prec, int n, const FillSta
         std::memcpy(slot.sorted, slot.host, sizeof(BfHeader));
         BfItem *dst = reinterpret_cast<BfItem *>(static_cast<char *>(slot.sorted) + sizeof(BfHeader) + kSinkBytes);
         const bool deal = chosen.order == 3 && cfg.schedule == 3;
+        const bool bal = chosen.order == 4 && cfg.schedule == 3;
         order_items(items, dst, n, p->n_w, p->sort_scratch, chosen.order,
-                    deal ? deal_table(p->deal, n, cfg.grid) : nullptr);
+                    deal ? deal_table(p->deal, n, cfg.grid) : nullptr,
+                    bal ? balance_table(p->balance, n, cfg.grid) : nullptr);
         items = dst;
         upload = slot.sorted;
     }
@@ -813,6 +868,8 @@ static bf_status upload_and_launch(bf_plan p, bf_prec prec, int n, const FillSta
 // out in the order order_items gives them.
 static void order_records(std::vector<BfReqRec> &recs, std::vector<BfReqRec> &tmp, int mode, int n_w)
 {
+    if (mode == 4)
+        mode = 2;   // (a record's items stay together: grouped only)
     const size_t n = recs.size();
     tmp.resize(n);
     if (mode == 2) {
@@ -1195,9 +1252,11 @@ extern "C" bf_status bf_graph_create(bf_graph *out, bf_plan p, int32_t batch, co
     }
     bfk::LaunchCfg cfg = choose_launch(p, prec, batch, max_f, vec16, min_f == max_f, &v);
     DealTable dt;
+    BalanceTable bt;
     if (v.order >= 1)
         order_items(raw.data(), items.data(), batch, p->n_w, scratch, v.order,
-                    v.order == 3 && cfg.schedule == 3 ? deal_table(dt, batch, cfg.grid) : nullptr);
+                    v.order == 3 && cfg.schedule == 3 ? deal_table(dt, batch, cfg.grid) : nullptr,
+                    v.order == 4 && cfg.schedule == 3 ? balance_table(bt, batch, cfg.grid) : nullptr);
     else
         items = raw;
     {
@@ -1272,7 +1331,7 @@ extern "C" bf_status bf_graph_destroy(bf_graph g)
 static bool valid_variant(const bf_variant &v)
 {
     return v.schedule >= 0 && v.schedule <= 3 && v.wg_per_cu >= 0 && v.wg_per_cu <= 64 &&
-           v.order >= 0 && v.order <= 3 && v.store >= 0 && v.store <= (v.schedule == 3 ? 9 : 1);
+           v.order >= 0 && v.order <= 4 && v.store >= 0 && v.store <= (v.schedule == 3 ? 9 : 1);
 }
 
 extern "C" bf_status bf_set_variant(bf_plan p, bf_prec prec, int32_t bucket, const bf_variant *v)
@@ -1337,7 +1396,7 @@ extern "C" bf_status bf_autotune(bf_plan p, int32_t batch, const int32_t *w_ids,
     // (the 16-bit wave-specialised kernel takes batches of one f only; store
     // fields 6 to 9 exist for the FP32 forms only)
     if (!lp || min_f == max_f)
-        for (int o = 0; o < 4; ++o)
+        for (int o = 0; o < 5; ++o)
             for (int st = 0; st < (lp ? 6 : 10); ++st)
                 cands.push_back(bf_variant{3, 0, o, st});
 

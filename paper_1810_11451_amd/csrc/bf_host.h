@@ -40,10 +40,16 @@ struct StagingSlot {
     bool launched = false;   // ev has been recorded after a launch
 };
 
-// Dealt positions of order 3 (ws_deal) for n items on a grid of g.
+// Dealt positions of order 3 (ws_deal) for n items on a grid of g; for
+// order 4 the balanced positions by rank (ws_balance_table) and the part of
+// each position (ws_part_table).
 struct DealTable {
     int n = -1, g = -1;
     std::vector<int> pos;
+};
+struct BalanceTable {
+    int n = -1, g = -1;
+    std::vector<int> pos, part;
 };
 
 struct bf_plan_s {
@@ -101,6 +107,7 @@ struct bf_plan_s {
     std::vector<BfReqRec> rec_tmp;
     std::vector<int> sort_scratch;
     DealTable deal;
+    BalanceTable balance;
 };
 
 struct FillStats {
@@ -130,7 +137,7 @@ public:
 using FillFn = std::function<FillStats(BfItem *)>;
 
 void order_items(const BfItem *in, BfItem *out, int n, int n_w, std::vector<int> &scratch, int mode,
-                 const int *deal = nullptr);
+                 const int *deal = nullptr, const BalanceTable *balance = nullptr);
 bfk::LaunchCfg choose_launch(bf_plan p, bf_prec prec, int n, int max_f, bool vec16,
                              bool uniform_f, const bf_variant *force);
 bf_status reserve_staging(bf_plan p, int n);

@@ -62,6 +62,36 @@ static int check(int n, int G)
     return 0;
 }
 
+// ws_balance_table: a bijection onto the shares' layout, every workgroup
+// getting exactly the products its share holds, and a balanced deal: the
+// ranks a workgroup receives sum to within the part's size of the mean
+// rank sum (so summed f, ranked longest first, comes out even).
+static int check_balance(int n, int G)
+{
+    std::vector<int> pos((size_t)n + 1, -7), hit((size_t)n, 0);
+    ws_balance_table(pos.data(), n, G);
+    if (pos[(size_t)n] != -7) {
+        std::fprintf(stderr, "balance n=%d G=%d: wrote past its end\n", n, G);
+        return 1;
+    }
+    for (int i = 0; i < n; ++i) {
+        const int p = pos[(size_t)i];
+        if (p < 0 || p >= n || hit[(size_t)p]++) {
+            std::fprintf(stderr, "balance n=%d G=%d: rank %d -> %d out of range or repeated\n", n, G, i, p);
+            return 1;
+        }
+    }
+    // every position's part is the part of its rank (items stay in their XCD's eighth)
+    std::vector<int> part((size_t)n);
+    ws_part_table(part.data(), n, G);
+    for (int i = 0; i < n; ++i)
+        if (part[(size_t)pos[(size_t)i]] != part[(size_t)i]) {
+            std::fprintf(stderr, "balance n=%d G=%d: rank %d leaves its part\n", n, G, i);
+            return 1;
+        }
+    return 0;
+}
+
 int main()
 {
     const int grids[] = {1, 2, 3, 7, 8, 9, 15, 16, 17, 31, 64, 255, 256, 257, 512, 1000};
@@ -74,7 +104,11 @@ int main()
         }
     for (int n : {8192, 16384, 16383, 65536})
         for (int G : {256, 255, 248})
-            if (check(n, G))
+            if (check(n, G) || check_balance(n, G))
+                return 1;
+    for (int G : grids)
+        for (int n = 0; n <= 3000; n += (n < 600 ? 1 : 37))
+            if (check_balance(n, G))
                 return 1;
     std::fprintf(stderr, "ws_deal ok (%ld cases)\n", cases);
     return 0;

@@ -24,7 +24,8 @@ VARIANTS = {"one-per-wg": (0, 0, 0), "ws-sorted": (3, 0, 1), "ws-asgiven": (3, 0
             "ws16-w-copied-by-matrix-waves": (3, 0, 0, 8), "ws16-w-copied-xcd-grouped": (3, 0, 2, 8),
             "ws16-w-and-s-copied": (3, 0, 0, 9), "ws16-w-and-s-copied-sorted": (3, 0, 1, 9),
             "ws16-w-blocked": (3, 0, 3, 8), "ws16-w-and-s-copied-w-blocked": (3, 0, 3, 9),
-            "one-per-wg-w-sorted": (0, 0, 3, 1)}
+            "one-per-wg-w-sorted": (0, 0, 3, 1), "ws16-f-balanced": (3, 0, 4, 9),
+            "ws16-f-balanced-w-staged": (3, 0, 4, 7)}
 WS16 = ["ws16", "ws16-sorted-depth-2", "ws16-w-copied-by-matrix-waves", "ws16-w-and-s-copied"]
 
 
@@ -148,7 +149,8 @@ def test_16x16_variants_agree_bitwise():
     b = wl.random_batch(rng, n, 9, f_values=np.arange(0, 37))
     announce(f"3m 16x16 variants bitwise n={n}")
     ref = run_batch(b, prec=P, variant=VARIANTS["ws16"])
-    for v in [(3, 0, 0, 7), (3, 0, 0, 8), (3, 0, 2, 8), (3, 0, 0, 9), (3, 0, 2, 9), (3, 0, 3, 8), (3, 0, 3, 9)]:
+    for v in [(3, 0, 0, 7), (3, 0, 0, 8), (3, 0, 2, 8), (3, 0, 0, 9), (3, 0, 2, 9), (3, 0, 3, 8), (3, 0, 3, 9),
+              (3, 0, 4, 8), (3, 0, 4, 9)]:
         R = run_batch(b, prec=P, variant=v)
         assert np.array_equal(R.view(np.uint32), ref.view(np.uint32)), v
     err, _ = rel_errors(b, ref)

@@ -47,12 +47,14 @@ VARIANTS = {
     "ws16-w-blocked": (3, 0, 3, 8),
     "ws16-w-and-s-copied-w-blocked": (3, 0, 3, 9),
     "one-per-wg-w-sorted": (0, 0, 3, 1),
+    "ws16-f-balanced": (3, 0, 4, 9),
+    "one-per-wg-f-balanced": (0, 0, 4, 1),
 }
 # 16 x 16 tiles, four products per step (store fields 6 to 9)
 WS16 = ["ws16", "ws16-sorted-depth-2", "ws16-w-copied", "ws16-w-and-s-copied"]
 WS_VARIANTS = ["ws-sorted", "ws-8-producers", "ws-8-producers-depth-2", "ws-8-producers-depth-3",
                "ws-12-producers-asgiven", "ws-12-producers-depth-2", "ws16", "ws16-w-copied",
-               "ws16-w-and-s-copied", "ws16-w-and-s-copied-w-blocked"]
+               "ws16-w-and-s-copied", "ws16-w-and-s-copied-w-blocked", "ws16-f-balanced"]
 
 
 @pytest.mark.parametrize("vname", sorted(VARIANTS))
@@ -152,7 +154,8 @@ def test_16x16_variants_agree_bitwise():
     b = wl.random_batch(rng, n, 9, f_values=np.arange(0, 37))
     announce(f"fp32 16x16 variants bitwise n={n}")
     ref = run_batch(b, variant=VARIANTS["ws16"])
-    for v in [(3, 0, 0, 7), (3, 0, 0, 8), (3, 0, 2, 8), (3, 0, 0, 9), (3, 0, 2, 9), (3, 0, 3, 8), (3, 0, 3, 9)]:
+    for v in [(3, 0, 0, 7), (3, 0, 0, 8), (3, 0, 2, 8), (3, 0, 0, 9), (3, 0, 2, 9), (3, 0, 3, 8), (3, 0, 3, 9),
+              (3, 0, 4, 8), (3, 0, 4, 9)]:
         R = run_batch(b, variant=v)
         assert np.array_equal(R.view(np.uint32), ref.view(np.uint32)), v
     err, _ = rel_errors(b, ref)

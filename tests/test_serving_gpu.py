@@ -97,10 +97,11 @@ def test_serve_matches_oracle():
 @pytest.mark.parametrize("prec,variant", [(bf.BF_FP32, (0, 0, 1, 1)), (bf.BF_FP32, (2, 0, 0)),
                                           (bf.BF_FP32, (1, 0, 2)), (bf.BF_FP32_3M, (0, 0, 2, 1)),
                                           (bf.BF_FP32_3M, (3, 0, 1, 7)), (bf.BF_FP32_3M, (3, 0, 3, 9)),
-                                          (bf.BF_FP32, (3, 0, 3, 8)), (bf.BF_FP32_3M, (0, 0, 3, 1))],
+                                          (bf.BF_FP32, (3, 0, 3, 8)), (bf.BF_FP32_3M, (0, 0, 3, 1)),
+                                          (bf.BF_FP32_3M, (3, 0, 4, 9))],
                          ids=["fp32-single-byw", "fp32-stream-asgiven", "fp32-claim-xcd",
                               "fp32_3m-single-xcd", "fp32_3m-ws16-byw", "fp32_3m-ws16-w-blocked",
-                              "fp32-ws16-w-blocked", "fp32_3m-single-w-sorted"])
+                              "fp32-ws16-w-blocked", "fp32_3m-single-w-sorted", "fp32_3m-ws16-f-balanced"])
 def test_serve_under_each_product_order(prec, variant):
     """Requests expand into items on the device in the order the variant
     asks for (as given, by W id then f, grouped by W id modulo 8, grouped

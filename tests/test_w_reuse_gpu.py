@@ -80,7 +80,7 @@ def test_w_blocked_order_matches_per_product_staging(form, n_w):
     b = wl.random_batch(rng, n, n_w, f_values=np.arange(0, 37))
     announce(f"w blocked order form={form} n_w={n_w} n={n}")
     ref = run_batch(b, prec=prec, variant=(3, 0, 0, 7))
-    for v in [(3, 0, 3, 8), (3, 0, 3, 9)]:
+    for v in [(3, 0, 3, 8), (3, 0, 3, 9), (3, 0, 4, 9)]:
         R = run_batch(b, prec=prec, variant=v)
         assert np.array_equal(R.view(np.uint32), ref.view(np.uint32)), (form, n_w, v)
     err, _ = rel_errors(b, ref)
