@@ -84,86 +84,6 @@ __host__ __device__ inline int ws_deal(int i, int n, int G)
     return lo + j + k * nb;
 }
 
-// ws_deal as a table on the host: pos[i] = ws_deal(i, n, G) for every i,
-// walking the parts and workgroup blocks with running offsets instead of
-// ws_deal's divisions per item.
-inline void ws_deal_table(int *pos, int n, int G)
-{
-    const int X = G < 8 ? G : 8;
-    if (X <= 0) {
-        for (int i = 0; i < n; ++i)
-            pos[i] = i;
-        return;
-    }
-    const int q = n / X, r = n % X;
-    int i = 0;
-    for (int x = 0; x < X; ++x) {
-        const int lo = x * q + (x < r ? x : r);
-        const int cnt = q + (x < r ? 1 : 0);
-        const int nb = G / X + (x < G % X ? 1 : 0);
-        const int a = cnt / nb, b = cnt % nb;
-        for (int j = 0; j < nb; ++j) {
-            const int nj = a + (j < b ? 1 : 0);
-            for (int k = 0; k < nj; ++k)
-                pos[i++] = lo + j + k * nb;
-        }
-    }
-}
-
-// Balanced dealing (product order 4) as a table on the host: for the
-// items of each of the wave-specialised schedule's parts (one per XCD,
-// positions lo .. lo + cnt - 1, nb workgroups), ranked r = 0 .. cnt - 1
-// longest f first, pos[lo + r] is the position rank r goes to.  Ranks are
-// dealt in rounds of nb, alternately forwards and backwards over the
-// workgroups (so each workgroup's summed f comes out close to the mean; a
-// short last round goes to the workgroups that take one product more),
-// and each workgroup j takes its round-ordered products starting at round
-// (j n_j) / nb, so that at any moment the workgroups of an XCD are at
-// different f.  The layout of each workgroup's share is ws_share's (lo + j
-// + k nb).  Depends only on n and G.
-inline void ws_balance_table(int *pos, int n, int G)
-{
-    const int X = G < 8 ? G : 8;
-    if (X <= 0) {
-        for (int i = 0; i < n; ++i)
-            pos[i] = i;
-        return;
-    }
-    const int q = n / X, r = n % X;
-    for (int x = 0; x < X; ++x) {
-        const int lo = x * q + (x < r ? x : r);
-        const int cnt = q + (x < r ? 1 : 0);
-        const int nb = G / X + (x < G % X ? 1 : 0);
-        const int a = cnt / nb, b = cnt % nb;
-        for (int s = 0; s < cnt; ++s) {
-            const int rnd = s / nb, u = s % nb;
-            const int j = rnd < a ? ((rnd & 1) ? nb - 1 - u : u) : u;
-            const int nj = a + (j < b ? 1 : 0);
-            const int k = (rnd + (int)((long)j * nj / nb)) % nj;
-            pos[lo + s] = lo + j + k * nb;
-        }
-    }
-}
-
-// Part (XCD share) of each position of the wave-specialised schedule's item
-// list: part[p] = x for lo_x <= p < lo_x + cnt_x.
-inline void ws_part_table(int *part, int n, int G)
-{
-    const int X = G < 8 ? G : 8;
-    if (X <= 0) {
-        for (int i = 0; i < n; ++i)
-            part[i] = 0;
-        return;
-    }
-    const int q = n / X, r = n % X;
-    int p = 0;
-    for (int x = 0; x < X; ++x) {
-        const int cnt = q + (x < r ? 1 : 0);
-        for (int c = 0; c < cnt; ++c)
-            part[p++] = x;
-    }
-}
-
 namespace bfk {
 
 constexpr int kM = BF_M;

@@ -1,4 +1,5 @@
-// Exhaustive host check of ws_deal and ws_deal_table (bf_internal.h): for item counts and
+// Exhaustive host check of ws_deal (bf_internal.h) and the host tables of
+// bf_host.h (ws_deal_table, ws_balance_table): for item counts and
 // grids of every size class, the map is a bijection of 0 .. n - 1, and
 // items that are consecutive within one workgroup's block land in
 // consecutive products of that workgroup, i.e. nb positions apart, where
@@ -6,7 +7,7 @@
 #include <cstdio>
 #include <vector>
 
-#include "bf_internal.h"
+#include "bf_host.h"
 
 static int check(int n, int G)
 {
