@@ -628,15 +628,27 @@ void order_items(const BfItem *in, BfItem *out, int n, int n_w, std::vector<int>
             out[cnt[in[t].w_id % kGroups]++] = in[t];
         return;
     }
-    std::vector<BfItem> tmp(in, in + n);
-    scratch.assign((size_t)std::max(n_w, BF_FMAX + 1) + 1, 0);
-    for (int t = 0; t < n; ++t)
-        scratch[(size_t)tmp[t].w_id + 1]++;
+    // Mode 1: stable counting sort by W id, then by f descending.  With one
+    // f in the batch the second pass is the identity, so the first writes
+    // straight to out.  (in and out never overlap; the intermediate buffer
+    // is kept across calls, so a hot loop does not allocate.)
+    scratch.assign((size_t)n_w + 1, 0);
+    bool one_f = true;
+    for (int t = 0; t < n; ++t) {
+        scratch[(size_t)in[t].w_id + 1]++;
+        one_f = one_f && in[t].f == in[0].f;
+    }
     for (int k = 0; k < n_w; ++k)
         scratch[(size_t)k + 1] += scratch[(size_t)k];
-    std::vector<BfItem> by_w((size_t)n);
+    if (one_f) {
+        for (int t = 0; t < n; ++t)
+            out[scratch[(size_t)in[t].w_id]++] = in[t];
+        return;
+    }
+    static thread_local std::vector<BfItem> by_w;
+    by_w.resize((size_t)n);
     for (int t = 0; t < n; ++t)
-        by_w[(size_t)scratch[(size_t)tmp[t].w_id]++] = tmp[t];
+        by_w[(size_t)scratch[(size_t)in[t].w_id]++] = in[t];
     int cnt[BF_FMAX + 2] = {0};
     for (int t = 0; t < n; ++t)
         cnt[BF_FMAX - by_w[(size_t)t].f + 1]++;

@@ -1,7 +1,9 @@
-// Host check of the product orders 3 and 4 of the library (order_items,
+// Host check of the product orders 1 to 4 of the library (order_items,
 // linked from libbf.so) on uneven batches (f ~ U{0..36}, W ids from a
 // pool), for the wave-specialised schedule's grid of one workgroup per CU:
-//   * both orders are a permutation of the items;
+//   * every order is a permutation of the items; orders 1 and 2 sort as
+//     documented (f descending then W id; W id modulo 8), stably, also for
+//     batches of one f;
 //   * order 3: with 8 or more items per W and per workgroup, the products of
 //     one workgroup come in runs of one W (3 in 4 consecutive pairs share it);
 //   * order 4: within each part, no workgroup's summed (f + 32) exceeds the
@@ -14,14 +16,14 @@
 
 #include "bf_host.h"
 
-static int run(int n, int n_w, int G, unsigned seed)
+static int run(int n, int n_w, int G, unsigned seed, bool one_f)
 {
     std::mt19937 rng(seed);
     std::vector<BfItem> in((size_t)n), out((size_t)n);
     for (int t = 0; t < n; ++t) {
         in[(size_t)t] = BfItem{};
         in[(size_t)t].w_id = (int)(rng() % (unsigned)n_w);
-        in[(size_t)t].f = (int)(rng() % 37u);
+        in[(size_t)t].f = one_f ? 36 : (int)(rng() % 37u);
         in[(size_t)t].pad0 = t;   // item identity
     }
     std::vector<int> scratch;
@@ -35,7 +37,7 @@ static int run(int n, int n_w, int G, unsigned seed)
     std::vector<int> deal((size_t)n);
     ws_deal_table(deal.data(), n, G);
     const int X = G < 8 ? G : 8;
-    for (int mode : {3, 4}) {
+    for (int mode : {1, 2, 3, 4}) {
         std::fill(out.begin(), out.end(), BfItem{});
         for (BfItem &o : out)
             o.pad0 = -1;
@@ -49,6 +51,26 @@ static int run(int n, int n_w, int G, unsigned seed)
                 return 1;
             }
         }
+        if (mode == 1)
+            for (int p = 1; p < n; ++p) {
+                const BfItem &u = out[(size_t)p - 1], &v = out[(size_t)p];
+                // f descending, then W id ascending, then the caller's order
+                const bool ok = u.f > v.f || (u.f == v.f && (u.w_id < v.w_id ||
+                                                            (u.w_id == v.w_id && u.pad0 < v.pad0)));
+                if (!ok) {
+                    std::fprintf(stderr, "mode 1 n=%d: positions %d, %d out of order\n", n, p - 1, p);
+                    return 1;
+                }
+            }
+        if (mode == 2)
+            for (int p = 1; p < n; ++p) {
+                const BfItem &u = out[(size_t)p - 1], &v = out[(size_t)p];
+                const bool ok = u.w_id % 8 < v.w_id % 8 || (u.w_id % 8 == v.w_id % 8 && u.pad0 < v.pad0);
+                if (!ok) {
+                    std::fprintf(stderr, "mode 2 n=%d: positions %d, %d out of order\n", n, p - 1, p);
+                    return 1;
+                }
+            }
         if (mode == 4) {
             // within each part, no workgroup's summed (f + 32) exceeds the
             // part's mean by more than 4% plus one product (those taking one
@@ -105,7 +127,8 @@ int main()
     for (int G : {1, 7, 8, 9, 64, 255, 256})
         for (int n : {0, 1, 5, 63, 64, 65, 1000, 4099, 8192, 16384})
             for (int n_w : {1, 3, 64, 256})
-                if (run(n, n_w, G, (unsigned)(n * 31 + G * 7 + n_w))) {
+                if (run(n, n_w, G, (unsigned)(n * 31 + G * 7 + n_w), false) ||
+                    run(n, n_w, G, (unsigned)(n * 17 + G + n_w), true)) {
                     return 1;
                 } else {
                     ++cases;

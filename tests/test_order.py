@@ -1,8 +1,9 @@
-"""Host check of the library's product orders 3 and 4 (order_items in
+"""Host check of the library's product orders 1 to 4 (order_items in
 libbf.so, called from tests/native/order_check.cpp built with hipcc for the
-host): both are permutations; order 3 gives each wave-specialised
-workgroup runs of one W; order 4 keeps every item in its XCD part and
-balances the workgroups' summed f."""
+host): all are permutations; orders 1 and 2 sort as documented, stably, on
+batches of mixed and of one f; order 3 gives each wave-specialised
+workgroup runs of one W; order 4 balances the workgroups' summed f within
+each XCD part."""
 import shutil
 import subprocess
 from pathlib import Path
@@ -14,7 +15,7 @@ from paper_1810_11451_amd import bf
 ROOT = Path(__file__).resolve().parents[1]
 
 
-def test_orders_3_and_4_on_uneven_batches(tmp_path):
+def test_product_orders(tmp_path):
     hipcc = "/opt/rocm/bin/hipcc" if Path("/opt/rocm/bin/hipcc").exists() else shutil.which("hipcc")
     if hipcc is None:
         pytest.skip("no hipcc")
